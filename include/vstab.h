@@ -1,0 +1,241 @@
+/*
+ * vstab.h -- C ABI of the MI355X (gfx950) video-stabilization hot path of
+ * Lim et al., "Real-Time Optical flow-based Video Stabilization for Unmanned Aerial Vehicles"
+ * (arXiv 1701.03572).
+ *
+ * The six operations follow the paper's three-stage pipeline (Section 2, framework figure):
+ * motion estimation (pyramids, corners, optical-flow tracking, robust model fit; Sections 3-4),
+ * motion compensation (trajectory smoothing; Section 5.1) and image composition (warp; Section 5).
+ *
+ * Conventions shared by every call
+ *  - Pointers named *frames, *pyrs, xy*, score, alive, status, fb_err, n_valid, params, info,
+ *    inliers, mats, state and workspace are DEVICE pointers owned by the caller. Structs passed
+ *    as `const vs_*_params*` and `vs_pyramid*` are HOST pointers read during the call only.
+ *  - `stream` is a hipStream_t (NULL: the null stream). Every call only enqueues work on it:
+ *    no allocation, no free, no host synchronisation. Data-dependent outcomes (corner counts,
+ *    skip flags, model choices, emitted frames) are written to device memory, never returned.
+ *  - Images are 8-bit grayscale, row-major, `pitch` bytes per row (pitch >= width).
+ *    Coordinates: x = column, y = row, pixel centres at integers; points are interleaved float
+ *    pairs (x, y).
+ *  - Batches: every call takes a count `n` of independent items and byte (or element) strides
+ *    between them, so one launch can serve one frame, a run of frames or many streams.
+ *  - Return codes: VS_OK (0), VS_ERR_INVALID (-1: null pointer, bad size, count or stride),
+ *    VS_ERR_UNSUPPORTED (-2: levels > VS_MAX_LEVELS, window > 31x31, capacity > VS_MAX_CORNERS),
+ *    VS_ERR_WORKSPACE (-3: workspace too small), VS_ERR_HIP (-4: launch failure; the message is
+ *    available from vs_last_error()). On an error no work has been enqueued.
+ */
+#ifndef VSTAB_H
+#define VSTAB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VS_MAX_LEVELS 8
+#define VS_MAX_CORNERS 4096
+#define VS_TRAJ_RING 256
+
+enum { VS_OK = 0, VS_ERR_INVALID = -1, VS_ERR_UNSUPPORTED = -2, VS_ERR_WORKSPACE = -3, VS_ERR_HIP = -4 };
+enum { VS_RIGID = 0, VS_SIMILARITY = 1, VS_HYBRID = 2 };
+enum { VS_SMOOTH_CENTERED = 0, VS_SMOOTH_CAUSAL = 1, VS_SMOOTH_KALMAN = 2 };
+
+/* ---------------------------------------------------------------------------------------------
+ * Pyramid layout (Section 3.2: image pyramids turn large motion into small motion).
+ * Level 0 is the caller's frame itself (never copied). Levels 1..levels-1 live in one pyramid
+ * buffer of `bytes` bytes: level l has size width[l] x height[l] with width[l+1] =
+ * (width[l] + 1) / 2 (same for height), row pitch pitch[l] (a multiple of 64) and starts at
+ * byte offset[l] (a multiple of 256). pitch[0] is the frame pitch, offset[0] = 0 (unused).
+ * ------------------------------------------------------------------------------------------- */
+typedef struct {
+    int32_t levels;
+    int32_t width[VS_MAX_LEVELS];
+    int32_t height[VS_MAX_LEVELS];
+    int32_t pitch[VS_MAX_LEVELS];
+    int64_t offset[VS_MAX_LEVELS];
+    int64_t bytes;
+} vs_pyramid;
+
+/* Host only. Fills *out for a width x height frame of row pitch `pitch0`. Every level must keep
+ * width and height >= 16, else VS_ERR_INVALID. */
+int vs_pyramid_layout(int32_t width, int32_t height, int32_t pitch0, int32_t levels, vs_pyramid* out);
+
+/* build_pyramid -- Section 3.2 (pyramids of Adelson et al. / Bouguet).
+ * Level l+1 = even samples of level l correlated with the binomial kernel [1 4 6 4 1]^T [1 4 6 4 1]
+ * / 256 (one integer sum, round half up), borders reflected without repeating the edge pixel.
+ * Item i reads frames + i * frame_stride (pitch layout->pitch[0]) and writes levels 1.. into
+ * pyrs + i * pyr_stride. Bit-exact. */
+int vs_build_pyramid(const uint8_t* frames, int64_t frame_stride, uint8_t* pyrs, int64_t pyr_stride, int32_t n,
+                     const vs_pyramid* layout, void* stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * detect_corners -- Section 3.1, Eq. 2 (Shi-Tomasi score R = min(lambda1, lambda2) of the
+ * windowed gradient tensor), the corner budget and the reduced region of interest.
+ * Gradients are Sobel, the window is 3x3, the score is evaluated in binary64 as
+ * 2 det / (tr + sqrt(disc)) from exact integer det, tr, disc. Candidates are the pixels of the ROI
+ * [roi_mx, W - roi_mx) x [roi_my, H - roi_my) whose score is > 0, >= quality * (max score in the ROI)
+ * and >= the score of each of their 8 neighbours inside the ROI. In the order (score desc, y asc,
+ * x asc) a candidate is accepted iff its squared distance to every accepted corner is >= min_dist^2;
+ * selection stops after max_corners acceptances.
+ * Item i reads frames + i * frame_stride. Its per-item records sit at record index g = i * istride
+ * (istride >= 1 lets a call address every 5th record of a pair-major array); each record has
+ * `capacity` point slots:
+ *   xy[g * capacity + k][2] (float, integer-valued), score[g * capacity + k] (double, may be NULL),
+ *   count[g] (int32), alive[g * capacity + k] (uint8: 1 for the accepted slots, 0 for the rest).
+ * Gating: when gate != NULL, item i runs only if gate[g] < gate_min; otherwise its outputs are
+ * left untouched (this implements the re-detection after a skipped pair on the device).
+ * max_corners <= capacity <= VS_MAX_CORNERS, roi margins >= 2.
+ * workspace: at least vs_detect_workspace(width, height, n) bytes. */
+typedef struct {
+    int32_t max_corners;
+    double quality;
+    int32_t min_dist;
+    int32_t roi_mx, roi_my;
+} vs_detect_params;
+
+size_t vs_detect_workspace(int32_t width, int32_t height, int32_t n);
+int vs_detect_corners(const uint8_t* frames, int64_t frame_stride, int32_t width, int32_t height, int32_t pitch,
+                      int32_t n, int32_t istride, const int32_t* gate, int32_t gate_min, const vs_detect_params* p,
+                      int32_t capacity,
+                      float* xy, double* score, int32_t* count, uint8_t* alive, void* workspace, size_t ws_bytes,
+                      void* stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * track_lk -- Section 3.2, Eqs. 3-6 (brightness constancy linearised to fx u + fy v + ft = 0,
+ * solved over a window by Lucas-Kanade, coarse to fine over the pyramid; tracked points become
+ * the previous points of the next step) and the backward consistency check of Section 4.1.
+ * For every alive slot u: at each level l from the top, c = u / 2^l, samples of the edge-
+ * replicated image are bilinear, gradients are half central differences; G = sum grad I grad I^T
+ * over the (2 win_half + 1)^2 window; if lambda_min(G) / window_size < min_eig the level gives no
+ * update (at level 0 the point is lost); otherwise nu += G^-1 sum (I - J) grad I until |eta| < eps
+ * or max_iter; the guess passed down is 2 (g + nu). v = u + g + nu must lie in the image. With fb,
+ * the same track from v back to the previous frame must return within fb_thresh of u.
+ * FP32 arithmetic.
+ * Item i uses the frame pair (prev_frames + i * frame_stride, next_frames + i * frame_stride),
+ * their pyramids (prev_pyrs/next_pyrs + i * pyr_stride), and the record g = i * istride of every
+ * per-item array: point slots xy_prev[g * capacity + k][2] with alive_prev[g * capacity + k].
+ * Outputs: xy_next[g * capacity + k][2], status[g * capacity + k] (1 = tracked and consistent),
+ * fb_err[g * capacity + k] (may be NULL; NaN where not computed), n_valid[g] (may be NULL: number
+ * of status-1 slots), and optional chained copies xy_chain / alive_chain (may be NULL) receiving the
+ * same values as xy_next / status (the next step's input, which a later re-detection may
+ * overwrite without touching this step's outputs). xy_chain may alias xy_prev (same for alive).
+ * work (may be NULL): two counters set by the call to the number of window set-ups (point x
+ * level x direction) and of Gauss-Newton iterations it performed, for throughput accounting. */
+typedef struct {
+    int32_t win_half;
+    int32_t max_iter;
+    float eps;
+    float min_eig;
+    int32_t fb;
+    float fb_thresh;
+} vs_lk_params;
+
+int vs_track_lk(const uint8_t* prev_frames, const uint8_t* prev_pyrs, const uint8_t* next_frames,
+                const uint8_t* next_pyrs, int64_t frame_stride, int64_t pyr_stride, int32_t n, int32_t istride,
+                const vs_pyramid* layout, const float* xy_prev, const uint8_t* alive_prev, int32_t capacity,
+                const vs_lk_params* p, float* xy_next, uint8_t* status, float* fb_err, int32_t* n_valid,
+                float* xy_chain, uint8_t* alive_chain, uint64_t* work, void* stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * fit_similarity -- Section 4, Eq. 7 (least-squares transform from src to dst points), the
+ * similarity (4 DOF) and rigid (3 DOF, unit scale) models, the hybrid mechanism of Section 4.1
+ * (compare the RMS residuals E_r and E_s, keep the choice for a dwell of `dwell` pairs) and the
+ * skip rule (too few points: no stabilization for that pair).
+ * Item i is pair index pair_index0 + i of one stream. Its valid points are the slots with
+ * valid[i][k] = 1, in slot order, in centred coordinates (x - cx, y - cy). With n_valid < min_valid
+ * the pair is the identity and skipped. Otherwise each model is fitted by a seeded 2-point RANSAC
+ * (ransac_iters hypotheses drawn by SplitMix64 from (seed, stream_id, pair index, hypothesis),
+ * scored by the count of residuals <= inlier_thresh, first best wins) followed by a binary64
+ * least-squares refit on the best inlier set (ransac_iters = 0: least squares on all points).
+ * HYBRID: the first non-skipped pair of each dwell block fits both models and picks rigid iff
+ * E_r < E_s (RMS over all valid points); later pairs of the block use that model. *state (device,
+ * one per stream) carries the block decision across calls; initialise it with
+ * vs_fit_state_init. Pairs of one call must be consecutive and in order.
+ * Outputs: params[i][4] = (a, b, tx, ty) with x' = a x - b y + tx, y' = b x + a y + ty (centred),
+ * info[i], inliers[i][capacity] (may be NULL).
+ * workspace: at least vs_fit_workspace(n, capacity) bytes. */
+typedef struct {
+    int32_t model;
+    int32_t ransac_iters;
+    double inlier_thresh;
+    uint64_t seed;
+    int64_t stream_id;
+    int32_t min_valid;
+    int32_t dwell;
+    double cx, cy;
+} vs_fit_params;
+
+typedef struct {
+    int64_t block;
+    int32_t model;
+    int32_t decided;
+} vs_fit_state;
+
+typedef struct {
+    int32_t model;
+    int32_t n_valid;
+    int32_t n_inliers;
+    int32_t skipped;
+    int32_t decided_here;
+    int32_t pad;
+    double err_rigid;
+    double err_sim;
+} vs_fit_info;
+
+size_t vs_fit_workspace(int32_t n, int32_t capacity);
+int vs_fit_state_init(vs_fit_state* state, void* stream);
+int vs_fit_similarity(const float* src, const float* dst, const uint8_t* valid, int32_t capacity, int32_t n,
+                      const vs_fit_params* p, int64_t pair_index0, vs_fit_state* state, double* params,
+                      vs_fit_info* info, uint8_t* inliers, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * smooth_trajectory -- Section 5.1 (accumulate the per-pair parameters into a trajectory, smooth
+ * it with an averaging window of twice the smoothing radius, correct each frame by smoothed minus
+ * accumulated) and the sliding parameter store of the real-time version (Section 6).
+ * Per pair: (tx, ty, angle = atan2(b, a), log-scale = ln |a + ib|); P_0 = 0, P_j = P_{j-1} + pair_{j-1}.
+ * CENTERED: Q_j = mean of P_i, i in [j - r, j + r] clipped to the known sequence; frame j is
+ * emitted once P_{j+r} is known or at end of stream, so a stream fed pair by pair emits exactly
+ * what one call over the whole sequence emits. CAUSAL: mean over [j - 2r, j]. KALMAN: per
+ * parameter random-walk filter, measurement noise 1, process noise kalman_ratio, started at P_0.
+ * Correction D_j = Q_j - P_j becomes the matrix mats[k] = Z o T(D_j) (2x3, row-major, maps frame
+ * pixel coordinates to output pixel coordinates), T a similarity about (cx, cy), Z a zoom by
+ * 1 / (1 - 2 crop) about (cx, cy).
+ * pair_params: n_new new pairs [n_new][4] (device). state: one per stream, vs_traj_state_bytes()
+ * bytes, initialised by vs_traj_state_init (radius <= 127). Emitted frames go to mats[0..],
+ * at most mats_capacity of them; *n_emitted and *first_frame (device) receive the count and the
+ * index of the first emitted frame. */
+typedef struct {
+    int32_t mode;
+    int32_t radius;
+    double kalman_ratio;
+    double crop;
+    double cx, cy;
+} vs_smooth_params;
+
+size_t vs_traj_state_bytes(void);
+int vs_traj_state_init(void* state, void* stream);
+int vs_smooth_trajectory(const double* pair_params, int32_t n_new, int32_t end_of_stream, const vs_smooth_params* p,
+                         void* state, double* mats, int32_t mats_capacity, int32_t* n_emitted, int64_t* first_frame,
+                         void* stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * warp_frame -- Section 5 (warp each frame by its corrected transform; cropping is folded into
+ * the matrix). Output pixel x takes the bilinear sample of the source at M^-1 x (FP32 coordinates,
+ * M inverted in binary64), source samples outside the image take `border`, rounded half up and
+ * clamped to [0, 255]. Item i: src + i * src_stride (pitch src_pitch), M = mats + i * mat_stride
+ * doubles (6 per matrix), dst + i * dst_stride (pitch dst_pitch); output size = input size. */
+int vs_warp_frame(const uint8_t* src, int64_t src_stride, int32_t width, int32_t height, int32_t src_pitch,
+                  const double* mats, int64_t mat_stride, uint8_t* dst, int64_t dst_stride, int32_t dst_pitch,
+                  int32_t n, int32_t border, void* stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * misc */
+const char* vs_last_error(void);   /* thread-local message of the last failing call */
+int vs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VSTAB_H */

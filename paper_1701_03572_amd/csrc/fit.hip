@@ -1,0 +1,480 @@
+// fit_similarity: seeded robust rigid / similarity fit, hybrid dwell switch and skip rule.
+//
+// Kernel 1 (fit_pair): one 256-thread workgroup per pair. The valid slots are compacted in slot
+// order into LDS (raw FP32 coordinates, centred exactly in binary64 when read), then each
+// requested model is fitted:
+// the 4 waves share the RANSAC hypotheses (wave w takes h = w, w + 4, ...), score them by
+// counting residuals <= threshold with a wave reduction, and the best (most inliers, then
+// smallest h) is refitted by least squares in binary64: the similarity through its 4x4 normal
+// equations (Gaussian elimination with partial pivoting), the rigid model through the centred
+// closed form atan2. Fixed-order reductions keep the result independent of scheduling.
+// The 2-point hypotheses and residuals use exactly the operation order
+//     px = (ar x - ai y) + br,  py = (ai x + ar y) + bi,  d2 = dx dx + dy dy
+// with floating-point contraction disabled, so inlier decisions are bit-reproducible.
+// Kernel 2 (fit_resolve): walks the pairs of the call in order through the dwell-block state
+// machine and writes the chosen model's parameters, info and inlier flags.
+#include <cmath>
+
+#include "vs_common.hpp"
+
+#pragma clang fp contract(off)
+
+namespace {
+
+struct ModelFit {
+    double p[4];
+    double err;
+    int32_t n_inl;
+    int32_t pad;
+};
+
+struct PairRec {
+    int32_t n_valid;
+    int32_t skipped;
+    int32_t pad[2];
+    ModelFit m[2];   // [VS_RIGID], [VS_SIMILARITY]
+};
+
+__host__ __device__ inline int64_t cap_aligned(int cap) { return ((int64_t)cap + 255) & ~(int64_t)255; }
+__host__ __device__ inline int64_t rec_bytes(int cap) { return 256 + 2 * cap_aligned(cap); }
+
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t ctr)
+{
+    uint64_t z = seed + (ctr + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t draw(uint64_t seed, int64_t stream_id, int64_t pair, int h, int k)
+{
+    const uint64_t ctr = (((uint64_t)stream_id & 0xFFFFFull) << 44) | (((uint64_t)pair & 0xFFFFFFFull) << 16) |
+                         (((uint64_t)h & 0x7FFFull) << 1) | ((uint64_t)k & 1u);
+    return splitmix64_at(seed, ctr);
+}
+
+__device__ __forceinline__ double resid2(double ar, double ai, double br, double bi, double x, double y, double xd,
+                                         double yd)
+{
+    const double px = (ar * x - ai * y) + br;
+    const double py = (ai * x + ar * y) + bi;
+    const double dx = xd - px, dy = yd - py;
+    return dx * dx + dy * dy;
+}
+
+constexpr int NT = 256;
+
+struct FitArgs {
+    int32_t model;
+    int32_t iters;
+    double tau2;
+    uint64_t seed;
+    int64_t stream_id;
+    int32_t min_valid;
+    int32_t dwell;
+    double cx, cy;
+};
+
+// deterministic block sum of NV doubles per thread: fixed tree over the 256 threads
+template <int NV>
+__device__ void block_sum(double (&v)[NV], double* red /* [NV][NT] */)
+{
+    const int t = threadIdx.x;
+    for (int j = 0; j < NV; ++j) red[j * NT + t] = v[j];
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+        if (t < o)
+            for (int j = 0; j < NV; ++j) red[j * NT + t] += red[j * NT + t + o];
+        __syncthreads();
+    }
+    for (int j = 0; j < NV; ++j) v[j] = red[j * NT];
+    __syncthreads();
+}
+
+__device__ void solve4(double A[4][4], double b[4], double x[4])
+{
+    int perm[4] = {0, 1, 2, 3};
+    for (int c = 0; c < 4; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 4; ++r)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        if (piv != c) {
+            for (int k = 0; k < 4; ++k) { const double t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t; }
+            const double t = b[c]; b[c] = b[piv]; b[piv] = t;
+            const int tp = perm[c]; perm[c] = perm[piv]; perm[piv] = tp;
+        }
+        for (int r = c + 1; r < 4; ++r) {
+            const double f = A[r][c] / A[c][c];
+            for (int k = c; k < 4; ++k) A[r][k] -= f * A[c][k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = 3; r >= 0; --r) {
+        double s = b[r];
+        for (int k = r + 1; k < 4; ++k) s -= A[r][k] * x[k];
+        x[r] = s / A[r][r];
+    }
+    (void)perm;
+}
+
+// least squares on the flagged points (all when flags == nullptr); result in out[4]
+__device__ void ls_refit(int model, const float* xs, const float* ys, const float* xd, const float* yd, double cx,
+                         double cy, const uint8_t* flags, int n, double* red, double* out)
+{
+    const int t = threadIdx.x;
+    if (model == VS_SIMILARITY) {
+        double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // n, Sx, Sy, Sx', Sy', S2, Sdot, Scross
+        for (int i = t; i < n; i += NT) {
+            if (flags && !flags[i]) continue;
+            const double x = xs[i] - cx, y = ys[i] - cy, u = xd[i] - cx, w = yd[i] - cy;
+            v[0] += 1.0;
+            v[1] += x;
+            v[2] += y;
+            v[3] += u;
+            v[4] += w;
+            v[5] += x * x + y * y;
+            v[6] += x * u + y * w;
+            v[7] += x * w - y * u;
+        }
+        block_sum<8>(v, red);
+        if (t == 0) {
+            double A[4][4] = {{v[5], 0.0, v[1], v[2]}, {0.0, v[5], -v[2], v[1]}, {v[1], -v[2], v[0], 0.0},
+                              {v[2], v[1], 0.0, v[0]}};
+            double b[4] = {v[6], v[7], v[3], v[4]};
+            double x[4];
+            if (v[5] * v[0] - (v[1] * v[1] + v[2] * v[2]) > 0.0) {
+                solve4(A, b, x);
+            } else {            // all points coincide: pure translation
+                x[0] = 1.0;
+                x[1] = 0.0;
+                x[2] = (v[3] - v[1]) / v[0];
+                x[3] = (v[4] - v[2]) / v[0];
+            }
+            for (int k = 0; k < 4; ++k) out[k] = x[k];
+        }
+        __syncthreads();
+        return;
+    }
+    // rigid: centroids, then centred cross sums
+    double m[5] = {0, 0, 0, 0, 0};
+    for (int i = t; i < n; i += NT) {
+        if (flags && !flags[i]) continue;
+        m[0] += 1.0;
+        m[1] += xs[i] - cx;
+        m[2] += ys[i] - cy;
+        m[3] += xd[i] - cx;
+        m[4] += yd[i] - cy;
+    }
+    block_sum<5>(m, red);
+    const double mx = m[1] / m[0], my = m[2] / m[0], mu = m[3] / m[0], mw = m[4] / m[0];
+    double s[2] = {0, 0};
+    for (int i = t; i < n; i += NT) {
+        if (flags && !flags[i]) continue;
+        const double x = (xs[i] - cx) - mx, y = (ys[i] - cy) - my, u = (xd[i] - cx) - mu, w = (yd[i] - cy) - mw;
+        s[0] += x * u + y * w;
+        s[1] += x * w - y * u;
+    }
+    block_sum<2>(s, red);
+    if (t == 0) {
+        const double th = atan2(s[1], s[0]);
+        const double a = cos(th), b = sin(th);
+        out[0] = a;
+        out[1] = b;
+        out[2] = mu - (a * mx - b * my);
+        out[3] = mw - (b * mx + a * my);
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(NT) void fit_pair_kernel(const float* __restrict__ src, const float* __restrict__ dst,
+                                                      const uint8_t* __restrict__ valid, int capacity, FitArgs a,
+                                                      int64_t pair_index0, uint8_t* ws)
+{
+    __shared__ float xs[VS_MAX_CORNERS], ys[VS_MAX_CORNERS], xd[VS_MAX_CORNERS], yd[VS_MAX_CORNERS];
+    __shared__ uint16_t slot_of[VS_MAX_CORNERS];
+    __shared__ uint8_t inl[VS_MAX_CORNERS];
+    __shared__ double red[8 * NT];
+    __shared__ int32_t s_cnt[NT];
+    __shared__ int32_t w_score[4], w_h[4];
+    __shared__ double w_model[4][4];
+    __shared__ double s_out[4];
+    __shared__ int s_n, s_best_h, s_ninl;
+
+    const int item = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t pair = pair_index0 + item;
+    PairRec* rec = reinterpret_cast<PairRec*>(ws + item * rec_bytes(capacity));
+    uint8_t* masks = ws + item * rec_bytes(capacity) + 256;
+    const int64_t base = (int64_t)item * capacity;
+
+    // ---- stable compaction of the valid slots
+    const int chunk = (capacity + NT - 1) / NT;
+    const int c0 = t * chunk, c1 = min(capacity, c0 + chunk);
+    int cnt = 0;
+    for (int k = c0; k < c1; ++k) cnt += valid[base + k] != 0;
+    s_cnt[t] = cnt;
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int i = 0; i < NT; ++i) { const int c = s_cnt[i]; s_cnt[i] = run; run += c; }
+        s_n = run;
+    }
+    __syncthreads();
+    {
+        int o = s_cnt[t];
+        for (int k = c0; k < c1; ++k) {
+            if (!valid[base + k]) continue;
+            xs[o] = src[2 * (base + k)];          // raw FP32 pixel coordinates; centred in binary64
+            ys[o] = src[2 * (base + k) + 1];      // at use, so every side sees identical values
+            xd[o] = dst[2 * (base + k)];
+            yd[o] = dst[2 * (base + k) + 1];
+            slot_of[o] = (uint16_t)k;
+            ++o;
+        }
+    }
+    for (int k = t; k < 2 * cap_aligned(capacity); k += NT) masks[k] = 0;
+    __syncthreads();
+    const int n = s_n;
+    if (t == 0) {
+        rec->n_valid = n;
+        rec->skipped = (n < a.min_valid || n < 2) ? 1 : 0;
+    }
+    if (n < a.min_valid || n < 2) return;
+
+    const int m_first = (a.model == VS_HYBRID) ? VS_RIGID : a.model;
+    const int m_last = (a.model == VS_HYBRID) ? VS_SIMILARITY : a.model;
+    for (int model = m_first; model <= m_last; ++model) {
+        bool have = false;
+        if (a.iters > 0) {
+            int best = -1, best_h = -1;
+            double bm[4] = {1, 0, 0, 0};
+            for (int h = wv; h < a.iters; h += 4) {
+                const int i1 = (int)(draw(a.seed, a.stream_id, pair, h, 0) % (uint64_t)n);
+                int i2 = (int)(draw(a.seed, a.stream_id, pair, h, 1) % (uint64_t)n);
+                if (i2 == i1) i2 = (i2 + 1) % n;
+                const double x1 = xs[i1] - a.cx, y1 = ys[i1] - a.cy, x2 = xs[i2] - a.cx, y2 = ys[i2] - a.cy;
+                const double u1 = xd[i1] - a.cx, w1 = yd[i1] - a.cy, u2 = xd[i2] - a.cx, w2 = yd[i2] - a.cy;
+                const double dzx = x2 - x1, dzy = y2 - y1;
+                const double den = dzx * dzx + dzy * dzy;
+                if (den < 1.0) continue;
+                const double wx = u2 - u1, wy = w2 - w1;
+                double ar = (wx * dzx + wy * dzy) / den;
+                double ai = (wy * dzx - wx * dzy) / den;
+                double br, bi;
+                if (model == VS_RIGID) {
+                    const double mag = sqrt(ar * ar + ai * ai);
+                    if (!(mag > 0.0)) continue;
+                    ar = ar / mag;
+                    ai = ai / mag;
+                    const double sxs = x1 + x2, sys = y1 + y2, sxd = u1 + u2, syd = w1 + w2;
+                    br = (sxd - (ar * sxs - ai * sys)) * 0.5;
+                    bi = (syd - (ai * sxs + ar * sys)) * 0.5;
+                } else {
+                    br = u1 - (ar * x1 - ai * y1);
+                    bi = w1 - (ai * x1 + ar * y1);
+                }
+                int sc = 0;
+                for (int i = lane; i < n; i += 64) sc += resid2(ar, ai, br, bi, xs[i] - a.cx, ys[i] - a.cy, xd[i] - a.cx,
+                                                                  yd[i] - a.cy) <= a.tau2;
+                sc = vs::wave_sum_i(sc);
+                if (sc > best) {
+                    best = sc;
+                    best_h = h;
+                    bm[0] = ar; bm[1] = ai; bm[2] = br; bm[3] = bi;
+                }
+            }
+            if (lane == 0) {
+                w_score[wv] = best;
+                w_h[wv] = best_h;
+                for (int k = 0; k < 4; ++k) w_model[wv][k] = bm[k];
+            }
+            __syncthreads();
+            if (t == 0) {
+                int bw = -1;
+                for (int w = 0; w < 4; ++w) {
+                    if (w_h[w] < 0) continue;
+                    if (bw < 0 || w_score[w] > w_score[bw] || (w_score[w] == w_score[bw] && w_h[w] < w_h[bw])) bw = w;
+                }
+                s_best_h = bw;
+            }
+            __syncthreads();
+            const int bw = s_best_h;
+            if (bw >= 0) {
+                const double ar = w_model[bw][0], ai = w_model[bw][1], br = w_model[bw][2], bi = w_model[bw][3];
+                int m = 0;
+                for (int i = t; i < n; i += NT) {
+                    const uint8_t f =
+                        resid2(ar, ai, br, bi, xs[i] - a.cx, ys[i] - a.cy, xd[i] - a.cx, yd[i] - a.cy) <= a.tau2;
+                    inl[i] = f;
+                    m += f;
+                }
+                s_cnt[t] = m;
+                __syncthreads();
+                if (t == 0) {
+                    int tot = 0;
+                    for (int i = 0; i < NT; ++i) tot += s_cnt[i];
+                    s_ninl = tot;
+                }
+                __syncthreads();
+                have = s_ninl >= 2;
+            }
+        }
+        if (!have) {
+            for (int i = t; i < n; i += NT) inl[i] = 1;
+            if (t == 0) s_ninl = n;
+            __syncthreads();
+        }
+        ls_refit(model, xs, ys, xd, yd, a.cx, a.cy, inl, n, red, s_out);
+        // RMS residual of the refitted model over all valid points
+        double e[1] = {0.0};
+        const double p0 = s_out[0], p1 = s_out[1], p2 = s_out[2], p3 = s_out[3];
+        for (int i = t; i < n; i += NT)
+            e[0] += resid2(p0, p1, p2, p3, xs[i] - a.cx, ys[i] - a.cy, xd[i] - a.cx, yd[i] - a.cy);
+        block_sum<1>(e, red);
+        if (t == 0) {
+            ModelFit& mf = rec->m[model];
+            for (int k = 0; k < 4; ++k) mf.p[k] = s_out[k];
+            mf.err = sqrt(e[0] / n);
+            mf.n_inl = s_ninl;
+        }
+        uint8_t* mk = masks + model * cap_aligned(capacity);
+        for (int i = t; i < n; i += NT) mk[slot_of[i]] = inl[i];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(NT) void fit_resolve_kernel(int n, int capacity, FitArgs a, int64_t pair_index0,
+                                                         vs_fit_state* state, const uint8_t* ws,
+                                                         double* __restrict__ params, vs_fit_info* __restrict__ info,
+                                                         uint8_t* __restrict__ inliers)
+{
+    __shared__ int8_t choice[1024];
+    __shared__ int8_t decided[1024];
+    const int t = threadIdx.x;
+    // the state machine runs in chunks of 1024 pairs, in order
+    for (int c0 = 0; c0 < n; c0 += 1024) {
+        const int c1 = min(n, c0 + 1024);
+        if (t == 0) {
+            vs_fit_state st = *state;
+            for (int i = c0; i < c1; ++i) {
+                const PairRec* rec = reinterpret_cast<const PairRec*>(ws + i * rec_bytes(capacity));
+                const int64_t pair = pair_index0 + i;
+                const int64_t block = pair / (a.dwell > 0 ? a.dwell : 1);
+                if (st.block != block) {
+                    st.block = block;
+                    st.decided = 0;
+                }
+                int ch, dh = 0;
+                if (rec->skipped) {
+                    ch = -1 - ((a.model == VS_HYBRID) ? st.model : a.model);   // identity, reported model
+                } else if (a.model == VS_HYBRID) {
+                    if (!st.decided) {
+                        st.model = (rec->m[VS_RIGID].err < rec->m[VS_SIMILARITY].err) ? VS_RIGID : VS_SIMILARITY;
+                        st.decided = 1;
+                        dh = 1;
+                    }
+                    ch = st.model;
+                } else {
+                    ch = a.model;
+                }
+                choice[i - c0] = (int8_t)ch;
+                decided[i - c0] = (int8_t)dh;
+            }
+            *state = st;
+        }
+        __syncthreads();
+        for (int i = c0 + t; i < c1; i += NT) {
+            const PairRec* rec = reinterpret_cast<const PairRec*>(ws + i * rec_bytes(capacity));
+            const int ch = choice[i - c0];
+            vs_fit_info f;
+            f.n_valid = rec->n_valid;
+            f.skipped = rec->skipped;
+            f.decided_here = decided[i - c0];
+            f.pad = 0;
+            f.err_rigid = __longlong_as_double(0x7ff8000000000000ll);
+            f.err_sim = f.err_rigid;
+            double* po = params + 4 * (int64_t)i;
+            if (ch < 0) {
+                f.model = -1 - ch;
+                f.n_inliers = 0;
+                po[0] = 1.0; po[1] = 0.0; po[2] = 0.0; po[3] = 0.0;
+            } else {
+                f.model = ch;
+                f.n_inliers = rec->m[ch].n_inl;
+                for (int k = 0; k < 4; ++k) po[k] = rec->m[ch].p[k];
+                if (f.decided_here) {
+                    f.err_rigid = rec->m[VS_RIGID].err;
+                    f.err_sim = rec->m[VS_SIMILARITY].err;
+                }
+            }
+            info[i] = f;
+        }
+        if (inliers) {
+            for (int i = c0; i < c1; ++i) {
+                const int ch = choice[i - c0];
+                const uint8_t* mk = ws + i * rec_bytes(capacity) + 256 + (ch < 0 ? 0 : ch) * cap_aligned(capacity);
+                uint8_t* o = inliers + (int64_t)i * capacity;
+                for (int k = t; k < capacity; k += NT) o[k] = ch < 0 ? 0 : mk[k];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void fit_state_init_kernel(vs_fit_state* s)
+{
+    s->block = -1;
+    s->model = VS_SIMILARITY;
+    s->decided = 0;
+}
+
+}  // namespace
+
+extern "C" size_t vs_fit_workspace(int32_t n, int32_t capacity)
+{
+    if (n <= 0 || capacity <= 0) return 0;
+    return (size_t)rec_bytes(capacity) * (size_t)n;
+}
+
+extern "C" int vs_fit_state_init(vs_fit_state* state, void* stream)
+{
+    if (!state) return vs::set_error(VS_ERR_INVALID, "vs_fit_state_init: null state");
+    fit_state_init_kernel<<<1, 1, 0, vs::as_stream(stream)>>>(state);
+    return vs::check_launch("vs_fit_state_init");
+}
+
+extern "C" int vs_fit_similarity(const float* src, const float* dst, const uint8_t* valid, int32_t capacity, int32_t n,
+                                 const vs_fit_params* p, int64_t pair_index0, vs_fit_state* state, double* params,
+                                 vs_fit_info* info, uint8_t* inliers, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!p) return vs::set_error(VS_ERR_INVALID, "vs_fit_similarity: null params");
+    if (n < 0 || capacity <= 0) return vs::set_error(VS_ERR_INVALID, "vs_fit_similarity: bad count or capacity");
+    if (n == 0) return VS_OK;
+    if (!src || !dst || !valid || !state || !params || !info || !workspace)
+        return vs::set_error(VS_ERR_INVALID, "vs_fit_similarity: null argument");
+    if (capacity > VS_MAX_CORNERS) return vs::set_error(VS_ERR_UNSUPPORTED, "vs_fit_similarity: capacity > %d", VS_MAX_CORNERS);
+    if (p->model < VS_RIGID || p->model > VS_HYBRID || p->ransac_iters < 0 || p->ransac_iters > 32767 ||
+        !(p->inlier_thresh >= 0.0) || p->dwell < 1 || pair_index0 < 0)
+        return vs::set_error(VS_ERR_INVALID, "vs_fit_similarity: bad parameters");
+    if (n > 65535) return vs::set_error(VS_ERR_INVALID, "vs_fit_similarity: more than 65535 pairs");
+    const size_t need = vs_fit_workspace(n, capacity);
+    if (ws_bytes < need) return vs::set_error(VS_ERR_WORKSPACE, "vs_fit_similarity: workspace %zu < %zu", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(workspace) & 255)
+        return vs::set_error(VS_ERR_INVALID, "vs_fit_similarity: workspace must be 256-byte aligned");
+    FitArgs a;
+    a.model = p->model;
+    a.iters = p->ransac_iters;
+    a.tau2 = p->inlier_thresh * p->inlier_thresh;
+    a.seed = p->seed;
+    a.stream_id = p->stream_id;
+    a.min_valid = p->min_valid;
+    a.dwell = p->dwell;
+    a.cx = p->cx;
+    a.cy = p->cy;
+    hipStream_t s = vs::as_stream(stream);
+    uint8_t* w8 = static_cast<uint8_t*>(workspace);
+    fit_pair_kernel<<<n, NT, 0, s>>>(src, dst, valid, capacity, a, pair_index0, w8);
+    int e = vs::check_launch("vs_fit_similarity(pairs)");
+    if (e) return e;
+    fit_resolve_kernel<<<1, NT, 0, s>>>(n, capacity, a, pair_index0, state, w8, params, info, inliers);
+    return vs::check_launch("vs_fit_similarity(resolve)");
+}

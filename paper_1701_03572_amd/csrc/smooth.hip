@@ -1,0 +1,184 @@
+// smooth_trajectory: per-stream trajectory accumulation, smoothing and correction matrices.
+//
+// One 256-thread workgroup per call. Thread 0 appends the new pairs to the trajectory in order
+// (binary64, sequential, as the definition states) into a ring of the last VS_TRAJ_RING frame
+// positions kept in the caller's device state; then every thread emits frames whose smoothing
+// window is complete, summing the window directly in ascending frame order. Because each
+// emitted value depends only on the positions (not on how the pairs were split across calls),
+// feeding a stream pair by pair emits bit-for-bit what one call over the whole sequence emits.
+// Long calls are processed in chunks small enough for the ring.
+#include <cmath>
+
+#include "vs_common.hpp"
+
+#pragma clang fp contract(off)
+
+namespace {
+
+struct TrajState {
+    int64_t known;      // frames whose position P_j is known (P_0 = 0 at start)
+    int64_t emitted;    // frames emitted so far
+    double kx[4];       // Kalman estimate
+    double kS[4];       // Kalman posterior variance
+    double ring[VS_TRAJ_RING][4];   // P_j at j % VS_TRAJ_RING
+    double kq[VS_TRAJ_RING][4];     // Kalman output Q_j at j % VS_TRAJ_RING
+};
+
+__global__ void traj_init_kernel(TrajState* s)
+{
+    const int t = threadIdx.x;
+    if (t == 0) {
+        s->known = 1;
+        s->emitted = 0;
+        for (int c = 0; c < 4; ++c) {
+            s->kx[c] = 0.0;
+            s->kS[c] = 0.0;
+        }
+    }
+    for (int i = t; i < VS_TRAJ_RING * 4; i += blockDim.x) {
+        (&s->ring[0][0])[i] = 0.0;
+        (&s->kq[0][0])[i] = 0.0;
+    }
+}
+
+struct SmoothArgs {
+    int mode, radius;
+    double ratio, crop, cx, cy;
+};
+
+__device__ void emit_frame(const TrajState* s, const SmoothArgs& a, int64_t j, int64_t last_known, double* M)
+{
+    double q[4];
+    const double* P = s->ring[j % VS_TRAJ_RING];
+    if (a.mode == VS_SMOOTH_KALMAN) {
+        for (int c = 0; c < 4; ++c) q[c] = s->kq[j % VS_TRAJ_RING][c];
+    } else {
+        const int64_t lo = (a.mode == VS_SMOOTH_CENTERED) ? (j - a.radius > 0 ? j - a.radius : 0)
+                                                          : (j - 2 * a.radius > 0 ? j - 2 * a.radius : 0);
+        int64_t hi = (a.mode == VS_SMOOTH_CENTERED) ? j + a.radius : j;
+        hi = hi < last_known ? hi : last_known;
+        for (int c = 0; c < 4; ++c) {
+            double sum = 0.0;
+            for (int64_t i = lo; i <= hi; ++i) sum += s->ring[i % VS_TRAJ_RING][c];
+            q[c] = sum / (double)(hi - lo + 1);
+        }
+    }
+    const double dx = q[0] - P[0], dy = q[1] - P[1], da = q[2] - P[2], ds = q[3] - P[3];
+    const double z = 1.0 / (1.0 - 2.0 * a.crop);
+    const double sc = exp(ds);
+    const double ca = sc * cos(da), sb = sc * sin(da);
+    M[0] = z * ca;
+    M[1] = -z * sb;
+    M[2] = z * (dx - ca * a.cx + sb * a.cy) + a.cx;
+    M[3] = z * sb;
+    M[4] = z * ca;
+    M[5] = z * (dy - sb * a.cx - ca * a.cy) + a.cy;
+}
+
+__global__ __launch_bounds__(256) void smooth_kernel(const double* __restrict__ pairs, int n_new, int eos, SmoothArgs a,
+                                                     TrajState* s, double* __restrict__ mats, int mats_cap,
+                                                     int32_t* n_emitted, int64_t* first_frame)
+{
+    __shared__ int64_t s_known, s_emitted, s_first;
+    __shared__ int s_count;
+    const int t = threadIdx.x;
+    const int window = (a.mode == VS_SMOOTH_KALMAN) ? 0 : (a.mode == VS_SMOOTH_CENTERED ? 2 * a.radius : 2 * a.radius);
+    const int chunk = VS_TRAJ_RING - window - 1;
+    if (t == 0) {
+        s_known = s->known;
+        s_emitted = s->emitted;
+        s_first = s->emitted;
+        s_count = 0;
+    }
+    __syncthreads();
+    int consumed = 0;
+    while (true) {
+        const int take = (n_new - consumed) < chunk ? (n_new - consumed) : chunk;
+        if (t == 0) {
+            int64_t known = s_known;
+            for (int k = 0; k < take; ++k) {
+                const double* q = pairs + 4 * (int64_t)(consumed + k);
+                const double d[4] = {q[2], q[3], atan2(q[1], q[0]), log(sqrt(q[0] * q[0] + q[1] * q[1]))};
+                const double* prev = s->ring[(known - 1) % VS_TRAJ_RING];
+                double* cur = s->ring[known % VS_TRAJ_RING];
+                for (int c = 0; c < 4; ++c) cur[c] = prev[c] + d[c];
+                if (a.mode == VS_SMOOTH_KALMAN) {
+                    for (int c = 0; c < 4; ++c) {
+                        const double Sm = s->kS[c] + a.ratio;
+                        const double K = Sm / (Sm + 1.0);
+                        s->kx[c] = s->kx[c] + K * (cur[c] - s->kx[c]);
+                        s->kS[c] = (1.0 - K) * Sm;
+                        s->kq[known % VS_TRAJ_RING][c] = s->kx[c];
+                    }
+                }
+                ++known;
+            }
+            s_known = known;
+        }
+        consumed += take;
+        __syncthreads();
+        const bool last = consumed >= n_new;
+        const int64_t known = s_known;
+        int64_t end;     // frames [s_emitted, end) are emitted now
+        if (a.mode == VS_SMOOTH_CENTERED) end = (last && eos) ? known : known - a.radius;
+        else end = known;
+        if (end < s_emitted) end = s_emitted;
+        const int64_t e0 = s_emitted;
+        for (int64_t j = e0 + t; j < end; j += 256) {
+            const int64_t k = j - s_first;
+            if (k < mats_cap) emit_frame(s, a, j, known - 1, mats + 6 * k);
+        }
+        __syncthreads();
+        if (t == 0) {
+            s_count += (int)(end - e0);
+            s_emitted = end;
+        }
+        __syncthreads();
+        if (last) break;
+    }
+    if (t == 0) {
+        s->known = s_known;
+        s->emitted = s_emitted;
+        if (n_emitted) *n_emitted = s_count < mats_cap ? s_count : mats_cap;
+        if (first_frame) *first_frame = s_first;
+    }
+}
+
+}  // namespace
+
+extern "C" size_t vs_traj_state_bytes(void) { return sizeof(TrajState); }
+
+extern "C" int vs_traj_state_init(void* state, void* stream)
+{
+    if (!state) return vs::set_error(VS_ERR_INVALID, "vs_traj_state_init: null state");
+    if (reinterpret_cast<uintptr_t>(state) & 7) return vs::set_error(VS_ERR_INVALID, "vs_traj_state_init: misaligned state");
+    traj_init_kernel<<<1, 256, 0, vs::as_stream(stream)>>>(static_cast<TrajState*>(state));
+    return vs::check_launch("vs_traj_state_init");
+}
+
+extern "C" int vs_smooth_trajectory(const double* pair_params, int32_t n_new, int32_t end_of_stream,
+                                    const vs_smooth_params* p, void* state, double* mats, int32_t mats_capacity,
+                                    int32_t* n_emitted, int64_t* first_frame, void* stream)
+{
+    if (!p || !state) return vs::set_error(VS_ERR_INVALID, "vs_smooth_trajectory: null argument");
+    if (n_new < 0 || mats_capacity < 0 || (n_new > 0 && !pair_params) || (mats_capacity > 0 && !mats))
+        return vs::set_error(VS_ERR_INVALID, "vs_smooth_trajectory: bad counts");
+    if (p->mode < VS_SMOOTH_CENTERED || p->mode > VS_SMOOTH_KALMAN)
+        return vs::set_error(VS_ERR_INVALID, "vs_smooth_trajectory: bad mode");
+    if (p->mode != VS_SMOOTH_KALMAN && (p->radius < 0 || 2 * p->radius + 2 > VS_TRAJ_RING))
+        return vs::set_error(VS_ERR_UNSUPPORTED, "vs_smooth_trajectory: radius must be 0..%d", (VS_TRAJ_RING - 2) / 2);
+    if (p->mode == VS_SMOOTH_KALMAN && !(p->kalman_ratio > 0.0))
+        return vs::set_error(VS_ERR_INVALID, "vs_smooth_trajectory: kalman_ratio must be > 0");
+    if (!(p->crop >= 0.0 && p->crop < 0.5)) return vs::set_error(VS_ERR_INVALID, "vs_smooth_trajectory: crop in [0, 0.5)");
+    SmoothArgs a;
+    a.mode = p->mode;
+    a.radius = p->radius;
+    a.ratio = p->kalman_ratio;
+    a.crop = p->crop;
+    a.cx = p->cx;
+    a.cy = p->cy;
+    smooth_kernel<<<1, 256, 0, vs::as_stream(stream)>>>(pair_params, n_new, end_of_stream, a,
+                                                        static_cast<TrajState*>(state), mats, mats_capacity,
+                                                        n_emitted, first_frame);
+    return vs::check_launch("vs_smooth_trajectory");
+}

@@ -1,0 +1,259 @@
+"""Stabilization pipelines over the C ABI (Section 2: motion estimation -> motion compensation ->
+image composition).
+
+``Stabilizer`` is the plain per-frame path of the real-time version (Section 6): every pushed
+frame is processed as soon as it arrives and the output lags by the smoothing radius (centred
+window) or not at all (causal / Kalman).
+
+``SequenceStabilizer`` runs a whole resident sequence (the offline version, Stage I of the paper,
+Section 7.1) with cross-frame parallelism: all pyramids in one launch, corner detection on every
+5th frame in one launch, then five tracking steps each covering all 5-frame segments at once
+(re-detection after a skipped pair stays on the device through gated launches), all fits, the
+smoothing and all warps in one launch each. Segments are independent because corners are
+re-detected every 5 frames (Section 3.2), so both paths produce bit-identical results.
+
+Every operation runs in libvstab's HIP kernels; torch only allocates device memory and supplies
+the stream.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import vstab as V
+from .params import StabParams
+
+
+def _lk_params(P: StabParams) -> V.vs_lk_params:
+    return V.vs_lk_params(P.win_half, P.max_iter, P.eps, P.min_eig, int(P.fb), P.fb_thresh)
+
+
+def _detect_params(P: StabParams, w: int, h: int) -> V.vs_detect_params:
+    mx, my = P.roi(w, h)
+    return V.vs_detect_params(P.max_corners, P.quality, P.min_dist, mx, my)
+
+
+def _fit_params(P: StabParams, w: int, h: int) -> V.vs_fit_params:
+    return V.vs_fit_params(P.model, P.ransac_iters, P.inlier_thresh, P.seed, P.stream_id, P.min_valid, P.dwell,
+                           (w - 1) / 2.0, (h - 1) / 2.0)
+
+
+def _smooth_params(P: StabParams, w: int, h: int) -> V.vs_smooth_params:
+    return V.vs_smooth_params(P.smooth_mode, P.radius, P.kalman_ratio, P.crop, (w - 1) / 2.0, (h - 1) / 2.0)
+
+
+def _bytes(n: int, device) -> torch.Tensor:
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
+
+
+class SequenceStabilizer:
+    """Whole-sequence (offline) path with segment-parallel tracking. Buffers are allocated once
+    for a (width, height, max_frames) shape and reused by every ``run``."""
+
+    def __init__(self, width: int, height: int, max_frames: int, P: StabParams, device="cuda"):
+        self.W, self.H, self.P = width, height, P
+        self.n_max = max_frames
+        self.dev = torch.device(device)
+        self.layout = V.vs_pyramid_layout(width, height, width, P.levels)
+        self.cap = P.max_corners
+        n, cap, dev = max_frames, self.cap, self.dev
+        self.n_seg_max = max(1, math.ceil((n - 1) / P.redetect_every))
+        self.pyr = _bytes(n * self.layout.bytes, dev)
+        self.src = torch.zeros((n, cap, 2), dtype=torch.float32, device=dev)      # one spare record
+        self.asrc = torch.zeros((n, cap), dtype=torch.uint8, device=dev)
+        self.dst = torch.zeros((n, cap, 2), dtype=torch.float32, device=dev)
+        self.status = torch.zeros((n, cap), dtype=torch.uint8, device=dev)
+        self.fb_err = torch.zeros((n, cap), dtype=torch.float32, device=dev)
+        self.n_valid = torch.zeros(n, dtype=torch.int32, device=dev)
+        self.count = torch.zeros(n, dtype=torch.int32, device=dev)
+        self.score = torch.zeros((n, cap), dtype=torch.float64, device=dev)
+        self.det_ws_bytes = V.vs_detect_workspace(width, height, self.n_seg_max)
+        self.det_ws = _bytes(self.det_ws_bytes, dev)
+        self.fit_ws_bytes = V.vs_fit_workspace(max(n - 1, 1), cap)
+        self.fit_ws = _bytes(self.fit_ws_bytes, dev)
+        self.fit_state = _bytes(V.FIT_STATE_BYTES, dev)
+        self.pair_params = torch.zeros((max(n - 1, 1), 4), dtype=torch.float64, device=dev)
+        self.info = _bytes(max(n - 1, 1) * V.FIT_INFO_BYTES, dev)
+        self.inliers = torch.zeros((max(n - 1, 1), cap), dtype=torch.uint8, device=dev)
+        self.traj_state = _bytes(V.vs_traj_state_bytes(), dev)
+        self.mats = torch.zeros((n, 6), dtype=torch.float64, device=dev)
+        self.n_emitted = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.first = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.out = torch.empty((n, height, width), dtype=torch.uint8, device=dev)
+        # per tracking step: [window set-ups, iterations] of its vs_track_lk launch
+        self.lk_work = torch.zeros((P.redetect_every, 2), dtype=torch.int64, device=dev)
+        self._lkp = _lk_params(P)
+        self._dp = _detect_params(P, width, height)
+        self._fp = _fit_params(P, width, height)
+        self._sp = _smooth_params(P, width, height)
+
+    def run(self, frames: torch.Tensor, warp: bool = True, lk_events: list | None = None) -> None:
+        """Stabilize frames [n, H, W] (uint8, resident on the device). Results stay in the
+        device buffers (pair_params, info, mats, out, ...); nothing is synchronised. When
+        ``lk_events`` is a list, a (start, end) pair of timing events recorded on the current
+        stream around every tracking launch is appended to it."""
+        n = frames.shape[0]
+        assert frames.is_cuda and frames.dtype == torch.uint8 and frames.is_contiguous()
+        assert frames.shape[1:] == (self.H, self.W) and 1 <= n <= self.n_max
+        P, L, cap = self.P, self.layout, self.cap
+        fs, ps, e = self.H * self.W, L.bytes, P.redetect_every
+        f0, p0 = frames.data_ptr(), self.pyr.data_ptr()
+        V.vs_build_pyramid(f0, fs, p0, ps, n, L)
+        n_pairs = n - 1
+        if n_pairs >= 1:
+            n_seg = math.ceil(n_pairs / e)
+            xy, al = self.src.data_ptr(), self.asrc.data_ptr()
+            V.vs_detect_corners(f0, e * fs, self.W, self.H, self.W, n_seg, e, None, 0, self._dp, cap, xy,
+                                self.score.data_ptr(), self.count.data_ptr(), al, self.det_ws, self.det_ws_bytes)
+            rec2, rec1 = cap * 2 * 4, cap                      # bytes per point record / flag record
+            for s in range(e):
+                n_s = (n_pairs - 1 - s) // e + 1 if s <= n_pairs - 1 else 0
+                if n_s <= 0:
+                    break
+                chain = s < e - 1
+                if lk_events is not None:
+                    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                    ev[0].record()
+                V.vs_track_lk(f0 + s * fs, p0 + s * ps, f0 + (s + 1) * fs, p0 + (s + 1) * ps, e * fs, e * ps, n_s, e,
+                              L, xy + s * rec2, al + s * rec1, cap, self._lkp, self.dst.data_ptr() + s * rec2,
+                              self.status.data_ptr() + s * rec1, self.fb_err.data_ptr() + s * cap * 4,
+                              self.n_valid.data_ptr() + s * 4, xy + (s + 1) * rec2 if chain else None,
+                              al + (s + 1) * rec1 if chain else None, self.lk_work[s])
+                if lk_events is not None:
+                    ev[1].record()
+                    lk_events.append(ev)
+                n_next = (n_pairs - 1 - (s + 1)) // e + 1 if s + 1 <= n_pairs - 1 else 0
+                if chain and n_next > 0:
+                    # re-detect where the pair just tracked was skipped (too few valid points)
+                    V.vs_detect_corners(f0 + (s + 1) * fs, e * fs, self.W, self.H, self.W, n_next, e,
+                                        self.n_valid.data_ptr() + s * 4, P.min_valid, self._dp, cap,
+                                        xy + (s + 1) * rec2, self.score.data_ptr() + (s + 1) * cap * 8,
+                                        self.count.data_ptr() + (s + 1) * 4, al + (s + 1) * rec1, self.det_ws,
+                                        self.det_ws_bytes)
+            V.vs_fit_state_init(self.fit_state)
+            V.vs_fit_similarity(self.src, self.dst, self.status, cap, n_pairs, self._fp, 0, self.fit_state,
+                                self.pair_params, self.info, self.inliers, self.fit_ws, self.fit_ws_bytes)
+        V.vs_traj_state_init(self.traj_state)
+        V.vs_smooth_trajectory(self.pair_params if n_pairs >= 1 else None, n_pairs, 1, self._sp, self.traj_state,
+                               self.mats, n, self.n_emitted, self.first)
+        if warp:
+            V.vs_warp_frame(frames, fs, self.W, self.H, self.W, self.mats, 6, self.out, fs, self.W, n, P.border)
+
+    def results(self, n: int) -> dict:
+        """Host copies of the per-pair results of the last run over n frames."""
+        n_pairs = n - 1
+        return {
+            "pair_params": self.pair_params[:n_pairs].cpu().numpy(),
+            "info": V.fit_info_to_dicts(self.info[:n_pairs * V.FIT_INFO_BYTES]) if n_pairs > 0 else [],
+            "mats": self.mats[:n].cpu().numpy(),
+            "src": self.src[:n_pairs].cpu().numpy(),
+            "alive_src": self.asrc[:n_pairs].cpu().numpy(),
+            "dst": self.dst[:n_pairs].cpu().numpy(),
+            "status": self.status[:n_pairs].cpu().numpy(),
+            "fb_err": self.fb_err[:n_pairs].cpu().numpy(),
+            "n_valid": self.n_valid[:n_pairs].cpu().numpy(),
+            "inliers": self.inliers[:n_pairs].cpu().numpy(),
+        }
+
+
+class Stabilizer:
+    """Plain per-frame streaming path. ``push`` enqueues all work for one frame on the current
+    stream and returns the indices and output views of the frames it emits (the outputs are
+    complete once the stream reaches this point). Pushed frames must stay unchanged until they
+    are emitted; no frame is copied."""
+
+    def __init__(self, width: int, height: int, P: StabParams, device="cuda", out_slots: int | None = None):
+        self.W, self.H, self.P = width, height, P
+        self.dev = torch.device(device)
+        dev = self.dev
+        self.layout = V.vs_pyramid_layout(width, height, width, P.levels)
+        self.cap = cap = P.max_corners
+        self.pyr = _bytes(2 * self.layout.bytes, dev)
+        self.pts = torch.zeros((2, cap, 2), dtype=torch.float32, device=dev)
+        self.alive = torch.zeros((2, cap), dtype=torch.uint8, device=dev)
+        self.dst = torch.zeros((cap, 2), dtype=torch.float32, device=dev)
+        self.status = torch.zeros(cap, dtype=torch.uint8, device=dev)
+        self.fb_err = torch.zeros(cap, dtype=torch.float32, device=dev)
+        self.n_valid = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.count = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.det_ws_bytes = V.vs_detect_workspace(width, height, 1)
+        self.det_ws = _bytes(self.det_ws_bytes, dev)
+        self.fit_ws_bytes = V.vs_fit_workspace(1, cap)
+        self.fit_ws = _bytes(self.fit_ws_bytes, dev)
+        self.fit_state = _bytes(V.FIT_STATE_BYTES, dev)
+        self.pair_params = torch.zeros((1, 4), dtype=torch.float64, device=dev)
+        self.info = _bytes(V.FIT_INFO_BYTES, dev)
+        self.inliers = torch.zeros(cap, dtype=torch.uint8, device=dev)
+        self.traj_state = _bytes(V.vs_traj_state_bytes(), dev)
+        self.lag = P.radius if P.smooth_mode == V.VS_SMOOTH_CENTERED else 0
+        self.mats_cap = self.lag + 2
+        self.mats = torch.zeros((self.mats_cap, 6), dtype=torch.float64, device=dev)
+        self.n_emitted = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.first = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.out_slots = out_slots or (self.lag + 2)
+        self.out = torch.empty((self.out_slots, height, width), dtype=torch.uint8, device=dev)
+        self._lkp = _lk_params(P)
+        self._dp = _detect_params(P, width, height)
+        self._fp = _fit_params(P, width, height)
+        self._sp = _smooth_params(P, width, height)
+        self.reset()
+
+    def reset(self):
+        self.j = 0
+        self.emitted = 0
+        self.frames = {}
+        V.vs_fit_state_init(self.fit_state)
+        V.vs_traj_state_init(self.traj_state)
+
+    def _detect(self, frame: torch.Tensor, slot: int, gated: bool):
+        V.vs_detect_corners(frame, 0, self.W, self.H, self.W, 1, 1, self.n_valid if gated else None,
+                            self.P.min_valid, self._dp, self.cap, self.pts[slot], None, self.count,
+                            self.alive[slot], self.det_ws, self.det_ws_bytes)
+
+    def _emit(self, end: int) -> list:
+        out = []
+        for k, e in enumerate(range(self.emitted, end)):
+            dst = self.out[e % self.out_slots]
+            V.vs_warp_frame(self.frames[e], 0, self.W, self.H, self.W, self.mats[k], 6, dst, 0, self.W, 1,
+                            self.P.border)
+            out.append((e, dst))
+        for e in range(self.emitted, end):
+            if e < self.j - 1:
+                self.frames.pop(e, None)
+        self.emitted = end
+        return out
+
+    def push(self, frame: torch.Tensor) -> list:
+        assert frame.is_cuda and frame.dtype == torch.uint8 and frame.shape == (self.H, self.W)
+        assert frame.is_contiguous()
+        j = self.j
+        L, bytes_ = self.layout, self.layout.bytes
+        cur, prev = j % 2, (j - 1) % 2
+        pyr_cur = self.pyr.data_ptr() + cur * bytes_
+        V.vs_build_pyramid(frame, 0, pyr_cur, 0, 1, L)
+        self.frames[j] = frame
+        if j == 0:
+            self._detect(frame, cur, gated=False)
+            V.vs_smooth_trajectory(None, 0, 0, self._sp, self.traj_state, self.mats, self.mats_cap, self.n_emitted,
+                                   self.first)
+        else:
+            V.vs_track_lk(self.frames[j - 1], self.pyr.data_ptr() + prev * bytes_, frame, pyr_cur, 0, 0, 1, 1, L,
+                          self.pts[prev], self.alive[prev], self.cap, self._lkp, self.dst, self.status, self.fb_err,
+                          self.n_valid, self.pts[cur], self.alive[cur])
+            V.vs_fit_similarity(self.pts[prev], self.dst, self.status, self.cap, 1, self._fp, j - 1, self.fit_state,
+                                self.pair_params, self.info, self.inliers, self.fit_ws, self.fit_ws_bytes)
+            self._detect(frame, cur, gated=(j % self.P.redetect_every != 0))
+            V.vs_smooth_trajectory(self.pair_params, 1, 0, self._sp, self.traj_state, self.mats, self.mats_cap,
+                                   self.n_emitted, self.first)
+        self.j = j + 1
+        end = self.j - self.lag if self.lag else self.j
+        return self._emit(max(end, self.emitted))
+
+    def flush(self) -> list:
+        """End of stream: emit the frames still waiting for their smoothing window."""
+        V.vs_smooth_trajectory(None, 0, 1, self._sp, self.traj_state, self.mats, self.mats_cap, self.n_emitted,
+                               self.first)
+        out = self._emit(self.j)
+        self.frames.clear()
+        return out

@@ -108,9 +108,9 @@ def _cameras(r: SeqRecipe, rng: np.random.Generator) -> np.ndarray:
     sdir = rng.uniform(0, 2 * math.pi, size=n)
     jt[spikes, 0] += 12.0 * k * np.cos(sdir[spikes])
     jt[spikes, 1] += 12.0 * k * np.sin(sdir[spikes])
-    js = rng.normal(0.0, 0.002, size=n)
+    # the camera keeps its altitude and zoom: rotation and translation jitter only
     ang = pa + jr
-    sc = 1.0 + js
+    sc = np.ones(n)
     tx = px + jt[:, 0]
     ty = py + jt[:, 1]
     ang -= ang[0]
@@ -161,7 +161,7 @@ def _blob_canvas(cw: int, ch: int, rng: np.random.Generator) -> np.ndarray:
 
 
 def _fbm_canvas(cw: int, ch: int, rng: np.random.Generator, octaves: int = 6,
-                persistence: float = 0.5, base_period: float = 128.0) -> np.ndarray:
+                persistence: float = 0.5, base_period: float = 64.0) -> np.ndarray:
     acc = torch.zeros((ch, cw), dtype=torch.float64)
     amp = 1.0
     period = base_period
@@ -178,14 +178,16 @@ def _fbm_canvas(cw: int, ch: int, rng: np.random.Generator, octaves: int = 6,
     return np.clip(128.0 + 45.0 * a, 0.0, 255.0)
 
 
-def _mover_textures(r: SeqRecipe, rng: np.random.Generator) -> list:
+def _mover_textures(r: SeqRecipe, canvas: np.ndarray, rng: np.random.Generator) -> list:
+    """Square patches cut from random places of the scene texture: the movers have the scene's
+    statistics (so they do not dominate the corner scores) but move independently of the camera."""
     out = []
     s = r.mover_size
+    ch, cw = canvas.shape
     for _ in range(r.n_movers):
-        t = rng.uniform(0, 255, size=(s // 8 + 3, s // 8 + 3))
-        tt = torch.from_numpy(t)[None, None]
-        up = torch.nn.functional.interpolate(tt, size=(s, s), mode="bicubic", align_corners=True)[0, 0]
-        out.append(np.clip(up.numpy(), 0, 255))
+        y0 = int(rng.integers(0, max(1, ch - s)))
+        x0 = int(rng.integers(0, max(1, cw - s)))
+        out.append(canvas[y0:y0 + s, x0:x0 + s].copy())
     return out
 
 
@@ -241,7 +243,12 @@ def make_sequence(name_or_recipe, n_frames: int | None = None, device: str | tor
         canvas = _blob_canvas(cw, ch, rng)
     else:
         canvas = _fbm_canvas(cw, ch, rng)
-    movers = _mover_textures(r, rng)
+    movers = _mover_textures(r, canvas, rng)
+    # movers are blended in with a raised-cosine border so their outline is not a hard step
+    ramp = max(3, r.mover_size // 12)
+    u = np.minimum(np.arange(r.mover_size) + 0.5, r.mover_size - np.arange(r.mover_size) - 0.5) / ramp
+    w1 = 0.5 - 0.5 * np.cos(np.pi * np.clip(u, 0.0, 1.0))
+    alpha_np = np.outer(w1, w1)
     # mover trajectories in frame coordinates: slow independent drift + wobble
     mpos = []
     for _ in range(r.n_movers):
@@ -253,6 +260,7 @@ def make_sequence(name_or_recipe, n_frames: int | None = None, device: str | tor
     dev = torch.device(device)
     dtype = torch.float32 if dev.type != "cpu" else torch.float64
     can = torch.from_numpy(canvas).to(device=dev, dtype=dtype)[None, None]
+    alpha = torch.from_numpy(alpha_np).to(device=dev, dtype=dtype)
     ys, xs = torch.meshgrid(torch.arange(H, device=dev, dtype=dtype), torch.arange(W, device=dev, dtype=dtype),
                             indexing="ij")
     frames = torch.empty((n, H, W), dtype=torch.uint8, device=dev)
@@ -271,7 +279,9 @@ def make_sequence(name_or_recipe, n_frames: int | None = None, device: str | tor
             px = _reflect(px, 0.0, W - s - 1.0)
             py = _reflect(py, 0.0, H - s - 1.0)
             x0, y0 = int(round(px)), int(round(py))
-            f[y0:y0 + s, x0:x0 + s] = torch.from_numpy(np.floor(tex + 0.5)).to(device=dev, dtype=f.dtype)
+            t = torch.from_numpy(tex).to(device=dev, dtype=f.dtype)
+            blk = f[y0:y0 + s, x0:x0 + s]
+            f[y0:y0 + s, x0:x0 + s] = torch.floor(alpha * t + (1 - alpha) * blk + 0.5)
         frames[j] = f.to(torch.uint8)
     out = frames.cpu().numpy() if (as_numpy and dev.type == "cpu") else frames
     seq = Sequence(r, out, A[:n])
