@@ -46,6 +46,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=6)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one elementwise kernel that reads and writes exactly 256 MiB (torch neg of "
+                         "float32), the reference for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: streams are independent and this build has no multi-GPU path "
@@ -111,6 +114,13 @@ def main() -> int:
                 "traffic": None, "avg_launch_ms": round(avg_lk_ms, 4), "flop_per_launch": flop_per_launch,
                 "share_of_step": round(lk_share, 4),
                 "iterations_per_setup": float(w[..., 1].sum() / max(w[..., 0].sum(), 1))}
+
+    if args.calibrate_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        del a, b
 
     plain = None
     if not args.no_plain:
