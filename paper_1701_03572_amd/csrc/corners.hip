@@ -1,9 +1,11 @@
 // detect_corners: Shi-Tomasi response + 3x3 NMS over the ROI, then the ordered greedy top-K.
 //
-// Kernel 1 (corner_response): one 256-thread workgroup per 32x32 ROI tile stages the pixels with
-// a 3-pixel halo in LDS, forms Sobel gradients, 3x3 box sums of the tensor (exact int32), the
-// binary64 score 2 det / (tr + sqrt(disc)) from exact int64 det/tr/disc, and keeps the 3x3 local
-// maxima inside the ROI. Survivors are appended (block-compacted, one atomic per workgroup) to
+// Kernel 1 (corner_response): one 256-thread workgroup per 128x16 ROI tile stages the pixels with
+// a 3-pixel halo in LDS, forms Sobel gradients and 3x3 box sums of the tensor (exact int32), and
+// keeps the 3x3 local maxima inside the ROI. The NMS runs on an FP32 estimate of the score with
+// a bounded relative error; a comparison that falls inside the error band, and every survivor,
+// uses the exact binary64 score 2 det / (tr + sqrt(disc)) from exact det/tr/disc, so the result
+// is the exact-score NMS. Survivors are appended (block-compacted, one atomic per workgroup) to
 // the item's candidate list in the workspace; the item's maximum score is folded in with an
 // integer atomic max on the score's bit pattern (non-negative doubles order like their bits).
 //
@@ -27,10 +29,12 @@ struct CandHeader {
 };
 
 constexpr int64_t HDR = 256;
-constexpr int RT = 32;          // response tile
-constexpr int PT = RT + 6;      // pixel tile with 3-pixel halo
-constexpr int GT = RT + 4;      // gradient tile (halo 2)
-constexpr int LT = RT + 2;      // score tile (halo 1)
+constexpr int RTW = 128;        // response tile width (rows of ~one cache line)
+constexpr int RTH = 16;         // response tile height
+constexpr int PER_T = RTW * RTH / 256;   // pixels per thread in the NMS pass
+constexpr int PTW = RTW + 6, PTH = RTH + 6;   // pixel tile with 3-pixel halo
+constexpr int GTW = RTW + 4, GTH = RTH + 4;   // gradient tile (halo 2)
+constexpr int LTW = RTW + 2, LTH = RTH + 2;   // score tile (halo 1)
 constexpr int CAP = 4096;       // LDS batch capacity of the selection
 constexpr int BATCH = 2048;     // keys requested per batch
 constexpr int DIGIT = 11;
@@ -70,46 +74,85 @@ __global__ void detect_init_kernel(uint8_t* ws, int64_t item_bytes, int n, int i
     h->lmax_bits = 0;
 }
 
-__device__ __forceinline__ double min_eig_key(int32_t A, int32_t B, int32_t C)
+// Exact binary64 score 2 det / (tr + sqrt(disc)) of the box-summed tensor. With |A|, |B|, |C| < 2^24
+// every product and sum below is an integer below 2^53, so det, tr and disc are exact and equal
+// to their 64-bit integer values; sqrt, add and divide are single correctly rounded operations.
+__device__ __forceinline__ double exact_key(int32_t A, int32_t B, int32_t C)
 {
-    const int64_t det = (int64_t)A * C - (int64_t)B * B;
-    const int64_t tr = (int64_t)A + C;
-    const int64_t dd = (int64_t)(A - C) * (A - C) + 4 * (int64_t)B * B;
-    if (tr == 0) return 0.0;
-    return __ddiv_rn(2.0 * (double)det, __dadd_rn((double)tr, __dsqrt_rn((double)dd)));
+    const double a = (double)A, b = (double)B, c = (double)C;
+    const double det = a * c - b * b;
+    const double tr = a + c;
+    const double dm = a - c;
+    const double disc = dm * dm + 4.0 * (b * b);
+    if (tr == 0.0) return 0.0;
+    return __ddiv_rn(2.0 * det, __dadd_rn(tr, __dsqrt_rn(disc)));
+}
+
+// FP32 estimate of the same score, relative error below 5e-7 (each of the roughly ten rounded
+// steps contributes at most one or two units of 2^-24); 0 exactly when det == 0.
+__device__ __forceinline__ float approx_key(int32_t A, int32_t B, int32_t C)
+{
+    const double a = (double)A, b = (double)B, c = (double)C;
+    const double det = a * c - b * b;
+    if (!(det > 0.0)) return 0.0f;
+    const double dm = a - c;
+    const double disc = dm * dm + 4.0 * (b * b);
+    const float sf = __builtin_amdgcn_sqrtf((float)disc);
+    return 2.0f * (float)det * __builtin_amdgcn_rcpf((float)(a + c) + sf);
+}
+
+// half-width of the band inside which two FP32 estimates are compared exactly
+constexpr float KEY_BAND = 1e-5f;
+
+__device__ __forceinline__ void box_tensor(const int16_t (*gxs)[GTW], const int16_t (*gys)[GTW], int r, int c, int32_t& A,
+                                           int32_t& B, int32_t& C)
+{
+    A = B = C = 0;
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            const int32_t gx = gxs[r + dy][c + dx], gy = gys[r + dy][c + dx];
+            A += gx * gx;
+            B += gx * gy;
+            C += gy * gy;
+        }
 }
 
 __global__ __launch_bounds__(256) void corner_response_kernel(const uint8_t* __restrict__ frames, int64_t frame_stride,
                                                               int W, int H, int pitch, int mx, int my,
+                                                              int n_items, int tiles_x, int tiles_y, int by_xcd,
                                                               int istride, const int32_t* gate, int gate_min,
                                                               uint8_t* ws, int64_t item_bytes)
 {
-    const int item = blockIdx.z;
+    int item, tile;
+    if (!vs::xcd_map(blockIdx.x, n_items, tiles_x * tiles_y, by_xcd != 0, item, tile)) return;
     if (gated_off(gate, gate_min, (int64_t)item * istride)) return;
-    __shared__ uint8_t pix[PT][PT + 2];
-    __shared__ int16_t gxs[GT][GT];
-    __shared__ int16_t gys[GT][GT];
-    __shared__ double lam[LT][LT + 1];
+    __shared__ uint8_t pix[PTH][PTW + 2];
+    __shared__ int16_t gxs[GTH][GTW];
+    __shared__ int16_t gys[GTH][GTW];
+    __shared__ float lam[LTH][LTW + 1];       // FP32 score estimates; -1 outside the ROI
     __shared__ uint32_t wave_cnt[4];
     __shared__ uint64_t wave_max[4];
     __shared__ uint32_t block_base;
 
     const uint8_t* img = frames + item * frame_stride;
     const int rx0 = mx, ry0 = my, rx1 = W - mx, ry1 = H - my;
-    const int tx0 = rx0 + blockIdx.x * RT, ty0 = ry0 + blockIdx.y * RT;
+    const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
+    const int tx0 = rx0 + txi * RTW, ty0 = ry0 + tyi * RTH;
     const int tid = threadIdx.x;
 
     // pixels needed by in-ROI scores lie in [rx0-2, rx1+2) x [ry0-2, ry1+2), inside the image
-    for (int k = tid; k < PT * PT; k += 256) {
-        const int r = k / PT, c = k - r * PT;
+    for (int k = tid; k < PTH * PTW; k += 256) {
+        const int r = k / PTW, c = k - r * PTW;
         const int x = tx0 - 3 + c, y = ty0 - 3 + r;
         uint8_t v = 0;
         if (x >= rx0 - 2 && x < rx1 + 2 && y >= ry0 - 2 && y < ry1 + 2) v = img[(int64_t)y * pitch + x];
         pix[r][c] = v;
     }
     __syncthreads();
-    for (int k = tid; k < GT * GT; k += 256) {
-        const int r = k / GT, c = k - r * GT;     // gradient at pixel-tile (r + 1, c + 1)
+    for (int k = tid; k < GTH * GTW; k += 256) {
+        const int r = k / GTW, c = k - r * GTW;   // gradient at pixel-tile (r + 1, c + 1)
         const int pr = r + 1, pc = c + 1;
         const int gx = (pix[pr - 1][pc + 1] - pix[pr - 1][pc - 1]) + 2 * (pix[pr][pc + 1] - pix[pr][pc - 1]) +
                        (pix[pr + 1][pc + 1] - pix[pr + 1][pc - 1]);
@@ -119,54 +162,65 @@ __global__ __launch_bounds__(256) void corner_response_kernel(const uint8_t* __r
         gys[r][c] = (int16_t)gy;
     }
     __syncthreads();
-    for (int k = tid; k < LT * LT; k += 256) {
-        const int r = k / LT, c = k - r * LT;     // score at gradient-tile (r + 1, c + 1)
+    for (int k = tid; k < LTH * LTW; k += 256) {
+        const int r = k / LTW, c = k - r * LTW;   // score at gradient-tile (r + 1, c + 1)
         const int x = tx0 - 1 + c, y = ty0 - 1 + r;
-        double v = -1.0;                           // outside the ROI: ignored by the NMS
+        float v = -1.0f;                           // outside the ROI: ignored by the NMS
         if (x >= rx0 && x < rx1 && y >= ry0 && y < ry1) {
-            int32_t A = 0, B = 0, C = 0;
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                for (int dx = 0; dx < 3; ++dx) {
-                    const int32_t gx = gxs[r + dy][c + dx], gy = gys[r + dy][c + dx];
-                    A += gx * gx;
-                    B += gx * gy;
-                    C += gy * gy;
-                }
-            v = min_eig_key(A, B, C);
+            int32_t A, B, C;
+            box_tensor(gxs, gys, r, c, A, B, C);
+            v = approx_key(A, B, C);
         }
         lam[r][c] = v;
     }
     __syncthreads();
 
-    // 3x3 NMS: every thread owns 4 pixels of the tile (one row, 4 consecutive columns)
-    const int pr = tid >> 3, pc0 = (tid & 7) * 4;
+    // 3x3 NMS on the estimates; comparisons inside the band are redone with exact keys. Thread t
+    // owns tile row t / 16 and columns (t % 16) + 16 q, so neighbouring lanes read neighbouring
+    // words of the score tile.
+    const int pr = tid >> 4, pcol = tid & 15;
     uint32_t mine = 0;
     uint64_t my_max = 0;
-    uint32_t my_idx[4];
-    uint64_t my_key[4];
+    uint32_t my_idx[PER_T];
+    uint64_t my_key[PER_T];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int c = pc0 + q;
+    for (int q = 0; q < PER_T; ++q) {
+        const int c = pcol + 16 * q;
         const int x = tx0 + c, y = ty0 + pr;
-        const double v = lam[pr + 1][c + 1];
-        if (x >= rx1 || y >= ry1 || !(v > 0.0)) continue;
-        const uint64_t vb = (uint64_t)__double_as_longlong(v);
-        my_max = vb > my_max ? vb : my_max;
-        bool is_max = true;
+        const float v = lam[pr + 1][c + 1];
+        if (x >= rx1 || y >= ry1 || !(v > 0.0f)) continue;
+        const float hi = v * (1.0f + KEY_BAND), lo = v * (1.0f - KEY_BAND);
+        bool beaten = false;
+        uint32_t close = 0;                        // neighbours whose estimate is inside the band
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx)
-                if (lam[pr + dy][c + dx] > v) is_max = false;
-        if (is_max) {
-            my_key[mine] = vb;
-            my_idx[mine] = (uint32_t)(y * W + x);
-            ++mine;
+            for (int dx = 0; dx < 3; ++dx) {
+                if (dy == 1 && dx == 1) continue;
+                const float u = lam[pr + dy][c + dx];
+                if (u > hi) beaten = true;
+                else if (u >= lo) close |= 1u << (dy * 3 + dx);
+            }
+        if (beaten) continue;
+        int32_t A, B, C;
+        box_tensor(gxs, gys, pr + 1, c + 1, A, B, C);
+        const double key = exact_key(A, B, C);
+        while (close) {
+            const int bit = __ffs(close) - 1;
+            close &= close - 1;
+            const int dy = bit / 3, dx = bit - dy * 3;
+            box_tensor(gxs, gys, pr + dy, c + dx, A, B, C);
+            if (exact_key(A, B, C) > key) beaten = true;
         }
+        if (beaten) continue;
+        const uint64_t kb = (uint64_t)__double_as_longlong(key);
+        my_max = kb > my_max ? kb : my_max;
+        my_key[mine] = kb;
+        my_idx[mine] = (uint32_t)(y * W + x);
+        ++mine;
     }
-    // block exclusive scan of the per-thread counts, and the block max
+    // block exclusive scan of the per-thread counts, and the block max (the maximum score of the
+    // ROI is always a local maximum, so the maximum over survivors is the ROI maximum)
     const int lane = tid & 63, wv = tid >> 6;
     uint32_t incl = mine;
 #pragma unroll
@@ -483,9 +537,12 @@ extern "C" int vs_detect_corners(const uint8_t* frames, int64_t frame_stride, in
     int e = vs::check_launch("vs_detect_corners(init)");
     if (e) return e;
     const int rw = width - 2 * p->roi_mx, rh = height - 2 * p->roi_my;
-    dim3 grid((rw + RT - 1) / RT, (rh + RT - 1) / RT, n);
-    corner_response_kernel<<<grid, 256, 0, s>>>(frames, frame_stride, width, height, pitch, p->roi_mx, p->roi_my,
-                                                istride, gate, gate_min, w8, ib);
+    const int tiles_x = (rw + RTW - 1) / RTW, tiles_y = (rh + RTH - 1) / RTH;
+    const bool by_xcd = n >= VS_XCD_MIN_ITEMS;
+    const int64_t nblk = vs::xcd_grid(n, tiles_x * tiles_y, by_xcd);
+    corner_response_kernel<<<(unsigned)nblk, 256, 0, s>>>(frames, frame_stride, width, height, pitch, p->roi_mx,
+                                                          p->roi_my, n, tiles_x, tiles_y, by_xcd, istride, gate,
+                                                          gate_min, w8, ib);
     e = vs::check_launch("vs_detect_corners(response)");
     if (e) return e;
     corner_select_kernel<<<n, 1024, 0, s>>>(w8, ib, width, height, istride, gate, gate_min, p->max_corners, p->quality,

@@ -12,7 +12,8 @@
 //     px = (ar x - ai y) + br,  py = (ai x + ar y) + bi,  d2 = dx dx + dy dy
 // with floating-point contraction disabled, so inlier decisions are bit-reproducible.
 // Kernel 2 (fit_resolve): walks the pairs of the call in order through the dwell-block state
-// machine and writes the chosen model's parameters, info and inlier flags.
+// machine. Kernel 3 (fit_emit): one workgroup per pair writes the chosen model's parameters,
+// info and inlier flags.
 #include <cmath>
 
 #include "vs_common.hpp"
@@ -342,21 +343,28 @@ __global__ __launch_bounds__(NT) void fit_pair_kernel(const float* __restrict__ 
     }
 }
 
+// Runs the dwell-block state machine over the pairs of the call in order (one thread, on
+// per-pair fields staged in LDS) and records each pair's choice in its workspace record.
 __global__ __launch_bounds__(NT) void fit_resolve_kernel(int n, int capacity, FitArgs a, int64_t pair_index0,
-                                                         vs_fit_state* state, const uint8_t* ws,
-                                                         double* __restrict__ params, vs_fit_info* __restrict__ info,
-                                                         uint8_t* __restrict__ inliers)
+                                                         vs_fit_state* state, uint8_t* ws)
 {
-    __shared__ int8_t choice[1024];
-    __shared__ int8_t decided[1024];
+    __shared__ int8_t skipped[1024];
+    __shared__ double er[1024], es[1024];
+    __shared__ int8_t choice[1024], decided[1024];
     const int t = threadIdx.x;
-    // the state machine runs in chunks of 1024 pairs, in order
+    vs_fit_state st;
+    if (t == 0) st = *state;
     for (int c0 = 0; c0 < n; c0 += 1024) {
         const int c1 = min(n, c0 + 1024);
+        for (int i = c0 + t; i < c1; i += NT) {
+            const PairRec* rec = reinterpret_cast<const PairRec*>(ws + i * rec_bytes(capacity));
+            skipped[i - c0] = (int8_t)rec->skipped;
+            er[i - c0] = rec->m[VS_RIGID].err;
+            es[i - c0] = rec->m[VS_SIMILARITY].err;
+        }
+        __syncthreads();
         if (t == 0) {
-            vs_fit_state st = *state;
             for (int i = c0; i < c1; ++i) {
-                const PairRec* rec = reinterpret_cast<const PairRec*>(ws + i * rec_bytes(capacity));
                 const int64_t pair = pair_index0 + i;
                 const int64_t block = pair / (a.dwell > 0 ? a.dwell : 1);
                 if (st.block != block) {
@@ -364,11 +372,11 @@ __global__ __launch_bounds__(NT) void fit_resolve_kernel(int n, int capacity, Fi
                     st.decided = 0;
                 }
                 int ch, dh = 0;
-                if (rec->skipped) {
+                if (skipped[i - c0]) {
                     ch = -1 - ((a.model == VS_HYBRID) ? st.model : a.model);   // identity, reported model
                 } else if (a.model == VS_HYBRID) {
                     if (!st.decided) {
-                        st.model = (rec->m[VS_RIGID].err < rec->m[VS_SIMILARITY].err) ? VS_RIGID : VS_SIMILARITY;
+                        st.model = (er[i - c0] < es[i - c0]) ? VS_RIGID : VS_SIMILARITY;
                         st.decided = 1;
                         dh = 1;
                     }
@@ -379,44 +387,53 @@ __global__ __launch_bounds__(NT) void fit_resolve_kernel(int n, int capacity, Fi
                 choice[i - c0] = (int8_t)ch;
                 decided[i - c0] = (int8_t)dh;
             }
-            *state = st;
         }
         __syncthreads();
         for (int i = c0 + t; i < c1; i += NT) {
-            const PairRec* rec = reinterpret_cast<const PairRec*>(ws + i * rec_bytes(capacity));
-            const int ch = choice[i - c0];
-            vs_fit_info f;
-            f.n_valid = rec->n_valid;
-            f.skipped = rec->skipped;
-            f.decided_here = decided[i - c0];
-            f.pad = 0;
-            f.err_rigid = __longlong_as_double(0x7ff8000000000000ll);
-            f.err_sim = f.err_rigid;
-            double* po = params + 4 * (int64_t)i;
-            if (ch < 0) {
-                f.model = -1 - ch;
-                f.n_inliers = 0;
-                po[0] = 1.0; po[1] = 0.0; po[2] = 0.0; po[3] = 0.0;
-            } else {
-                f.model = ch;
-                f.n_inliers = rec->m[ch].n_inl;
-                for (int k = 0; k < 4; ++k) po[k] = rec->m[ch].p[k];
-                if (f.decided_here) {
-                    f.err_rigid = rec->m[VS_RIGID].err;
-                    f.err_sim = rec->m[VS_SIMILARITY].err;
-                }
-            }
-            info[i] = f;
-        }
-        if (inliers) {
-            for (int i = c0; i < c1; ++i) {
-                const int ch = choice[i - c0];
-                const uint8_t* mk = ws + i * rec_bytes(capacity) + 256 + (ch < 0 ? 0 : ch) * cap_aligned(capacity);
-                uint8_t* o = inliers + (int64_t)i * capacity;
-                for (int k = t; k < capacity; k += NT) o[k] = ch < 0 ? 0 : mk[k];
-            }
+            PairRec* rec = reinterpret_cast<PairRec*>(ws + i * rec_bytes(capacity));
+            rec->pad[0] = choice[i - c0];
+            rec->pad[1] = decided[i - c0];
         }
         __syncthreads();
+    }
+    if (t == 0) *state = st;
+}
+
+// One workgroup per pair: writes the chosen model's parameters, info record and inlier flags.
+__global__ __launch_bounds__(NT) void fit_emit_kernel(int capacity, const uint8_t* ws, double* __restrict__ params,
+                                                      vs_fit_info* __restrict__ info, uint8_t* __restrict__ inliers)
+{
+    const int i = blockIdx.x, t = threadIdx.x;
+    const PairRec* rec = reinterpret_cast<const PairRec*>(ws + i * rec_bytes(capacity));
+    const int ch = rec->pad[0];
+    if (t == 0) {
+        vs_fit_info f;
+        f.n_valid = rec->n_valid;
+        f.skipped = rec->skipped;
+        f.decided_here = rec->pad[1];
+        f.pad = 0;
+        f.err_rigid = __longlong_as_double(0x7ff8000000000000ll);
+        f.err_sim = f.err_rigid;
+        double* po = params + 4 * (int64_t)i;
+        if (ch < 0) {
+            f.model = -1 - ch;
+            f.n_inliers = 0;
+            po[0] = 1.0; po[1] = 0.0; po[2] = 0.0; po[3] = 0.0;
+        } else {
+            f.model = ch;
+            f.n_inliers = rec->m[ch].n_inl;
+            for (int k = 0; k < 4; ++k) po[k] = rec->m[ch].p[k];
+            if (f.decided_here) {
+                f.err_rigid = rec->m[VS_RIGID].err;
+                f.err_sim = rec->m[VS_SIMILARITY].err;
+            }
+        }
+        info[i] = f;
+    }
+    if (inliers) {
+        const uint8_t* mk = ws + i * rec_bytes(capacity) + 256 + (ch < 0 ? 0 : ch) * cap_aligned(capacity);
+        uint8_t* o = inliers + (int64_t)i * capacity;
+        for (int k = t; k < capacity; k += NT) o[k] = ch < 0 ? 0 : mk[k];
     }
 }
 
@@ -475,6 +492,9 @@ extern "C" int vs_fit_similarity(const float* src, const float* dst, const uint8
     fit_pair_kernel<<<n, NT, 0, s>>>(src, dst, valid, capacity, a, pair_index0, w8);
     int e = vs::check_launch("vs_fit_similarity(pairs)");
     if (e) return e;
-    fit_resolve_kernel<<<1, NT, 0, s>>>(n, capacity, a, pair_index0, state, w8, params, info, inliers);
-    return vs::check_launch("vs_fit_similarity(resolve)");
+    fit_resolve_kernel<<<1, NT, 0, s>>>(n, capacity, a, pair_index0, state, w8);
+    e = vs::check_launch("vs_fit_similarity(resolve)");
+    if (e) return e;
+    fit_emit_kernel<<<n, NT, 0, s>>>(capacity, w8, params, info, inliers);
+    return vs::check_launch("vs_fit_similarity(emit)");
 }

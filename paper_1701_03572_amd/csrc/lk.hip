@@ -1,42 +1,46 @@
-// track_lk: pyramidal Lucas-Kanade with the forward-backward check, one wave64 per point slot.
+// track_lk: pyramidal Lucas-Kanade with the forward-backward check, one wave64 (one workgroup)
+// per point slot.
 //
 // Lane layout for a (2h+1)^2 window: the window's 2h+1 columns are spread over the lanes and the
 // rows over G = 64 / (2h+1) lane groups, each group owning R = ceil((2h+1) / G) consecutive rows
-// (h = 10: 21 columns x 3 groups of 7 rows = 63 lanes). Every sample of the window shares one
-// fractional offset, so a lane reads its (R+3) x 4 pixel block once per level, keeps I, dI/dx,
-// dI/dy of its R samples in registers, and per iteration reads an (R+1) x 2 block of the next
-// image. The three tensor sums and the two residual sums are wave butterfly reductions, whose
-// totals are bit-identical in every lane, so the iteration control is wave-uniform.
+// (h = 10: 21 columns x 3 groups of 7 rows = 63 lanes). Samples outside the window get zero
+// gradient weight, so every lane runs the same branch-free loops. All samples of a window share
+// one fractional offset, so per level a lane reads its (R+3) x 4 pixel block once (buffer loads
+// with 32-bit offsets, edge-clamped), interpolates each row horizontally first and derives I,
+// dI/dx, dI/dy of its R samples into registers. Each Gauss-Newton iteration needs the lane's
+// (R+1) x 2 next-frame block; it stays in registers while the iterate's integer position is
+// unchanged and is reloaded when it moves. The three tensor sums and the two residual sums are
+// DPP row reductions plus four lane reads, giving every lane the same total, so the iteration
+// control is wave-uniform. One wave per workgroup lets every point retire independently.
 #include "vs_common.hpp"
 
 namespace {
 
+constexpr uint32_t RSRC_WORD3 = 0x00020000;   // raw (untyped) buffer access on gfx9-family parts
+
 struct Img {
-    const uint8_t* p;
+    __amdgpu_buffer_rsrc_t rs;
     int w, h, pitch;
 };
 
 __device__ __forceinline__ Img level_img(const uint8_t* frame, const uint8_t* pyr, const vs::LevelDesc& d, int l)
 {
     Img im;
-    im.p = (l == 0) ? frame : pyr + d.off[l];
+    const uint8_t* p = (l == 0) ? frame : pyr + d.off[l];
     im.w = d.w[l];
     im.h = d.h[l];
     im.pitch = d.pitch[l];
+    // loads past the level's bytes would return 0; clamped coordinates never get there
+    im.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(p), (short)0, im.pitch * im.h, RSRC_WORD3);
     return im;
 }
 
-__device__ __forceinline__ float px(const Img& im, int x, int y)
+__device__ __forceinline__ float ld(const Img& im, int off)
 {
-    x = vs::clampi(x, 0, im.w - 1);
-    y = vs::clampi(y, 0, im.h - 1);
-    return (float)im.p[(int64_t)y * im.pitch + x];
+    return (float)__builtin_amdgcn_raw_buffer_load_b8(im.rs, off, 0, 0);
 }
 
-__device__ __forceinline__ float bil(float a, float b, float v00, float v10, float v01, float v11)
-{
-    return (1.0f - b) * ((1.0f - a) * v00 + a * v10) + b * ((1.0f - a) * v01 + a * v11);
-}
+__device__ __forceinline__ float lerp(float u, float v, float t) { return fmaf(t, v - u, u); }
 
 // g11 g22 - g12^2 with Kahan's compensated 2x2 determinant (one fma recovers the product error)
 __device__ __forceinline__ float det2(float g11, float g22, float g12)
@@ -78,39 +82,40 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
         const float a = cx - fx, b = cy - fy;
         const int ix = (int)fx + qx, iy = (int)fy + qy0;
 
+        // ---- window set-up: rows iy-1 .. iy+RMAX+1, columns ix-1 .. ix+2 of the previous frame
+        int col[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) col[t] = vs::clampi(ix - 1 + t, 0, A.w - 1);
+        float H1[4], Dd[4];             // sliding rows: horizontal lerp at the sample column, and
+                                        // the horizontal central difference lerped the same way
+        auto row_terms = [&](int r, float& h1, float& dd) {
+            const int base = (int)__umul24((unsigned)vs::clampi(iy - 1 + r, 0, A.h - 1), (unsigned)A.pitch);
+            const float p0 = ld(A, base + col[0]), p1 = ld(A, base + col[1]);
+            const float p2 = ld(A, base + col[2]), p3 = ld(A, base + col[3]);
+            h1 = lerp(p1, p2, a);
+            dd = lerp(p2, p3, a) - lerp(p0, p1, a);
+        };
+        row_terms(0, H1[0], Dd[0]);
+        row_terms(1, H1[1], Dd[1]);
+        row_terms(2, H1[2], Dd[2]);
         float I[RMAX], Ix[RMAX], Iy[RMAX];
         float g11 = 0.f, g12 = 0.f, g22 = 0.f;
-        {
-            // rows iy-1 .. iy+nrows+1, columns ix-1 .. ix+2
-            float p0[4], p1[4], p2[4], p3[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                p0[t] = px(A, ix - 1 + t, iy - 1);
-                p1[t] = px(A, ix - 1 + t, iy);
-                p2[t] = px(A, ix - 1 + t, iy + 1);
-            }
-#pragma unroll
-            for (int k = 0; k < RMAX; ++k) {
-                if (k < nrows) {
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) p3[t] = px(A, ix - 1 + t, iy + k + 2);
-                    // p0: row k-1, p1: row k, p2: row k+1, p3: row k+2 (relative to iy)
-                    I[k] = bil(a, b, p1[1], p1[2], p2[1], p2[2]);
-                    Ix[k] = 0.5f * bil(a, b, p1[2] - p1[0], p1[3] - p1[1], p2[2] - p2[0], p2[3] - p2[1]);
-                    Iy[k] = 0.5f * bil(a, b, p2[1] - p0[1], p2[2] - p0[2], p3[1] - p1[1], p3[2] - p1[2]);
-                    g11 += Ix[k] * Ix[k];
-                    g12 += Ix[k] * Iy[k];
-                    g22 += Iy[k] * Iy[k];
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) { p0[t] = p1[t]; p1[t] = p2[t]; p2[t] = p3[t]; }
-                } else {
-                    I[k] = Ix[k] = Iy[k] = 0.f;
-                }
-            }
+        for (int k = 0; k < RMAX; ++k) {
+            row_terms(k + 3, H1[3], Dd[3]);
+            // sample row k sits between sliding rows 1 and 2
+            const float wgt = k < nrows ? 0.5f : 0.0f;   // zero weight outside the window
+            I[k] = lerp(H1[1], H1[2], b);
+            Ix[k] = wgt * lerp(Dd[1], Dd[2], b);
+            Iy[k] = wgt * lerp(H1[2] - H1[0], H1[3] - H1[1], b);
+            g11 = fmaf(Ix[k], Ix[k], g11);
+            g12 = fmaf(Ix[k], Iy[k], g12);
+            g22 = fmaf(Iy[k], Iy[k], g22);
+            H1[0] = H1[1]; H1[1] = H1[2]; H1[2] = H1[3];
+            Dd[0] = Dd[1]; Dd[1] = Dd[2]; Dd[2] = Dd[3];
         }
-        g11 = vs::wave_sum(g11);
-        g12 = vs::wave_sum(g12);
-        g22 = vs::wave_sum(g22);
+        vs::wave_total2(g11, g12);
+        g22 = vs::wave_total(g22);
         ++n_setup;
         const float tr = g11 + g22;
         const float s = sqrtf((g11 - g22) * (g11 - g22) + 4.0f * g12 * g12);
@@ -121,30 +126,36 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
         if (!(lmin / (float)c.nwin >= c.min_eig)) {
             if (l == 0) ok = false;
         } else {
-            const float inv = 1.0f / det;
+            const float inv = __builtin_amdgcn_rcpf(det);
+            int cjx = 0x7fffffff, cjy = 0;                // cached integer position of the next block
+            float qa[RMAX + 1], qd[RMAX + 1];             // next-frame column jx and (jx + 1) - jx
             for (int it = 0; it < c.max_iter; ++it) {
                 const float pxx = cx + gx + nux, pyy = cy + gy + nuy;
                 const float jfx = floorf(pxx), jfy = floorf(pyy);
                 const float ja = pxx - jfx, jb = pyy - jfy;
-                const int jx = (int)jfx + qx, jy = (int)jfy + qy0;
-                float b1 = 0.f, b2 = 0.f;
-                if (nrows > 0) {
-                    float q0a = px(B, jx, jy), q0b = px(B, jx + 1, jy);
+                const int jx = (int)jfx, jy = (int)jfy;
+                if (jx != cjx || jy != cjy) {
+                    cjx = jx;
+                    cjy = jy;
+                    const int c0 = vs::clampi(jx + qx, 0, B.w - 1), c1 = vs::clampi(jx + qx + 1, 0, B.w - 1);
 #pragma unroll
-                    for (int k = 0; k < RMAX; ++k) {
-                        if (k < nrows) {
-                            const float q1a = px(B, jx, jy + k + 1), q1b = px(B, jx + 1, jy + k + 1);
-                            const float J = bil(ja, jb, q0a, q0b, q1a, q1b);
-                            const float dlt = I[k] - J;
-                            b1 += dlt * Ix[k];
-                            b2 += dlt * Iy[k];
-                            q0a = q1a;
-                            q0b = q1b;
-                        }
+                    for (int k = 0; k <= RMAX; ++k) {
+                        const int base = (int)__umul24((unsigned)vs::clampi(jy + qy0 + k, 0, B.h - 1), (unsigned)B.pitch);
+                        qa[k] = ld(B, base + c0);
+                        qd[k] = ld(B, base + c1) - qa[k];
                     }
                 }
-                b1 = vs::wave_sum(b1);
-                b2 = vs::wave_sum(b2);
+                float b1 = 0.f, b2 = 0.f;
+                float h0 = fmaf(ja, qd[0], qa[0]);
+#pragma unroll
+                for (int k = 0; k < RMAX; ++k) {
+                    const float h1 = fmaf(ja, qd[k + 1], qa[k + 1]);
+                    const float dlt = I[k] - lerp(h0, h1, jb);
+                    b1 = fmaf(dlt, Ix[k], b1);
+                    b2 = fmaf(dlt, Iy[k], b2);
+                    h0 = h1;
+                }
+                vs::wave_total2(b1, b2);
                 const float ex = (g22 * b1 - g12 * b2) * inv;
                 const float ey = (g11 * b2 - g12 * b1) * inv;
                 nux += ex;
@@ -166,20 +177,19 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
 }
 
 template <int RMAX>
-__global__ __launch_bounds__(256) void lk_kernel(const uint8_t* __restrict__ prev_frames,
-                                                 const uint8_t* __restrict__ prev_pyrs,
-                                                 const uint8_t* __restrict__ next_frames,
-                                                 const uint8_t* __restrict__ next_pyrs, int64_t frame_stride,
-                                                 int64_t pyr_stride, int istride, vs::LevelDesc d,
-                                                 const float* xy_prev, const uint8_t* alive_prev, int capacity,
-                                                 LKConst c, int fb, float fb_thresh, float* xy_next, uint8_t* status,
-                                                 float* fb_err, int32_t* n_valid, float* xy_chain,
-                                                 uint8_t* alive_chain, unsigned long long* work)
+__global__ __launch_bounds__(64) void lk_kernel(const uint8_t* __restrict__ prev_frames,
+                                                const uint8_t* __restrict__ prev_pyrs,
+                                                const uint8_t* __restrict__ next_frames,
+                                                const uint8_t* __restrict__ next_pyrs, int64_t frame_stride,
+                                                int64_t pyr_stride, int istride, vs::LevelDesc d, const float* xy_prev,
+                                                const uint8_t* alive_prev, int capacity, LKConst c, int fb,
+                                                float fb_thresh, float* xy_next, uint8_t* status, float* fb_err,
+                                                int32_t* n_valid, float* xy_chain, uint8_t* alive_chain,
+                                                unsigned long long* work)
 {
-    const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int slot = blockIdx.x;
     const int item = blockIdx.y;
-    if (slot >= capacity) return;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x;
     const int64_t rec = (int64_t)item * istride;
     const int64_t k = rec * capacity + slot;
     const float ux = xy_prev[2 * k], uy = xy_prev[2 * k + 1];
@@ -229,12 +239,12 @@ __global__ void zero_counters(int32_t* p, int n, int istride, unsigned long long
 
 extern "C" int vs_track_lk(const uint8_t* prev_frames, const uint8_t* prev_pyrs, const uint8_t* next_frames,
                            const uint8_t* next_pyrs, int64_t frame_stride, int64_t pyr_stride, int32_t n,
-                           int32_t istride, const vs_pyramid* layout, const float* xy_prev, const uint8_t* alive_prev, int32_t capacity,
-                           const vs_lk_params* p, float* xy_next, uint8_t* status, float* fb_err, int32_t* n_valid,
-                           float* xy_chain, uint8_t* alive_chain, uint64_t* work, void* stream)
+                           int32_t istride, const vs_pyramid* layout, const float* xy_prev, const uint8_t* alive_prev,
+                           int32_t capacity, const vs_lk_params* p, float* xy_next, uint8_t* status, float* fb_err,
+                           int32_t* n_valid, float* xy_chain, uint8_t* alive_chain, uint64_t* work, void* stream)
 {
     if (!layout || !p) return vs::set_error(VS_ERR_INVALID, "vs_track_lk: null argument");
-    if (n < 0 || capacity < 0 || istride < 1) return vs::set_error(VS_ERR_INVALID, "vs_track_lk: negative count");
+    if (n < 0 || capacity < 0 || istride < 1) return vs::set_error(VS_ERR_INVALID, "vs_track_lk: bad count or stride");
     if (n == 0 || capacity == 0) return VS_OK;
     if (!prev_frames || !next_frames || !xy_prev || !xy_next || !status)
         return vs::set_error(VS_ERR_INVALID, "vs_track_lk: null argument");
@@ -247,6 +257,8 @@ extern "C" int vs_track_lk(const uint8_t* prev_frames, const uint8_t* prev_pyrs,
     if (p->max_iter < 1 || !(p->eps >= 0.f) || !(p->min_eig >= 0.f) || !(p->fb_thresh >= 0.f))
         return vs::set_error(VS_ERR_INVALID, "vs_track_lk: bad parameters");
     if (n > 65535) return vs::set_error(VS_ERR_INVALID, "vs_track_lk: more than 65535 items");
+    if ((int64_t)layout->pitch[0] * layout->height[0] >= ((int64_t)1 << 31))
+        return vs::set_error(VS_ERR_UNSUPPORTED, "vs_track_lk: frame larger than 2 GiB");
     LKConst c;
     c.hw = p->win_half;
     c.cols = 2 * c.hw + 1;
@@ -264,14 +276,14 @@ extern "C" int vs_track_lk(const uint8_t* prev_frames, const uint8_t* prev_pyrs,
         if (e) return e;
     }
     const vs::LevelDesc d = vs::level_desc(*layout);
-    dim3 grid((capacity + 3) / 4, n);
+    dim3 grid(capacity, n);
     if (c.rows <= 7)
-        lk_kernel<7><<<grid, 256, 0, s>>>(prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride,
+        lk_kernel<7><<<grid, 64, 0, s>>>(prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride,
+                                         istride, d, xy_prev, alive_prev, capacity, c, p->fb, p->fb_thresh, xy_next,
+                                         status, fb_err, n_valid, xy_chain, alive_chain, wk);
+    else
+        lk_kernel<16><<<grid, 64, 0, s>>>(prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride,
                                           istride, d, xy_prev, alive_prev, capacity, c, p->fb, p->fb_thresh, xy_next,
                                           status, fb_err, n_valid, xy_chain, alive_chain, wk);
-    else
-        lk_kernel<16><<<grid, 256, 0, s>>>(prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride,
-                                           istride, d, xy_prev, alive_prev, capacity, c, p->fb, p->fb_thresh, xy_next,
-                                           status, fb_err, n_valid, xy_chain, alive_chain, wk);
     return vs::check_launch("vs_track_lk");
 }

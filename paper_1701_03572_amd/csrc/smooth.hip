@@ -46,12 +46,13 @@ struct SmoothArgs {
     double ratio, crop, cx, cy;
 };
 
-__device__ void emit_frame(const TrajState* s, const SmoothArgs& a, int64_t j, int64_t last_known, double* M)
+__device__ void emit_frame(const double (*ring)[4], const double (*kq)[4], const SmoothArgs& a, int64_t j,
+                           int64_t last_known, double* M)
 {
     double q[4];
-    const double* P = s->ring[j % VS_TRAJ_RING];
+    const double* P = ring[j % VS_TRAJ_RING];
     if (a.mode == VS_SMOOTH_KALMAN) {
-        for (int c = 0; c < 4; ++c) q[c] = s->kq[j % VS_TRAJ_RING][c];
+        for (int c = 0; c < 4; ++c) q[c] = kq[j % VS_TRAJ_RING][c];
     } else {
         const int64_t lo = (a.mode == VS_SMOOTH_CENTERED) ? (j - a.radius > 0 ? j - a.radius : 0)
                                                           : (j - 2 * a.radius > 0 ? j - 2 * a.radius : 0);
@@ -59,7 +60,7 @@ __device__ void emit_frame(const TrajState* s, const SmoothArgs& a, int64_t j, i
         hi = hi < last_known ? hi : last_known;
         for (int c = 0; c < 4; ++c) {
             double sum = 0.0;
-            for (int64_t i = lo; i <= hi; ++i) sum += s->ring[i % VS_TRAJ_RING][c];
+            for (int64_t i = lo; i <= hi; ++i) sum += ring[i % VS_TRAJ_RING][c];
             q[c] = sum / (double)(hi - lo + 1);
         }
     }
@@ -79,11 +80,25 @@ __global__ __launch_bounds__(256) void smooth_kernel(const double* __restrict__ 
                                                      TrajState* s, double* __restrict__ mats, int mats_cap,
                                                      int32_t* n_emitted, int64_t* first_frame)
 {
+    // the ring (and Kalman outputs) live in LDS during the call; the per-pair parameter
+    // conversions run in parallel, only the 4 running sums are sequential (one thread each)
+    __shared__ double ring[VS_TRAJ_RING][4];
+    __shared__ double kq[VS_TRAJ_RING][4];
+    __shared__ double dlt[VS_TRAJ_RING][4];
     __shared__ int64_t s_known, s_emitted, s_first;
     __shared__ int s_count;
     const int t = threadIdx.x;
-    const int window = (a.mode == VS_SMOOTH_KALMAN) ? 0 : (a.mode == VS_SMOOTH_CENTERED ? 2 * a.radius : 2 * a.radius);
+    const int window = (a.mode == VS_SMOOTH_KALMAN) ? 0 : 2 * a.radius;
     const int chunk = VS_TRAJ_RING - window - 1;
+    for (int i = t; i < VS_TRAJ_RING * 4; i += 256) {
+        (&ring[0][0])[i] = (&s->ring[0][0])[i];
+        (&kq[0][0])[i] = (&s->kq[0][0])[i];
+    }
+    double kx = 0.0, kS = 0.0;
+    if (t < 4) {
+        kx = s->kx[t];
+        kS = s->kS[t];
+    }
     if (t == 0) {
         s_known = s->known;
         s_emitted = s->emitted;
@@ -94,31 +109,35 @@ __global__ __launch_bounds__(256) void smooth_kernel(const double* __restrict__ 
     int consumed = 0;
     while (true) {
         const int take = (n_new - consumed) < chunk ? (n_new - consumed) : chunk;
-        if (t == 0) {
-            int64_t known = s_known;
+        for (int k = t; k < take; k += 256) {
+            const double* q = pairs + 4 * (int64_t)(consumed + k);
+            dlt[k][0] = q[2];
+            dlt[k][1] = q[3];
+            dlt[k][2] = atan2(q[1], q[0]);
+            dlt[k][3] = log(sqrt(q[0] * q[0] + q[1] * q[1]));
+        }
+        __syncthreads();
+        const int64_t known0 = s_known;
+        if (t < 4) {
+            // P_j = P_{j-1} + d_{j-1} for parameter t, in order
+            double p = ring[(known0 - 1) % VS_TRAJ_RING][t];
             for (int k = 0; k < take; ++k) {
-                const double* q = pairs + 4 * (int64_t)(consumed + k);
-                const double d[4] = {q[2], q[3], atan2(q[1], q[0]), log(sqrt(q[0] * q[0] + q[1] * q[1]))};
-                const double* prev = s->ring[(known - 1) % VS_TRAJ_RING];
-                double* cur = s->ring[known % VS_TRAJ_RING];
-                for (int c = 0; c < 4; ++c) cur[c] = prev[c] + d[c];
+                const int64_t j = known0 + k;
+                p = p + dlt[k][t];
+                ring[j % VS_TRAJ_RING][t] = p;
                 if (a.mode == VS_SMOOTH_KALMAN) {
-                    for (int c = 0; c < 4; ++c) {
-                        const double Sm = s->kS[c] + a.ratio;
-                        const double K = Sm / (Sm + 1.0);
-                        s->kx[c] = s->kx[c] + K * (cur[c] - s->kx[c]);
-                        s->kS[c] = (1.0 - K) * Sm;
-                        s->kq[known % VS_TRAJ_RING][c] = s->kx[c];
-                    }
+                    const double Sm = kS + a.ratio;
+                    const double K = Sm / (Sm + 1.0);
+                    kx = kx + K * (p - kx);
+                    kS = (1.0 - K) * Sm;
+                    kq[j % VS_TRAJ_RING][t] = kx;
                 }
-                ++known;
             }
-            s_known = known;
         }
         consumed += take;
         __syncthreads();
         const bool last = consumed >= n_new;
-        const int64_t known = s_known;
+        const int64_t known = known0 + take;
         int64_t end;     // frames [s_emitted, end) are emitted now
         if (a.mode == VS_SMOOTH_CENTERED) end = (last && eos) ? known : known - a.radius;
         else end = known;
@@ -126,15 +145,24 @@ __global__ __launch_bounds__(256) void smooth_kernel(const double* __restrict__ 
         const int64_t e0 = s_emitted;
         for (int64_t j = e0 + t; j < end; j += 256) {
             const int64_t k = j - s_first;
-            if (k < mats_cap) emit_frame(s, a, j, known - 1, mats + 6 * k);
+            if (k < mats_cap) emit_frame(ring, kq, a, j, known - 1, mats + 6 * k);
         }
         __syncthreads();
         if (t == 0) {
+            s_known = known;
             s_count += (int)(end - e0);
             s_emitted = end;
         }
         __syncthreads();
         if (last) break;
+    }
+    for (int i = t; i < VS_TRAJ_RING * 4; i += 256) {
+        (&s->ring[0][0])[i] = (&ring[0][0])[i];
+        (&s->kq[0][0])[i] = (&kq[0][0])[i];
+    }
+    if (t < 4) {
+        s->kx[t] = kx;
+        s->kS[t] = kS;
     }
     if (t == 0) {
         s->known = s_known;
