@@ -1,77 +1,163 @@
 // warp_frame: inverse-mapped bilinear warp of 8-bit frames, all items of a batch in one launch.
 //
-// A 256-thread workgroup covers a 256 x 16 output tile; each thread produces 4 consecutive pixels
-// in each of 4 rows, stored as one 32-bit word per row when the row allows it. The 2x3 matrix is
-// inverted in binary64 once per thread; per-pixel source coordinates are FP32. The source map is
-// affine, so the extreme source coordinates of a thread's 4x4 block are at its corners: when all
-// four corners map inside [0, W-2] x [0, H-2], every 2x2 source footprint of the block is inside
-// the frame and the thread takes a path without per-pixel border tests, reading through a buffer
-// descriptor with 32-bit offsets. Other threads take the general path (border value outside).
+// A 256-thread workgroup covers a 256 x 16 output tile; each thread produces 4 consecutive pixels in
+// each of 4 rows, stored as one 32-bit word per row when the row allows it. The 2x3 matrix is
+// inverted in binary64; per-pixel source coordinates are FP32, relative to the tile's source box.
+//
+// Source box: the map is affine and is evaluated in a form that is monotone in x and in y, so the
+// extreme source coordinates of the tile's in-frame pixels are at its four corners. The box (plus a
+// one-pixel margin) is staged in LDS with 16-byte loads; bytes outside the frame are staged as the
+// border value, which gives every tap exactly the border semantics of a per-tap test. Each pixel then
+// reads its four taps as single bytes from LDS (a fixed row pitch makes the lower taps immediate
+// offsets). Tiles whose box does not fit the LDS buffer (strong zoom-out or rotation) take a
+// per-pixel path that reads the frame directly.
 // Values are rounded half up: floor(v + 0.5) is an integer in [0, 255], packed exactly.
 #include "vs_common.hpp"
 
 namespace {
 
-constexpr int TW = 256, TH = 16;
+constexpr int TW = 256;                 // tile width: 64 lanes x 4 pixels
+constexpr int RPT = 4;                  // rows per thread
+constexpr int TH = 4 * RPT;             // 4 waves stacked vertically
+constexpr int LW = 288;                 // LDS row pitch: 18 chunks of 16 bytes
+constexpr int NCH = LW / 16;
+constexpr int MAXR = 48;                // staged rows at most
+constexpr int NLD = (NCH * MAXR + 255) / 256;
+constexpr float BIG = 1048576.0f;       // boxes beyond +-2^20 take the direct path
 constexpr uint32_t RSRC_WORD3 = 0x00020000;   // raw (untyped) buffer access on gfx9-family parts
 
 __device__ __forceinline__ float lerp(float u, float v, float t) { return fmaf(t, v - u, u); }
 
-__global__ __launch_bounds__(256) void warp_kernel(const uint8_t* __restrict__ src, int64_t src_stride, int W, int H,
-                                                   int src_pitch, const double* __restrict__ mats, int64_t mat_stride,
-                                                   uint8_t* __restrict__ dst, int64_t dst_stride, int dst_pitch,
-                                                   int border, int tiles_x, int tiles_y)
+struct Box {
+    float mnx, mxx, mny, mxy;
+    bool finite;   // every corner coordinate is a number inside (-2^20, 2^20)
+};
+
+// source-coordinate box of the pixels [ox, xe] x [oy, ye] under x' = f00 x + f01 y + c0, y' = f10 x + f11 y + c1,
+// evaluated exactly as the per-pixel loop evaluates it
+__device__ __forceinline__ Box corner_box(float f00, float f01, float c0, float f10, float f11, float c1, int ox, int xe,
+                                          int oy, int ye)
 {
+    Box b{INFINITY, -INFINITY, INFINITY, -INFINITY, true};
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx) {
+            const float fx = (float)(cx ? xe : ox), fy = (float)(cy ? ye : oy);
+            const float sx = fmaf(f00, fx, fmaf(f01, fy, c0));
+            const float sy = fmaf(f10, fx, fmaf(f11, fy, c1));
+            b.mnx = fminf(b.mnx, sx);
+            b.mxx = fmaxf(b.mxx, sx);
+            b.mny = fminf(b.mny, sy);
+            b.mxy = fmaxf(b.mxy, sy);
+            b.finite = b.finite && sx > -BIG && sx < BIG && sy > -BIG && sy < BIG;   // false for NaN
+        }
+    return b;
+}
+
+__global__ __launch_bounds__(256, 8) void warp_kernel(const uint8_t* __restrict__ src, int64_t src_stride, int W, int H,
+                                                      int src_pitch, const double* __restrict__ mats, int64_t mat_stride,
+                                                      uint8_t* __restrict__ dst, int64_t dst_stride, int dst_pitch,
+                                                      int border, int tiles_x, int tiles_y, int vec_ok)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t tin[MAXR * LW];
     const int tiles = tiles_x * tiles_y;
     const int item = blockIdx.x / tiles, tile = blockIdx.x - item * tiles;
     const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-    const int x4 = tx * TW + (threadIdx.x & 63) * 4;
-    const int ybase = ty * TH + (threadIdx.x >> 6) * 4;
-    if (x4 >= W || ybase >= H) return;
+    const int ox = tx * TW, oy = ty * TH;
+    const int x4 = ox + (threadIdx.x & 63) * 4;
+    const int ybase = oy + (threadIdx.x >> 6) * RPT;
     const double* M = mats + item * mat_stride;
     const double rdet = 1.0 / (M[0] * M[4] - M[1] * M[3]);
     const double i00 = M[4] * rdet, i01 = -M[1] * rdet, i10 = -M[3] * rdet, i11 = M[0] * rdet;
     const double i02 = -(i00 * M[2] + i01 * M[5]);
     const double i12 = -(i10 * M[2] + i11 * M[5]);
-    const float f00 = (float)i00, f01 = (float)i01, f02 = (float)i02;
-    const float f10 = (float)i10, f11 = (float)i11, f12 = (float)i12;
+    const float f00 = (float)i00, f01 = (float)i01;
+    const float f10 = (float)i10, f11 = (float)i11;
     const uint8_t* s = src + item * src_stride;
-    const int nx = W - x4 < 4 ? W - x4 : 4;
-    const int ny = H - ybase < 4 ? H - ybase : 4;
+    const int nx = W - x4 < 4 ? W - x4 : 4;      // <= 0 for threads past the right edge
+    const int ny = H - ybase < RPT ? H - ybase : RPT;
     uint8_t* drow = dst + item * dst_stride + (int64_t)ybase * dst_pitch + x4;
     const bool word_store = nx == 4 && (reinterpret_cast<uintptr_t>(drow) & 3) == 0 && (dst_pitch & 3) == 0;
+    const int xe = (ox + TW < W ? ox + TW : W) - 1, ye = (oy + TH < H ? oy + TH : H) - 1;
 
-    // corners of the block in source coordinates
-    bool inside = true;
-#pragma unroll
-    for (int cy = 0; cy < 2; ++cy)
-#pragma unroll
-        for (int cx = 0; cx < 2; ++cx) {
-            const float fx = (float)(x4 + 3 * cx), fy = (float)(ybase + 3 * cy);
-            const float sx = fmaf(f00, fx, fmaf(f01, fy, f02));
-            const float sy = fmaf(f10, fx, fmaf(f11, fy, f12));
-            inside = inside && sx >= 0.0f && sy >= 0.0f && sx < (float)(W - 1) && sy < (float)(H - 1);
-        }
-
-    if (inside) {
+    // box in absolute coordinates -> origin of the staged box (one pixel of margin on the low sides)
+    const Box ab = corner_box(f00, f01, (float)i02, f10, f11, (float)i12, ox, xe, oy, ye);
+    bool staged = ab.finite;
+    int a0 = 0, by0 = 0, nr = 0;
+    float g02 = 0.0f, g12 = 0.0f;
+    if (staged) {
+        a0 = ((int)floorf(ab.mnx) - 1) & ~15;
+        by0 = (int)floorf(ab.mny) - 1;
+        g02 = (float)(i02 - (double)a0);
+        g12 = (float)(i12 - (double)by0);
+        // the same box in the relative coordinates the pixels use: every tap must be inside the buffer
+        const Box rb = corner_box(f00, f01, g02, f10, f11, g12, ox, xe, oy, ye);
+        nr = (int)floorf(rb.mxy) + 2;
+        staged = rb.finite && rb.mnx >= 0.0f && rb.mny >= 0.0f && rb.mxx < (float)(LW - 1) && nr <= MAXR;
+    }
+    if (staged) {
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(s), (short)0,
                                                                             src_pitch * H, RSRC_WORD3);
+        using V4 = __attribute__((ext_vector_type(4))) unsigned int;
+        const uint32_t bw = (uint32_t)border * 0x01010101u;
+        const int total = NCH * nr;
+        V4 v[NLD];
+#pragma unroll
+        for (int j = 0; j < NLD; ++j) {
+            const int k = threadIdx.x + 256 * j;
+            v[j] = V4{bw, bw, bw, bw};
+            if (k < total) {
+                const int r = k / NCH, c = k - r * NCH;
+                const int gy = by0 + r, gx = a0 + 16 * c;
+                const bool row_in = gy >= 0 && gy < H;
+                if (vec_ok && row_in && gx >= 0 && gx + 16 <= W) {
+                    v[j] = __builtin_bit_cast(V4, __builtin_amdgcn_raw_buffer_load_b128(rs, gy * src_pitch + gx, 0, 0));
+                } else if (row_in && gx < W && gx + 16 > 0) {
+                    // chunk straddling the left or right edge (or an unaligned source): byte by byte
+                    uint32_t wd[4] = {bw, bw, bw, bw};
+                    for (int e = 0; e < 16; ++e) {
+                        const int x = gx + e;
+                        if (x >= 0 && x < W) {
+                            const uint32_t byte = s[(int64_t)gy * src_pitch + x];
+                            const int sh = 8 * (e & 3);
+                            wd[e >> 2] = (wd[e >> 2] & ~(0xffu << sh)) | (byte << sh);
+                        }
+                    }
+                    v[j] = V4{wd[0], wd[1], wd[2], wd[3]};
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NLD; ++j) {
+            const int k = threadIdx.x + 256 * j;
+            if (k < total) {
+                const int r = k / NCH, c = k - r * NCH;
+                *reinterpret_cast<V4*>(&tin[r * LW + 16 * c]) = v[j];
+            }
+        }
+        __syncthreads();
+        if (nx <= 0 || ny <= 0) return;
+        float fxq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fxq[q] = (float)(x4 + (q < nx ? q : nx - 1));   // past-the-edge columns repeat
         for (int r = 0; r < ny; ++r) {
             const float fy = (float)(ybase + r);
-            const float bx = fmaf(f01, fy, f02), by = fmaf(f11, fy, f12);
+            const float bx = fmaf(f01, fy, g02), by = fmaf(f11, fy, g12);
             uint32_t packed = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const float fx = (float)(x4 + q);
-                const float sx = fmaf(f00, fx, bx);
-                const float sy = fmaf(f10, fx, by);
+                const float sx = fmaf(f00, fxq[q], bx);
+                const float sy = fmaf(f10, fxq[q], by);
                 const float x0 = floorf(sx), y0 = floorf(sy);
                 const float a = sx - x0, b = sy - y0;
-                const int off = (int)__umul24((unsigned)(int)y0, (unsigned)src_pitch) + (int)x0;
-                const float v00 = (float)__builtin_amdgcn_raw_buffer_load_b8(rs, off, 0, 0);
-                const float v10 = (float)__builtin_amdgcn_raw_buffer_load_b8(rs, off + 1, 0, 0);
-                const float v01 = (float)__builtin_amdgcn_raw_buffer_load_b8(rs, off + src_pitch, 0, 0);
-                const float v11 = (float)__builtin_amdgcn_raw_buffer_load_b8(rs, off + src_pitch + 1, 0, 0);
+                const int p = (int)fmaf(y0, (float)LW, x0);   // exact: < 2^24
+                int p1 = p + 1;
+                // an empty asm hides that p1 = p + 1, so the taps stay single-byte reads (a merged 16-bit
+                // read at an odd address takes the LDS unaligned path)
+                asm volatile("" : "+v"(p1));
+                const float v00 = (float)tin[p], v10 = (float)tin[p1];
+                const float v01 = (float)tin[p + LW], v11 = (float)tin[p1 + LW];
                 const float v = lerp(lerp(v00, v10, a), lerp(v01, v11, a), b);
                 packed = __builtin_amdgcn_cvt_pk_u8_f32(floorf(v + 0.5f), q, packed);
             }
@@ -82,12 +168,13 @@ __global__ __launch_bounds__(256) void warp_kernel(const uint8_t* __restrict__ s
         }
         return;
     }
+    if (nx <= 0 || ny <= 0) return;
 
+    const float f02 = (float)i02, f12 = (float)i12;
     const float bord = (float)border;
     const float fW = (float)W, fH = (float)H;
     for (int r = 0; r < ny; ++r) {
-        const int y = ybase + r;
-        const float fy = (float)y;
+        const float fy = (float)(ybase + r);
         const float bx = fmaf(f01, fy, f02), by = fmaf(f11, fy, f12);
         uint32_t packed = 0;
 #pragma unroll
@@ -137,8 +224,11 @@ extern "C" int vs_warp_frame(const uint8_t* src, int64_t src_stride, int32_t wid
     const int tiles_x = (width + TW - 1) / TW, tiles_y = (height + TH - 1) / TH;
     const int64_t nblk = (int64_t)n * tiles_x * tiles_y;
     if (nblk > 0x7fffffff) return vs::set_error(VS_ERR_INVALID, "vs_warp_frame: grid too large");
+    // 16-byte staging loads need 16-byte aligned rows in every item
+    const int vec_ok = (src_pitch % 16 == 0) && (reinterpret_cast<uintptr_t>(src) % 16 == 0) &&
+                       (n == 1 || src_stride % 16 == 0);
     warp_kernel<<<(unsigned)nblk, 256, 0, vs::as_stream(stream)>>>(src, src_stride, width, height, src_pitch, mats,
                                                                    mat_stride, dst, dst_stride, dst_pitch, border,
-                                                                   tiles_x, tiles_y);
+                                                                   tiles_x, tiles_y, vec_ok);
     return vs::check_launch("vs_warp_frame");
 }

@@ -66,3 +66,20 @@ def test_degenerate_matrix_gives_border():
     assert (out.ravel()[1:] == 9).all()            # only the origin maps inside the source
     out = gpu_warp(img, [float("nan")] * 6, border=7)
     assert (out == 7).all()
+
+
+@pytest.mark.parametrize("theta,scale", [(0.087, 1.0), (0.5, 1.0), (0.0, 0.5), (-0.03, 1.04)])
+def test_rotation_and_zoom_both_paths(theta, scale):
+    """Moderate rotations stage the tile's source box in LDS; strong rotation or zoom-out give boxes
+    too large for it and take the direct per-pixel path. Both must match the oracle, borders included."""
+    say("warp rotation/zoom", theta, scale)
+    w, h = 640, 480
+    img = synth.smooth_random_image(w, h, 11, sigma=1.3)
+    a, b = scale * math.cos(theta), scale * math.sin(theta)
+    cx, cy = w / 2, h / 2
+    M = [a, -b, cx - a * cx + b * cy + 3.25, b, a, cy - b * cx - a * cy - 2.5]
+    for border in (0, 131):
+        g, o = gpu_warp(img, M, border).astype(int), O.warp(img, M, border).astype(int)
+        d = np.abs(g - o)
+        assert d.max() <= 1
+        assert (d > 0).mean() < 1e-3
