@@ -1,12 +1,12 @@
 // build_pyramid: binomial (1 4 6 4 1)^2 / 256 reduce, one level per launch, all items of the batch
 // in the same launch.
 //
-// Each 256-thread workgroup produces a 128 x 32 tile of level l+1. It stages the (2*128+3) x
-// (2*32+3) input window of level l in LDS: interior tiles with aligned 32-bit loads (rows of 66
-// words), tiles touching the border byte by byte with reflect-101 indices. It then filters rows
-// into 16-bit horizontal sums (exact: <= 16 * 255), then columns into 32-bit totals, and rounds
-// once. The result is bit-identical to the direct 5x5 integer sum. The tiles of one frame run on
-// one XCD when the batch has at least 8 frames, so tile halos are shared in that XCD's L2.
+// Each 256-thread workgroup produces a 128 x 32 tile of level l+1 from the (2*128+3) x (2*32+3) input
+// window of level l, staged in LDS with 16-byte loads from reflect-101 rows (16-byte chunks that cross
+// the left or right frame edge: byte by byte with reflect-101 columns). Each thread then produces a 4 x 4 block: for each of its 11 input rows
+// it forms the 4 horizontal 5-tap sums with byte dot products on aligned LDS words, and it filters
+// those sums vertically in registers. All sums are exact integers (<= 65280); one rounding at the end
+// makes the result bit-identical to the direct 5 x 5 integer sum.
 #include "vs_common.hpp"
 
 namespace {
@@ -15,8 +15,12 @@ constexpr int TW = 128;                // output tile width
 constexpr int TH = 32;                 // output tile height
 constexpr int IW = 2 * TW + 3;         // input columns 2*x0-2 .. 2*(x0+TW-1)+2
 constexpr int IH = 2 * TH + 3;
-constexpr int NWORD = (IW + 3) / 4 + 1;   // 32-bit words covering IW bytes from a 4-aligned start
-constexpr int IWP = 4 * NWORD;            // LDS row pitch (bytes)
+constexpr int OFF = 14;                // LDS byte offset of input column 2*x0-2 (16-byte aligned staging)
+constexpr int LP = 288;                // LDS row pitch: OFF + IW rounded up to 16
+constexpr int NCH = LP / 16;
+constexpr int NLD = (NCH * IH + 255) / 256;
+constexpr uint32_t RSRC_WORD3 = 0x00020000;   // raw (untyped) buffer access on gfx9-family parts
+constexpr uint32_t W1464 = 0x04060401u;       // byte weights 1, 4, 6, 4 (byte 0 first)
 
 __device__ __forceinline__ int refl101_clamped(int t, int n)
 {
@@ -28,10 +32,9 @@ __device__ __forceinline__ int refl101_clamped(int t, int n)
 __global__ __launch_bounds__(256) void pyr_down_kernel(const uint8_t* __restrict__ src, int64_t src_stride,
                                                         int src_pitch, int sw, int sh, uint8_t* __restrict__ dst,
                                                         int64_t dst_stride, int dst_pitch, int dw, int dh, int n_items,
-                                                        int tiles_x, int tiles_y, int by_xcd, int word_ok)
+                                                        int tiles_x, int tiles_y, int by_xcd, int vec_ok)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t tin[IH][IWP];
-    __shared__ uint16_t hsum[IH][TW];
+    __shared__ __attribute__((aligned(16))) uint8_t tin[IH * LP];
     int item, tile;
     if (!vs::xcd_map(blockIdx.x, n_items, tiles_x * tiles_y, by_xcd != 0, item, tile)) return;
     const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
@@ -40,38 +43,82 @@ __global__ __launch_bounds__(256) void pyr_down_kernel(const uint8_t* __restrict
     const int ox = tx * TW, oy = ty * TH;
     const int ix0 = 2 * ox - 2, iy0 = 2 * oy - 2;
     const int tid = threadIdx.x;
-    const int a0 = ix0 & ~3;                 // aligned start of the word path
-    int shift = 0;                           // byte offset of input column 0 inside an LDS row
-    const bool interior = word_ok && ix0 >= 0 && iy0 >= 0 && a0 + 4 * NWORD <= sw && iy0 + IH <= sh;
-    if (interior) {
-        shift = ix0 - a0;
-        for (int k = tid; k < IH * NWORD; k += 256) {
-            const int r = k / NWORD, w = k - r * NWORD;
-            const uint32_t v = *reinterpret_cast<const uint32_t*>(s + (int64_t)(iy0 + r) * src_pitch + a0 + 4 * w);
-            *reinterpret_cast<uint32_t*>(&tin[r][4 * w]) = v;
+    const int a0 = ix0 - OFF;                // global column of LDS byte 0 (may be negative)
+    {
+        using V4 = __attribute__((ext_vector_type(4))) unsigned int;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(s), (short)0,
+                                                                            src_pitch * sh, RSRC_WORD3);
+        // only input columns/rows that some output of the tile reads are staged: relative columns
+        // [0, need_c) and rows [0, need_r); at the frame edges these reach 2 past it (reflect-101)
+        const int need_c = 2 * min(TW, dw - ox) + 3, need_r = 2 * min(TH, dh - oy) + 3;
+        V4 v[NLD];
+#pragma unroll
+        for (int j = 0; j < NLD; ++j) {
+            const int k = tid + 256 * j;
+            const int r = k / NCH, c = k - r * NCH;
+            if (k < NCH * IH && r < need_r && 16 * c - OFF < need_c) {
+                const int gy = refl101_clamped(iy0 + r, sh);
+                const int gx = a0 + 16 * c;
+                if (vec_ok && gx >= 0 && gx + 16 <= sw) {
+                    v[j] = __builtin_bit_cast(V4, __builtin_amdgcn_raw_buffer_load_b128(rs, gy * src_pitch + gx, 0, 0));
+                } else {
+                    // chunk crossing the left or right frame edge (or an unaligned source): 16 independent
+                    // byte loads from reflect-101 columns, issued together
+                    uint32_t wd[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const uint32_t byte = __builtin_amdgcn_raw_buffer_load_b8(
+                            rs, gy * src_pitch + refl101_clamped(gx + e, sw), 0, 0);
+                        wd[e >> 2] |= byte << (8 * (e & 3));
+                    }
+                    v[j] = V4{wd[0], wd[1], wd[2], wd[3]};
+                }
+            }
         }
-    } else {
-        for (int k = tid; k < IH * IW; k += 256) {
-            const int r = k / IW, c = k - r * IW;
-            const int sy = refl101_clamped(iy0 + r, sh);
-            const int sx = refl101_clamped(ix0 + c, sw);
-            tin[r][c] = s[(int64_t)sy * src_pitch + sx];
+#pragma unroll
+        for (int j = 0; j < NLD; ++j) {
+            const int k = tid + 256 * j;
+            const int r = k / NCH, c = k - r * NCH;
+            if (k < NCH * IH && r < need_r && 16 * c - OFF < need_c)
+                *reinterpret_cast<V4*>(&tin[16 * k]) = v[j];   // row r, chunk c at r * LP + 16 c
         }
     }
     __syncthreads();
-    for (int k = tid; k < IH * TW; k += 256) {
-        const int r = k / TW, c = k - r * TW;
-        const uint8_t* row = &tin[r][2 * c + shift];
-        hsum[r][c] = (uint16_t)(row[0] + 4 * row[1] + 6 * row[2] + 4 * row[3] + row[4]);
+
+    const int g = tid & 31, rg = tid >> 5;     // 4 output columns 4g.., 4 output rows 4rg..
+    const int x = ox + 4 * g, y = oy + 4 * rg;
+    if (x >= dw || y >= dh) return;
+    // input columns (relative to 2*ox-2) 8g .. 8g+10 sit at LDS bytes OFF+8g ..; the words read start
+    // at OFF-2+8g (4-aligned) and hold relative columns 8g-2 .. 8g+13
+    const uint32_t* wrow = reinterpret_cast<const uint32_t*>(&tin[(8 * rg) * LP + OFF - 2 + 8 * g]);
+    uint32_t h[11][4];
+#pragma unroll
+    for (int j = 0; j < 11; ++j) {
+        const uint32_t* w = wrow + j * (LP / 4);
+        const uint32_t d0 = w[0], d1 = w[1], d2 = w[2], d3 = w[3];
+        // d0 = cols -2..1, d1 = 2..5, d2 = 6..9, d3 = 10..13 (relative to 8g)
+        const uint32_t a01 = __builtin_amdgcn_alignbyte(d1, d0, 2);   // cols 0..3
+        const uint32_t a12 = __builtin_amdgcn_alignbyte(d2, d1, 2);   // cols 4..7
+        h[j][0] = __builtin_amdgcn_udot4(d1, 0x00010000u, __builtin_amdgcn_udot4(a01, W1464, 0, false), false);
+        h[j][1] = __builtin_amdgcn_udot4(d2, 0x00000001u, __builtin_amdgcn_udot4(d1, W1464, 0, false), false);
+        h[j][2] = __builtin_amdgcn_udot4(d2, 0x00010000u, __builtin_amdgcn_udot4(a12, W1464, 0, false), false);
+        h[j][3] = __builtin_amdgcn_udot4(d3, 0x00000001u, __builtin_amdgcn_udot4(d2, W1464, 0, false), false);
     }
-    __syncthreads();
-    for (int k = tid; k < TH * TW; k += 256) {
-        const int r = k / TW, c = k - r * TW;
-        const int x = ox + c, y = oy + r;
-        if (x >= dw || y >= dh) continue;
-        const uint32_t v = hsum[2 * r][c] + 4u * hsum[2 * r + 1][c] + 6u * hsum[2 * r + 2][c] +
-                           4u * hsum[2 * r + 3][c] + hsum[2 * r + 4][c];
-        d[(int64_t)y * dst_pitch + x] = (uint8_t)((v + 128u) >> 8);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        if (y + m >= dh) break;
+        uint32_t packed = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t t = h[2 * m][c] + h[2 * m + 4][c] + 128u + 4u * (h[2 * m + 1][c] + h[2 * m + 3][c]) +
+                               6u * h[2 * m + 2][c];
+            packed |= (t >> 8) << (8 * c);
+        }
+        uint8_t* out = d + (int64_t)(y + m) * dst_pitch + x;
+        if (x + 4 <= dw && (dst_pitch & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 3) == 0)
+            *reinterpret_cast<uint32_t*>(out) = packed;
+        else
+            for (int c = 0; c < 4 && x + c < dw; ++c) out[c] = (uint8_t)(packed >> (8 * c));
     }
 }
 
@@ -88,6 +135,8 @@ extern "C" int vs_build_pyramid(const uint8_t* frames, int64_t frame_stride, uin
     if (n > 65535) return vs::set_error(VS_ERR_INVALID, "vs_build_pyramid: more than 65535 items");
     if (n > 1 && (frame_stride < (int64_t)layout->pitch[0] * layout->height[0] || pyr_stride < layout->bytes))
         return vs::set_error(VS_ERR_INVALID, "vs_build_pyramid: strides overlap items");
+    if ((int64_t)layout->pitch[0] * layout->height[0] >= ((int64_t)1 << 31))
+        return vs::set_error(VS_ERR_UNSUPPORTED, "vs_build_pyramid: frame larger than 2 GiB");
     hipStream_t s = vs::as_stream(stream);
     const bool by_xcd = n >= VS_XCD_MIN_ITEMS;
     for (int l = 1; l < layout->levels; ++l) {
@@ -96,13 +145,13 @@ extern "C" int vs_build_pyramid(const uint8_t* frames, int64_t frame_stride, uin
         const int spitch = layout->pitch[l - 1];
         const int dw = layout->width[l], dh = layout->height[l];
         const int tiles_x = (dw + TW - 1) / TW, tiles_y = (dh + TH - 1) / TH;
-        // 32-bit loads need 4-byte aligned rows in every item
-        const bool word_ok = (spitch % 4 == 0) && (reinterpret_cast<uintptr_t>(src) % 4 == 0) &&
-                             (n == 1 || sstride % 4 == 0);
+        // 16-byte staging loads need 16-byte aligned rows in every item
+        const bool vec_ok = (spitch % 16 == 0) && (reinterpret_cast<uintptr_t>(src) % 16 == 0) &&
+                            (n == 1 || sstride % 16 == 0);
         const int64_t nblk = vs::xcd_grid(n, tiles_x * tiles_y, by_xcd);
         pyr_down_kernel<<<(unsigned)nblk, 256, 0, s>>>(src, sstride, spitch, layout->width[l - 1],
                                                        layout->height[l - 1], pyrs + layout->offset[l], pyr_stride,
-                                                       layout->pitch[l], dw, dh, n, tiles_x, tiles_y, by_xcd, word_ok);
+                                                       layout->pitch[l], dw, dh, n, tiles_x, tiles_y, by_xcd, vec_ok);
         int e = vs::check_launch("vs_build_pyramid");
         if (e) return e;
     }
