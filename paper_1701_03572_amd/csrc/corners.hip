@@ -1,15 +1,22 @@
 // detect_corners: Shi-Tomasi response + 3x3 NMS over the ROI, then the ordered greedy top-K.
 //
-// Kernel 1 (corner_response): one 256-thread workgroup per 128x16 ROI tile stages the pixels with
-// a 3-pixel halo in LDS, forms Sobel gradients and 3x3 box sums of the tensor (exact int32), and
-// keeps the 3x3 local maxima inside the ROI. The NMS runs on an FP32 estimate of the score with
-// a bounded relative error; a comparison that falls inside the error band, and every survivor,
-// uses the exact binary64 score 2 det / (tr + sqrt(disc)) from exact det/tr/disc, so the result
-// is the exact-score NMS. Survivors are appended (block-compacted, one atomic per workgroup) to
-// the item's candidate list in the workspace; the item's maximum score is folded in with an
-// integer atomic max on the score's bit pattern (non-negative doubles order like their bits).
+// Kernel 1 (corner_response): each wave walks down a 240-column strip of the ROI, 60 output rows at a
+// time; lane i owns 4 columns. Per pixel row it forms, in registers, the Sobel terms (byte dot
+// products), the tensor products and their 3x3 box sums (exact int32), an FP32 estimate of the score
+// with a bounded relative error, and a separable 3x3 max of the estimates; neighbouring lanes' edge
+// columns arrive by DPP wave shifts. A pixel whose neighbours' estimates are all below its own by
+// more than the error band survives; one whose neighbours are above by more than the band is
+// dropped; a pixel inside the band survives flagged. Survivors are appended (one atomic per wave and
+// row) as their exact box-summed tensor (A, B, C) and pixel index.
 //
-// Kernel 2 (corner_select): one 1024-thread workgroup per item. Candidates below
+// Kernel 2 (corner_keys): one thread per appended survivor computes the exact binary64 score
+// 2 det / (tr + sqrt(disc)) from exact det/tr/disc; a flagged survivor is compared exactly against
+// its in-ROI neighbours, recomputed from the image. Survivors that remain are written, compacted, to
+// the item's candidate list, and the item's maximum score is folded in with an integer atomic max on
+// the score's bit pattern (non-negative doubles order like their bits). The result is exactly the
+// set of 3x3 maxima of the exact scores.
+//
+// Kernel 3 (corner_select): one 1024-thread workgroup per item. Candidates below
 // quality * max are dropped. The order is (score desc, y asc, x asc), i.e. the composite key
 // V = (bits(score) - bits(threshold)) * 2^32 + (2^32 - 1 - y * W - x) taken descending. Batches of
 // the next ~2048 keys are cut out by a most-significant-digit radix select (11-bit digits),
@@ -23,27 +30,26 @@ namespace {
 typedef unsigned __int128 u128;
 
 struct CandHeader {
-    uint32_t count;
-    uint32_t pad;
+    uint32_t count;        // candidates (exact 3x3 maxima) in the key/index lists
+    uint32_t raw_count;    // survivors appended by the response kernel
     uint64_t lmax_bits;
 };
 
 constexpr int64_t HDR = 256;
-constexpr int RTW = 128;        // response tile width (rows of ~one cache line)
-constexpr int RTH = 16;         // response tile height
-constexpr int PER_T = RTW * RTH / 256;   // pixels per thread in the NMS pass
-constexpr int PTW = RTW + 6, PTH = RTH + 6;   // pixel tile with 3-pixel halo
-constexpr int GTW = RTW + 4, GTH = RTH + 4;   // gradient tile (halo 2)
-constexpr int LTW = RTW + 2, LTH = RTH + 2;   // score tile (halo 1)
+constexpr int SW = 240;         // output columns per wave strip (lanes 1..62 of 64 x 4 columns)
+constexpr int SUP = 6;          // rows per unrolled super-step (period of the register rotation)
+constexpr int SR = 60;          // output rows per wave: the pipeline runs SR + 6 pixel rows
 constexpr int CAP = 4096;       // LDS batch capacity of the selection
 constexpr int BATCH = 2048;     // keys requested per batch
 constexpr int DIGIT = 11;
 constexpr int NBIN = 1 << DIGIT;
 
+// per item: header | keys (8 B each) | indices (4 B) | survivors (16 B: A, B, C, index | flag << 31);
+// every list has room for one entry per pixel
 __host__ __device__ inline int64_t per_item_bytes(int w, int h)
 {
     const int64_t c = (int64_t)w * h;
-    return (HDR + 8 * c + 4 * c + 255) & ~(int64_t)255;
+    return (HDR + 8 * c + 4 * c + 16 * c + 255) & ~(int64_t)255;
 }
 
 __device__ __forceinline__ CandHeader* hdr_of(uint8_t* ws, int64_t item_bytes, int item)
@@ -58,6 +64,10 @@ __device__ __forceinline__ uint32_t* idx_of(uint8_t* ws, int64_t item_bytes, int
 {
     return reinterpret_cast<uint32_t*>(ws + item * item_bytes + HDR + 8 * (int64_t)w * h);
 }
+__device__ __forceinline__ uint4* raw_of(uint8_t* ws, int64_t item_bytes, int item, int w, int h)
+{
+    return reinterpret_cast<uint4*>(ws + item * item_bytes + HDR + 12 * (int64_t)w * h);
+}
 
 __device__ __forceinline__ bool gated_off(const int32_t* gate, int gate_min, int64_t rec)
 {
@@ -71,6 +81,7 @@ __global__ void detect_init_kernel(uint8_t* ws, int64_t item_bytes, int n, int i
     if (i >= n || gated_off(gate, gate_min, (int64_t)i * istride)) return;
     CandHeader* h = hdr_of(ws, item_bytes, i);
     h->count = 0;
+    h->raw_count = 0;
     h->lmax_bits = 0;
 }
 
@@ -104,155 +115,285 @@ __device__ __forceinline__ float approx_key(int32_t A, int32_t B, int32_t C)
 // half-width of the band inside which two FP32 estimates are compared exactly
 constexpr float KEY_BAND = 1e-5f;
 
-__device__ __forceinline__ void box_tensor(const int16_t (*gxs)[GTW], const int16_t (*gys)[GTW], int r, int c, int32_t& A,
-                                           int32_t& B, int32_t& C)
+// exact box-summed Sobel tensor at (x, y) from the image (all pixels within 2 of (x, y) are read)
+__device__ void tensor_from_image(const uint8_t* img, int pitch, int x, int y, int32_t& A, int32_t& B, int32_t& C)
 {
     A = B = C = 0;
-#pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-            const int32_t gx = gxs[r + dy][c + dx], gy = gys[r + dy][c + dx];
+    for (int by = -1; by <= 1; ++by)
+        for (int bx = -1; bx <= 1; ++bx) {
+            const uint8_t* r0 = img + (int64_t)(y + by - 1) * pitch + (x + bx);
+            const uint8_t* r1 = r0 + pitch;
+            const uint8_t* r2 = r1 + pitch;
+            const int gx = (r0[1] - r0[-1]) + 2 * (r1[1] - r1[-1]) + (r2[1] - r2[-1]);
+            const int gy = (r2[-1] - r0[-1]) + 2 * (r2[0] - r0[0]) + (r2[1] - r0[1]);
             A += gx * gx;
             B += gx * gy;
             C += gy * gy;
         }
 }
 
-__global__ __launch_bounds__(256) void corner_response_kernel(const uint8_t* __restrict__ frames, int64_t frame_stride,
-                                                              int W, int H, int pitch, int mx, int my,
-                                                              int n_items, int tiles_x, int tiles_y, int by_xcd,
-                                                              int istride, const int32_t* gate, int gate_min,
-                                                              uint8_t* ws, int64_t item_bytes)
+constexpr int DPP_SHR = 0x138;   // wave_shr:1 -- lane i receives lane i-1
+constexpr int DPP_SHL = 0x130;   // wave_shl:1 -- lane i receives lane i+1
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v)
 {
-    int item, tile;
-    if (!vs::xcd_map(blockIdx.x, n_items, tiles_x * tiles_y, by_xcd != 0, item, tile)) return;
-    if (gated_off(gate, gate_min, (int64_t)item * istride)) return;
-    __shared__ uint8_t pix[PTH][PTW + 2];
-    __shared__ int16_t gxs[GTH][GTW];
-    __shared__ int16_t gys[GTH][GTW];
-    __shared__ float lam[LTH][LTW + 1];       // FP32 score estimates; -1 outside the ROI
-    __shared__ uint32_t wave_cnt[4];
-    __shared__ uint64_t wave_max[4];
-    __shared__ uint32_t block_base;
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
 
-    const uint8_t* img = frames + item * frame_stride;
-    const int rx0 = mx, ry0 = my, rx1 = W - mx, ry1 = H - my;
-    const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
-    const int tx0 = rx0 + txi * RTW, ty0 = ry0 + tyi * RTH;
-    const int tid = threadIdx.x;
+// Register state of one lane's 4 columns, indexed by pixel-row step modulo 3 (horizontal Sobel terms,
+// horizontal box sums of the products, 3x3 maxima of the estimates) or modulo 2 (box sums, estimates,
+// side maxima). All indices are compile-time constants after unrolling.
+struct RespState {
+    int dx[3][4], sy[3][4];
+    int ha[3][4], hb[3][4], hc[3][4];
+    int sa[2][4], sb[2][4], sc[2][4];
+    float sv[2][4], hm[3][4], sd[2][4];
+};
 
-    // pixels needed by in-ROI scores lie in [rx0-2, rx1+2) x [ry0-2, ry1+2), inside the image
-    for (int k = tid; k < PTH * PTW; k += 256) {
-        const int r = k / PTW, c = k - r * PTW;
-        const int x = tx0 - 3 + c, y = ty0 - 3 + r;
-        uint8_t v = 0;
-        if (x >= rx0 - 2 && x < rx1 + 2 && y >= ry0 - 2 && y < ry1 + 2) v = img[(int64_t)y * pitch + x];
-        pix[r][c] = v;
-    }
-    __syncthreads();
-    for (int k = tid; k < GTH * GTW; k += 256) {
-        const int r = k / GTW, c = k - r * GTW;   // gradient at pixel-tile (r + 1, c + 1)
-        const int pr = r + 1, pc = c + 1;
-        const int gx = (pix[pr - 1][pc + 1] - pix[pr - 1][pc - 1]) + 2 * (pix[pr][pc + 1] - pix[pr][pc - 1]) +
-                       (pix[pr + 1][pc + 1] - pix[pr + 1][pc - 1]);
-        const int gy = (pix[pr + 1][pc - 1] - pix[pr - 1][pc - 1]) + 2 * (pix[pr + 1][pc] - pix[pr - 1][pc]) +
-                       (pix[pr + 1][pc + 1] - pix[pr - 1][pc + 1]);
-        gxs[r][c] = (int16_t)gx;
-        gys[r][c] = (int16_t)gy;
-    }
-    __syncthreads();
-    for (int k = tid; k < LTH * LTW; k += 256) {
-        const int r = k / LTW, c = k - r * LTW;   // score at gradient-tile (r + 1, c + 1)
-        const int x = tx0 - 1 + c, y = ty0 - 1 + r;
-        float v = -1.0f;                           // outside the ROI: ignored by the NMS
-        if (x >= rx0 && x < rx1 && y >= ry0 && y < ry1) {
-            int32_t A, B, C;
-            box_tensor(gxs, gys, r, c, A, B, C);
-            v = approx_key(A, B, C);
+struct RespCtx {
+    int lane, xb, oy, oy_end;
+    int rx0, rx1, ry0, ry1;
+    int out_lo, out_hi;          // output columns of this strip
+    int W;
+    uint32_t* raw_count;
+    uint4* raw;
+};
+
+// One pixel-row step. T is the step number modulo SUP; GRAD/BOX/NMS switch the pipeline stages on.
+// Pixel row yp = oy - 3 + t; gradients for row yp - 1; box sums and estimates for row yp - 2; NMS
+// decisions for row yp - 3.
+template <int T, bool GRAD, bool BOX, bool NMS>
+__device__ __forceinline__ void resp_step(RespState& st, uint32_t P, int t, const RespCtx& cx)
+{
+    constexpr int i3 = T % 3, m3 = (T + 2) % 3, mm3 = (T + 1) % 3;   // t, t-1, t-2 (mod 3)
+    constexpr int i2 = T % 2, m2 = (T + 1) % 2;                       // t, t-1 (mod 2)
+    const uint32_t L = (uint32_t)dpp_i<DPP_SHR>((int)P), R = (uint32_t)dpp_i<DPP_SHL>((int)P);
+    // horizontal Sobel terms: (1,2,1) smoothing and central difference
+    st.sy[i3][0] = (int)__builtin_amdgcn_udot4(L, 0x01000000u, __builtin_amdgcn_udot4(P, 0x00000102u, 0, false), false);
+    st.sy[i3][1] = (int)__builtin_amdgcn_udot4(P, 0x00010201u, 0, false);
+    st.sy[i3][2] = (int)__builtin_amdgcn_udot4(P, 0x01020100u, 0, false);
+    st.sy[i3][3] = (int)__builtin_amdgcn_udot4(R, 0x00000001u, __builtin_amdgcn_udot4(P, 0x02010000u, 0, false), false);
+    const int b0 = (int)(P & 0xff), b1 = (int)((P >> 8) & 0xff), b2 = (int)((P >> 16) & 0xff), b3 = (int)(P >> 24);
+    st.dx[i3][0] = b1 - (int)(L >> 24);
+    st.dx[i3][1] = b2 - b0;
+    st.dx[i3][2] = b3 - b1;
+    st.dx[i3][3] = (int)(R & 0xff) - b2;
+    if constexpr (GRAD) {
+        int A[4], B[4], C[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int gx = st.dx[mm3][c] + 2 * st.dx[m3][c] + st.dx[i3][c];
+            const int gy = st.sy[i3][c] - st.sy[mm3][c];
+            A[c] = __mul24(gx, gx);
+            B[c] = __mul24(gx, gy);
+            C[c] = __mul24(gy, gy);
         }
-        lam[r][c] = v;
+        const int al = dpp_i<DPP_SHR>(A[3]), ar = dpp_i<DPP_SHL>(A[0]);
+        const int bl = dpp_i<DPP_SHR>(B[3]), br = dpp_i<DPP_SHL>(B[0]);
+        const int cl = dpp_i<DPP_SHR>(C[3]), cr = dpp_i<DPP_SHL>(C[0]);
+        st.ha[i3][0] = al + A[0] + A[1];
+        st.hb[i3][0] = bl + B[0] + B[1];
+        st.hc[i3][0] = cl + C[0] + C[1];
+#pragma unroll
+        for (int c = 1; c < 3; ++c) {
+            st.ha[i3][c] = A[c - 1] + A[c] + A[c + 1];
+            st.hb[i3][c] = B[c - 1] + B[c] + B[c + 1];
+            st.hc[i3][c] = C[c - 1] + C[c] + C[c + 1];
+        }
+        st.ha[i3][3] = A[2] + A[3] + ar;
+        st.hb[i3][3] = B[2] + B[3] + br;
+        st.hc[i3][3] = C[2] + C[3] + cr;
     }
-    __syncthreads();
-
-    // 3x3 NMS on the estimates; comparisons inside the band are redone with exact keys. Thread t
-    // owns tile row t / 16 and columns (t % 16) + 16 q, so neighbouring lanes read neighbouring
-    // words of the score tile.
-    const int pr = tid >> 4, pcol = tid & 15;
-    uint32_t mine = 0;
-    uint64_t my_max = 0;
-    uint32_t my_idx[PER_T];
-    uint64_t my_key[PER_T];
+    if constexpr (BOX) {
+        const int yb = cx.oy - 5 + t;
+        const bool row_in = yb >= cx.ry0 && yb < cx.ry1;
 #pragma unroll
-    for (int q = 0; q < PER_T; ++q) {
-        const int c = pcol + 16 * q;
-        const int x = tx0 + c, y = ty0 + pr;
-        const float v = lam[pr + 1][c + 1];
-        if (x >= rx1 || y >= ry1 || !(v > 0.0f)) continue;
-        const float hi = v * (1.0f + KEY_BAND), lo = v * (1.0f - KEY_BAND);
-        bool beaten = false;
-        uint32_t close = 0;                        // neighbours whose estimate is inside the band
+        for (int c = 0; c < 4; ++c) {
+            st.sa[i2][c] = st.ha[mm3][c] + st.ha[m3][c] + st.ha[i3][c];
+            st.sb[i2][c] = st.hb[mm3][c] + st.hb[m3][c] + st.hb[i3][c];
+            st.sc[i2][c] = st.hc[mm3][c] + st.hc[m3][c] + st.hc[i3][c];
+            const int x = cx.xb + c;
+            const bool in = row_in && x >= cx.rx0 && x < cx.rx1;
+            st.sv[i2][c] = in ? approx_key(st.sa[i2][c], st.sb[i2][c], st.sc[i2][c]) : -1.0f;   // -1: ignored
+        }
+        const float sl = dpp_f<DPP_SHR>(st.sv[i2][3]), sr = dpp_f<DPP_SHL>(st.sv[i2][0]);
+        st.hm[i3][0] = fmaxf(fmaxf(sl, st.sv[i2][0]), st.sv[i2][1]);
+        st.sd[i2][0] = fmaxf(sl, st.sv[i2][1]);
 #pragma unroll
-        for (int dy = 0; dy < 3; ++dy)
+        for (int c = 1; c < 3; ++c) {
+            st.hm[i3][c] = fmaxf(fmaxf(st.sv[i2][c - 1], st.sv[i2][c]), st.sv[i2][c + 1]);
+            st.sd[i2][c] = fmaxf(st.sv[i2][c - 1], st.sv[i2][c + 1]);
+        }
+        st.hm[i3][3] = fmaxf(fmaxf(st.sv[i2][2], st.sv[i2][3]), sr);
+        st.sd[i2][3] = fmaxf(st.sv[i2][2], sr);
+    }
+    if constexpr (NMS) {
+        const int yn = cx.oy - 6 + t;
+        const bool row_ok = yn < cx.oy_end;
+        bool surv[4], flag[4];
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                if (dy == 1 && dx == 1) continue;
-                const float u = lam[pr + dy][c + dx];
-                if (u > hi) beaten = true;
-                else if (u >= lo) close |= 1u << (dy * 3 + dx);
+        for (int c = 0; c < 4; ++c) {
+            const float v = st.sv[m2][c];
+            const float nmax = fmaxf(fmaxf(st.hm[mm3][c], st.hm[i3][c]), st.sd[m2][c]);
+            const int x = cx.xb + c;
+            const bool ok = row_ok && cx.lane >= 1 && cx.lane <= 62 && x >= cx.out_lo && x < cx.out_hi && v > 0.0f;
+            surv[c] = ok && !(nmax > v * (1.0f + KEY_BAND));
+            flag[c] = !(nmax < v * (1.0f - KEY_BAND));
+        }
+        uint64_t bal[4];
+        uint32_t tot = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            bal[c] = __ballot(surv[c]);
+            tot += (uint32_t)__popcll(bal[c]);
+        }
+        if (tot) {
+            uint32_t base = 0;
+            if (cx.lane == 0) base = atomicAdd(cx.raw_count, tot);
+            base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const uint32_t lo = (uint32_t)bal[c], hi = (uint32_t)(bal[c] >> 32);
+                const uint32_t pos = base + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+                if (surv[c]) {
+                    const uint32_t ix = (uint32_t)(yn * cx.W + cx.xb + c) | (flag[c] ? 0x80000000u : 0u);
+                    cx.raw[pos] = make_uint4((uint32_t)st.sa[m2][c], (uint32_t)st.sb[m2][c], (uint32_t)st.sc[m2][c], ix);
+                }
+                base += (uint32_t)__popcll(bal[c]);
             }
-        if (beaten) continue;
-        int32_t A, B, C;
-        box_tensor(gxs, gys, pr + 1, c + 1, A, B, C);
-        const double key = exact_key(A, B, C);
-        while (close) {
-            const int bit = __ffs(close) - 1;
-            close &= close - 1;
-            const int dy = bit / 3, dx = bit - dy * 3;
-            box_tensor(gxs, gys, pr + dy, c + dx, A, B, C);
-            if (exact_key(A, B, C) > key) beaten = true;
         }
-        if (beaten) continue;
-        const uint64_t kb = (uint64_t)__double_as_longlong(key);
-        my_max = kb > my_max ? kb : my_max;
-        my_key[mine] = kb;
-        my_idx[mine] = (uint32_t)(y * W + x);
-        ++mine;
     }
-    // block exclusive scan of the per-thread counts, and the block max (the maximum score of the
-    // ROI is always a local maximum, so the maximum over survivors is the ROI maximum)
-    const int lane = tid & 63, wv = tid >> 6;
-    uint32_t incl = mine;
+}
+
+__global__ __launch_bounds__(256) void corner_response_kernel(const uint8_t* __restrict__ frames, int64_t frame_stride,
+                                                              int W, int H, int pitch, int mx, int my, int n_items,
+                                                              int strips, int segs, int istride, const int32_t* gate,
+                                                              int gate_min, uint8_t* ws, int64_t item_bytes)
+{
+    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);   // one independent wave per (item, strip, segment)
+    const int per_item = strips * segs;
+    const int item = gw / per_item;
+    if (item >= n_items) return;
+    if (gated_off(gate, gate_min, (int64_t)item * istride)) return;
+    const int rem = gw - item * per_item;
+    const int seg = rem / strips, strip = rem - seg * strips;
+
+    RespCtx cx;
+    cx.lane = threadIdx.x & 63;
+    cx.W = W;
+    cx.rx0 = mx; cx.rx1 = W - mx; cx.ry0 = my; cx.ry1 = H - my;
+    cx.out_lo = mx + SW * strip;
+    cx.out_hi = min(cx.out_lo + SW, cx.rx1);
+    cx.xb = ((cx.out_lo - 4) & ~3) + 4 * cx.lane;   // lanes 1..62 cover [out_lo, out_lo + SW)
+    cx.oy = my + SR * seg;
+    cx.oy_end = min(cx.oy + SR, cx.ry1);
+    cx.raw_count = &hdr_of(ws, item_bytes, item)->raw_count;
+    cx.raw = raw_of(ws, item_bytes, item, W, H);
+
+    // pixel rows are read through a buffer descriptor: rows or columns past the image read as 0 and
+    // only feed estimates outside the ROI, which the NMS ignores
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t*>(frames + item * frame_stride), (short)0, pitch * H, 0x00020000);
+    auto load_row = [&](int yp) -> uint32_t {
+        return __builtin_amdgcn_raw_buffer_load_b32(rs, yp * pitch + cx.xb, 0, 0);
+    };
+
+    RespState st;
+    const int nsteps = (cx.oy_end - cx.oy) + 6;
+    const int nsup = (nsteps + SUP - 1) / SUP;
+    uint32_t P[SUP];
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t t = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += t;
-    }
-    uint64_t wmax = my_max;
+    for (int u = 0; u < SUP; ++u) P[u] = load_row(cx.oy - 3 + u);
+    uint32_t Q[SUP];
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const uint64_t t = __shfl_xor(wmax, m, 64);
-        wmax = t > wmax ? t : wmax;
+    for (int u = 0; u < SUP; ++u) Q[u] = load_row(cx.oy - 3 + SUP + u);
+    // warm-up super-step: rows t = 0..5 (no NMS output yet)
+    resp_step<0, false, false, false>(st, P[0], 0, cx);
+    resp_step<1, false, false, false>(st, P[1], 1, cx);
+    resp_step<2, true, false, false>(st, P[2], 2, cx);
+    resp_step<3, true, false, false>(st, P[3], 3, cx);
+    resp_step<4, true, true, false>(st, P[4], 4, cx);
+    resp_step<5, true, true, false>(st, P[5], 5, cx);
+    for (int sup = 1; sup < nsup; ++sup) {
+        const int t0 = SUP * sup;
+#pragma unroll
+        for (int u = 0; u < SUP; ++u) P[u] = Q[u];
+        if (sup + 1 < nsup) {
+#pragma unroll
+            for (int u = 0; u < SUP; ++u) Q[u] = load_row(cx.oy - 3 + t0 + SUP + u);
+        }
+        resp_step<0, true, true, true>(st, P[0], t0 + 0, cx);
+        resp_step<1, true, true, true>(st, P[1], t0 + 1, cx);
+        resp_step<2, true, true, true>(st, P[2], t0 + 2, cx);
+        resp_step<3, true, true, true>(st, P[3], t0 + 3, cx);
+        resp_step<4, true, true, true>(st, P[4], t0 + 4, cx);
+        resp_step<5, true, true, true>(st, P[5], t0 + 5, cx);
     }
-    if (lane == 63) wave_cnt[wv] = incl;
-    if (lane == 0) wave_max[wv] = wmax;
-    __syncthreads();
-    if (tid == 0) {
-        const uint32_t tot = wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
-        CandHeader* h = hdr_of(ws, item_bytes, item);
-        block_base = tot ? atomicAdd(&h->count, tot) : 0u;
-        uint64_t bm = wave_max[0];
-        for (int i = 1; i < 4; ++i) bm = wave_max[i] > bm ? wave_max[i] : bm;
-        if (bm) atomicMax((unsigned long long*)&h->lmax_bits, (unsigned long long)bm);
-    }
-    __syncthreads();
-    uint32_t base = block_base + incl - mine;
-    for (int i = 0; i < wv; ++i) base += wave_cnt[i];
+}
+
+// Exact scores of the survivors; flagged ones get the exact NMS against their in-ROI neighbours.
+__global__ __launch_bounds__(256) void corner_keys_kernel(const uint8_t* __restrict__ frames, int64_t frame_stride,
+                                                          int W, int H, int pitch, int mx, int my, int istride,
+                                                          const int32_t* gate, int gate_min, uint8_t* ws,
+                                                          int64_t item_bytes)
+{
+    const int item = blockIdx.y;
+    if (gated_off(gate, gate_min, (int64_t)item * istride)) return;
+    CandHeader* hd = hdr_of(ws, item_bytes, item);
+    const uint32_t nraw = hd->raw_count;
+    const uint4* raw = raw_of(ws, item_bytes, item, W, H);
     uint64_t* keys = keys_of(ws, item_bytes, item);
     uint32_t* idx = idx_of(ws, item_bytes, item, W, H);
-    for (uint32_t q = 0; q < mine; ++q) {
-        keys[base + q] = my_key[q];
-        idx[base + q] = my_idx[q];
+    const uint8_t* img = frames + item * frame_stride;
+    const int lane = threadIdx.x & 63;
+    const int rx0 = mx, rx1 = W - mx, ry0 = my, ry1 = H - my;
+    for (uint32_t b0 = blockIdx.x * 256u; b0 < nraw; b0 += gridDim.x * 256u) {
+        const uint32_t i = b0 + threadIdx.x;
+        bool keep = false;
+        uint64_t kb = 0;
+        uint32_t ix = 0;
+        if (i < nraw) {
+            const uint4 r = raw[i];
+            ix = r.w & 0x7FFFFFFFu;
+            const double key = exact_key((int32_t)r.x, (int32_t)r.y, (int32_t)r.z);
+            keep = key > 0.0;
+            if (keep && (r.w >> 31)) {
+                const int x = (int)(ix % (uint32_t)W), y = (int)(ix / (uint32_t)W);
+                for (int dy = -1; dy <= 1 && keep; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        const int nx = x + dx, ny = y + dy;
+                        if ((dx == 0 && dy == 0) || nx < rx0 || nx >= rx1 || ny < ry0 || ny >= ry1) continue;
+                        int32_t A, B, C;
+                        tensor_from_image(img, pitch, nx, ny, A, B, C);
+                        if (exact_key(A, B, C) > key) { keep = false; break; }
+                    }
+            }
+            kb = (uint64_t)__double_as_longlong(key);
+        }
+        const uint64_t bal = __ballot(keep);
+        if (bal) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&hd->count, (uint32_t)__popcll(bal));
+            base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+            const uint32_t pos = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            if (keep) {
+                keys[pos] = kb;
+                idx[pos] = ix;
+            }
+            uint64_t m = keep ? kb : 0;
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                const uint64_t t = __shfl_xor(m, o, 64);
+                m = t > m ? t : m;
+            }
+            if (lane == 0) atomicMax((unsigned long long*)&hd->lmax_bits, (unsigned long long)m);
+        }
     }
 }
 
@@ -524,7 +665,7 @@ extern "C" int vs_detect_corners(const uint8_t* frames, int64_t frame_stride, in
     if (n > 65535) return vs::set_error(VS_ERR_INVALID, "vs_detect_corners: more than 65535 items");
     if (n > 1 && frame_stride < (int64_t)pitch * height)
         return vs::set_error(VS_ERR_INVALID, "vs_detect_corners: frame stride overlaps items");
-    if ((int64_t)width * height >= (int64_t)1 << 32)
+    if ((int64_t)pitch * height >= (int64_t)1 << 31)
         return vs::set_error(VS_ERR_UNSUPPORTED, "vs_detect_corners: frame too large");
     const size_t need = vs_detect_workspace(width, height, n);
     if (ws_bytes < need) return vs::set_error(VS_ERR_WORKSPACE, "vs_detect_corners: workspace %zu < %zu", ws_bytes, need);
@@ -537,13 +678,17 @@ extern "C" int vs_detect_corners(const uint8_t* frames, int64_t frame_stride, in
     int e = vs::check_launch("vs_detect_corners(init)");
     if (e) return e;
     const int rw = width - 2 * p->roi_mx, rh = height - 2 * p->roi_my;
-    const int tiles_x = (rw + RTW - 1) / RTW, tiles_y = (rh + RTH - 1) / RTH;
-    const bool by_xcd = n >= VS_XCD_MIN_ITEMS;
-    const int64_t nblk = vs::xcd_grid(n, tiles_x * tiles_y, by_xcd);
-    corner_response_kernel<<<(unsigned)nblk, 256, 0, s>>>(frames, frame_stride, width, height, pitch, p->roi_mx,
-                                                          p->roi_my, n, tiles_x, tiles_y, by_xcd, istride, gate,
-                                                          gate_min, w8, ib);
+    const int strips = (rw + SW - 1) / SW, segs = (rh + SR - 1) / SR;
+    const int64_t nwaves = (int64_t)n * strips * segs;
+    corner_response_kernel<<<(unsigned)((nwaves + 3) / 4), 256, 0, s>>>(frames, frame_stride, width, height, pitch,
+                                                                      p->roi_mx, p->roi_my, n, strips, segs, istride,
+                                                                      gate, gate_min, w8, ib);
     e = vs::check_launch("vs_detect_corners(response)");
+    if (e) return e;
+    // survivors are a small fraction of the ROI: 32 blocks per item stride over them
+    corner_keys_kernel<<<dim3(32, n), 256, 0, s>>>(frames, frame_stride, width, height, pitch, p->roi_mx, p->roi_my,
+                                                   istride, gate, gate_min, w8, ib);
+    e = vs::check_launch("vs_detect_corners(keys)");
     if (e) return e;
     corner_select_kernel<<<n, 1024, 0, s>>>(w8, ib, width, height, istride, gate, gate_min, p->max_corners, p->quality,
                                             p->min_dist, capacity, xy, score, count, alive);
