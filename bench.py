@@ -100,7 +100,7 @@ def main() -> int:
 
     # roofline of the dominant kernel: the tracker (FP32 VALU bound)
     lk_ms = [a.elapsed_time(b) for a, b in lk_events]
-    w = torch.stack(work).cpu().numpy()          # [steps, 5, 2]
+    w = torch.stack(work).sum(dim=2).cpu().numpy()   # [steps, 5, segments, 2] -> [steps, 5, 2]
     nwin = (2 * P.win_half + 1) ** 2
     flop = (w[..., 0].astype(np.float64) * LK_FLOP_SETUP_PER_SAMPLE + w[..., 1] * LK_FLOP_ITER_PER_SAMPLE) * nwin
     flop_per_launch = float(flop.sum() / max(len(lk_ms), 1))

@@ -121,8 +121,9 @@ int vs_detect_corners(const uint8_t* frames, int64_t frame_stride, int32_t width
  * of status-1 slots), and optional chained copies xy_chain / alive_chain (may be NULL) receiving the
  * same values as xy_next / status (the next step's input, which a later re-detection may
  * overwrite without touching this step's outputs). xy_chain may alias xy_prev (same for alive).
- * work (may be NULL): two counters set by the call to the number of window set-ups (point x
- * level x direction) and of Gauss-Newton iterations it performed, for throughput accounting. */
+ * work (may be NULL): uint64[2 * n]; work[2 i] and work[2 i + 1] are set by the call to the number
+ * of window set-ups (point x level x direction) and of Gauss-Newton iterations it performed for
+ * item i, for throughput accounting. */
 typedef struct {
     int32_t win_half;
     int32_t max_iter;

@@ -5,13 +5,21 @@
 // rows over G = 64 / (2h+1) lane groups, each group owning R = ceil((2h+1) / G) consecutive rows
 // (h = 10: 21 columns x 3 groups of 7 rows = 63 lanes). Samples outside the window get zero
 // gradient weight, so every lane runs the same branch-free loops. All samples of a window share
-// one fractional offset, so per level a lane reads its (R+3) x 4 pixel block once (buffer loads
-// with 32-bit offsets, edge-clamped), interpolates each row horizontally first and derives I,
-// dI/dx, dI/dy of its R samples into registers. Each Gauss-Newton iteration needs the lane's
-// (R+1) x 2 next-frame block; it stays in registers while the iterate's integer position is
-// unchanged and is reloaded when it moves. The three tensor sums and the two residual sums are
-// DPP row reductions plus four lane reads, giving every lane the same total, so the iteration
-// control is wave-uniform. One wave per workgroup lets every point retire independently.
+// one fractional offset, so per level a lane reads its (R+3) x 4 previous-frame block once (one
+// unaligned 32-bit load per row when the whole window is inside the level, edge-clamped byte loads
+// otherwise), interpolates each row horizontally first and derives I, dI/dx, dI/dy of its R samples
+// into registers.
+//
+// Gauss-Newton iterations: all samples also share the iterate's fractional offset (ja, jb), so the
+// residual sum over the window, sum (I - J) grad I, is E0 - ja E1 - jb E2 - ja jb E3 with four sums
+// per gradient component that depend only on the iterate's integer position (the bilinear form of
+// the next-frame 2 x 2 blocks; see residual_partials). They are recomputed, from the lane's (R+1) x 2
+// next-frame block, only when the integer position moves; an iteration that stays on the same
+// pixel costs a few wave-uniform operations. The first block of each level is read with the set-up,
+// and its eight sums share the set-up's reduction with the three tensor sums. Reductions are
+// transposing DPP row sums, so several sums cost little more than one; every lane ends with the
+// same totals, and the iteration control is wave-uniform. One wave per workgroup lets every point
+// retire independently.
 #include "vs_common.hpp"
 
 namespace {
@@ -57,6 +65,103 @@ struct LKConst {
     float eps2, min_eig;
 };
 
+__device__ __forceinline__ bool wave_all(bool c) { return __ballot(!c) == 0; }
+
+// Next-frame 2-pixel rows x0, x0 + 1 of rows y0 .. y0 + RMAX: qa = P(x0), qd = P(x0 + 1) - P(x0). When
+// every active lane's block is inside the level, one (unaligned) 16-bit load per row; otherwise
+// edge-clamped byte loads.
+template <int RMAX>
+__device__ __forceinline__ void load_next_block(const Img& B, int x0, int y0, bool active, float (&qa)[RMAX + 1],
+                                                float (&qd)[RMAX + 1])
+{
+    const bool b_in = wave_all(!active || (x0 >= 0 && x0 + 1 <= B.w - 1 && y0 >= 0 && y0 + RMAX <= B.h - 1));
+    if (b_in) {
+#pragma unroll
+        for (int k = 0; k <= RMAX; ++k) {
+            const uint32_t w = __builtin_amdgcn_raw_buffer_load_b16(
+                B.rs, (int)__umul24((unsigned)(y0 + k), (unsigned)B.pitch) + x0, 0, 0);
+            qa[k] = (float)(w & 0xff);
+            qd[k] = (float)(w >> 8) - qa[k];
+        }
+    } else {
+        const int c0 = vs::clampi(x0, 0, B.w - 1), c1 = vs::clampi(x0 + 1, 0, B.w - 1);
+#pragma unroll
+        for (int k = 0; k <= RMAX; ++k) {
+            const int base = (int)__umul24((unsigned)vs::clampi(y0 + k, 0, B.h - 1), (unsigned)B.pitch);
+            qa[k] = ld(B, base + c0);
+            qd[k] = ld(B, base + c1) - qa[k];
+        }
+    }
+}
+
+// Lane partials of the residual sums for the next-frame block (qa, qd) at integer offset (x0, y0).
+// With the iterate's fraction (ja, jb), the bilinear next-frame sample of window pixel k is
+// P00 + ja d10 + jb d01 + ja jb d11 with d10 = qd_k, d01 = qa_{k+1} - qa_k, d11 = qd_{k+1} - qd_k, so
+//   sum_k (I_k - J_k) Ix_k = E0x - ja E1x - jb E2x - ja jb E3x,  E0x = sum (I_k - P00_k) Ix_k,
+// E1x = sum d10 Ix, E2x = sum d01 Ix, E3x = sum d11 Ix (likewise for Iy). The E sums depend on the
+// integer offset only. Output order: E0x E1x E2x E3x E0y E1y E2y E3y.
+template <int RMAX>
+__device__ __forceinline__ void residual_partials(const float (&I)[RMAX], const float (&Ix)[RMAX], const float (&Iy)[RMAX],
+                                                  const float (&qa)[RMAX + 1], const float (&qd)[RMAX + 1], float* e)
+{
+#pragma unroll
+    for (int j = 0; j < 8; ++j) e[j] = 0.f;
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) {
+        const float e0 = I[k] - qa[k], d10 = qd[k];
+        const float d01 = qa[k + 1] - qa[k], d11 = qd[k + 1] - qd[k];
+        e[0] = fmaf(e0, Ix[k], e[0]);
+        e[1] = fmaf(d10, Ix[k], e[1]);
+        e[2] = fmaf(d01, Ix[k], e[2]);
+        e[3] = fmaf(d11, Ix[k], e[3]);
+        e[4] = fmaf(e0, Iy[k], e[4]);
+        e[5] = fmaf(d10, Iy[k], e[5]);
+        e[6] = fmaf(d01, Iy[k], e[6]);
+        e[7] = fmaf(d11, Iy[k], e[7]);
+    }
+}
+
+// Previous-frame samples of one lane: I, and the gradient terms 0.5 * central differences (zero
+// outside the window), at rows iy .. iy + RMAX - 1 and column ix, offset by the shared fraction (a, b).
+// Rows iy-1 .. iy+RMAX+1 and columns ix-1 .. ix+2 are read: with FAST (every lane's block inside the
+// level) one unaligned 32-bit load per row, otherwise four edge-clamped byte loads. Rows are
+// interpolated horizontally first.
+template <int RMAX, bool FAST>
+__device__ __forceinline__ void window_samples(const Img& A, int ix, int iy, float a, float b, int nrows, float (&I)[RMAX],
+                                               float (&Ix)[RMAX], float (&Iy)[RMAX])
+{
+    float H1[RMAX + 3], Dd[RMAX + 3];   // per row: horizontal lerp at the sample column, and the
+                                        // horizontal central difference lerped the same way
+#pragma unroll
+    for (int r = 0; r < RMAX + 3; ++r) {
+        float p0, p1, p2, p3;
+        if constexpr (FAST) {
+            const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(
+                A.rs, (int)__umul24((unsigned)(iy - 1 + r), (unsigned)A.pitch) + ix - 1, 0, 0);
+            p0 = (float)(w & 0xff);
+            p1 = (float)((w >> 8) & 0xff);
+            p2 = (float)((w >> 16) & 0xff);
+            p3 = (float)(w >> 24);
+        } else {
+            const int base = (int)__umul24((unsigned)vs::clampi(iy - 1 + r, 0, A.h - 1), (unsigned)A.pitch);
+            p0 = ld(A, base + vs::clampi(ix - 1, 0, A.w - 1));
+            p1 = ld(A, base + vs::clampi(ix, 0, A.w - 1));
+            p2 = ld(A, base + vs::clampi(ix + 1, 0, A.w - 1));
+            p3 = ld(A, base + vs::clampi(ix + 2, 0, A.w - 1));
+        }
+        H1[r] = lerp(p1, p2, a);
+        Dd[r] = lerp(p2, p3, a) - lerp(p0, p1, a);
+    }
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) {
+        // sample row k sits between rows k + 1 and k + 2
+        const float wgt = k < nrows ? 0.5f : 0.0f;   // zero weight outside the window
+        I[k] = lerp(H1[k + 1], H1[k + 2], b);
+        Ix[k] = wgt * lerp(Dd[k + 1], Dd[k + 2], b);
+        Iy[k] = wgt * lerp(H1[k + 2] - H1[k], H1[k + 3] - H1[k + 1], b);
+    }
+}
+
 template <int RMAX>
 __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* fb, const uint8_t* pb,
                           const vs::LevelDesc& d, const LKConst& c, float ux, float uy, float& vx, float& vy,
@@ -82,44 +187,41 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
         const float a = cx - fx, b = cy - fy;
         const int ix = (int)fx + qx, iy = (int)fy + qy0;
 
-        // ---- window set-up: rows iy-1 .. iy+RMAX+1, columns ix-1 .. ix+2 of the previous frame
-        int col[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) col[t] = vs::clampi(ix - 1 + t, 0, A.w - 1);
-        float H1[4], Dd[4];             // sliding rows: horizontal lerp at the sample column, and
-                                        // the horizontal central difference lerped the same way
-        auto row_terms = [&](int r, float& h1, float& dd) {
-            const int base = (int)__umul24((unsigned)vs::clampi(iy - 1 + r, 0, A.h - 1), (unsigned)A.pitch);
-            const float p0 = ld(A, base + col[0]), p1 = ld(A, base + col[1]);
-            const float p2 = ld(A, base + col[2]), p3 = ld(A, base + col[3]);
-            h1 = lerp(p1, p2, a);
-            dd = lerp(p2, p3, a) - lerp(p0, p1, a);
-        };
-        row_terms(0, H1[0], Dd[0]);
-        row_terms(1, H1[1], Dd[1]);
-        row_terms(2, H1[2], Dd[2]);
+        // ---- window set-up: rows iy-1 .. iy+RMAX+1, columns ix-1 .. ix+2 of the previous frame. When
+        // every lane's block is inside the level, a row is one (unaligned) 32-bit load; otherwise four
+        // edge-clamped byte loads.
+        const bool a_in = wave_all(!active || (ix - 1 >= 0 && ix + 2 <= A.w - 1 && iy - 1 >= 0 && iy + RMAX + 1 <= A.h - 1));
         float I[RMAX], Ix[RMAX], Iy[RMAX];
-        float g11 = 0.f, g12 = 0.f, g22 = 0.f;
+        if (a_in)
+            window_samples<RMAX, true>(A, ix, iy, a, b, nrows, I, Ix, Iy);
+        else
+            window_samples<RMAX, false>(A, ix, iy, a, b, nrows, I, Ix, Iy);
+        // the first iterate's next-frame block is read here, so its residual sums share the set-up's
+        // reduction: 3 tensor sums + 8 residual sums in one transposing reduction
+        int cjx = (int)floorf(cx + gx), cjy = (int)floorf(cy + gy);
+        float qa[RMAX + 1], qd[RMAX + 1];
+        load_next_block<RMAX>(B, cjx + qx, cjy + qy0, active, qa, qd);
+        float v[16];
+        residual_partials<RMAX>(I, Ix, Iy, qa, qd, v + 3);
+        v[0] = v[1] = v[2] = 0.f;
 #pragma unroll
         for (int k = 0; k < RMAX; ++k) {
-            row_terms(k + 3, H1[3], Dd[3]);
-            // sample row k sits between sliding rows 1 and 2
-            const float wgt = k < nrows ? 0.5f : 0.0f;   // zero weight outside the window
-            I[k] = lerp(H1[1], H1[2], b);
-            Ix[k] = wgt * lerp(Dd[1], Dd[2], b);
-            Iy[k] = wgt * lerp(H1[2] - H1[0], H1[3] - H1[1], b);
-            g11 = fmaf(Ix[k], Ix[k], g11);
-            g12 = fmaf(Ix[k], Iy[k], g12);
-            g22 = fmaf(Iy[k], Iy[k], g22);
-            H1[0] = H1[1]; H1[1] = H1[2]; H1[2] = H1[3];
-            Dd[0] = Dd[1]; Dd[1] = Dd[2]; Dd[2] = Dd[3];
+            v[0] = fmaf(Ix[k], Ix[k], v[0]);
+            v[1] = fmaf(Ix[k], Iy[k], v[1]);
+            v[2] = fmaf(Iy[k], Iy[k], v[2]);
         }
-        vs::wave_total2(g11, g12);
-        g22 = vs::wave_total(g22);
+#pragma unroll
+        for (int j = 11; j < 16; ++j) v[j] = 0.f;
+        const float tot = vs::wave_transpose_sum<16>(v);
+        const float g11 = vs::transposed_total<16>(tot, 0), g12 = vs::transposed_total<16>(tot, 1);
+        const float g22 = vs::transposed_total<16>(tot, 2);
+        float E[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) E[j] = vs::transposed_total<16>(tot, 3 + j);
         ++n_setup;
         const float tr = g11 + g22;
-        const float s = sqrtf((g11 - g22) * (g11 - g22) + 4.0f * g12 * g12);
-        const float lmax = 0.5f * (tr + s);
+        const float sq = sqrtf((g11 - g22) * (g11 - g22) + 4.0f * g12 * g12);
+        const float lmax = 0.5f * (tr + sq);
         const float det = det2(g11, g22, g12);
         const float lmin = lmax > 0.f ? det / lmax : 0.f;
         float nux = 0.f, nuy = 0.f;
@@ -127,35 +229,24 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
             if (l == 0) ok = false;
         } else {
             const float inv = __builtin_amdgcn_rcpf(det);
-            int cjx = 0x7fffffff, cjy = 0;                // cached integer position of the next block
-            float qa[RMAX + 1], qd[RMAX + 1];             // next-frame column jx and (jx + 1) - jx
             for (int it = 0; it < c.max_iter; ++it) {
                 const float pxx = cx + gx + nux, pyy = cy + gy + nuy;
                 const float jfx = floorf(pxx), jfy = floorf(pyy);
                 const float ja = pxx - jfx, jb = pyy - jfy;
                 const int jx = (int)jfx, jy = (int)jfy;
                 if (jx != cjx || jy != cjy) {
+                    // the integer position moved: new block, new residual sums
                     cjx = jx;
                     cjy = jy;
-                    const int c0 = vs::clampi(jx + qx, 0, B.w - 1), c1 = vs::clampi(jx + qx + 1, 0, B.w - 1);
+                    load_next_block<RMAX>(B, jx + qx, jy + qy0, active, qa, qd);
+                    float e[8];
+                    residual_partials<RMAX>(I, Ix, Iy, qa, qd, e);
+                    const float t8 = vs::wave_transpose_sum<8>(e);
 #pragma unroll
-                    for (int k = 0; k <= RMAX; ++k) {
-                        const int base = (int)__umul24((unsigned)vs::clampi(jy + qy0 + k, 0, B.h - 1), (unsigned)B.pitch);
-                        qa[k] = ld(B, base + c0);
-                        qd[k] = ld(B, base + c1) - qa[k];
-                    }
+                    for (int j = 0; j < 8; ++j) E[j] = vs::transposed_total<8>(t8, j);
                 }
-                float b1 = 0.f, b2 = 0.f;
-                float h0 = fmaf(ja, qd[0], qa[0]);
-#pragma unroll
-                for (int k = 0; k < RMAX; ++k) {
-                    const float h1 = fmaf(ja, qd[k + 1], qa[k + 1]);
-                    const float dlt = I[k] - lerp(h0, h1, jb);
-                    b1 = fmaf(dlt, Ix[k], b1);
-                    b2 = fmaf(dlt, Iy[k], b2);
-                    h0 = h1;
-                }
-                vs::wave_total2(b1, b2);
+                const float b1 = E[0] - fmaf(ja, fmaf(jb, E[3], E[1]), jb * E[2]);
+                const float b2 = E[4] - fmaf(ja, fmaf(jb, E[7], E[5]), jb * E[6]);
                 const float ex = (g22 * b1 - g12 * b2) * inv;
                 const float ey = (g11 * b2 - g12 * b1) * inv;
                 nux += ex;
@@ -221,9 +312,9 @@ __global__ __launch_bounds__(64) void lk_kernel(const uint8_t* __restrict__ prev
         }
         if (alive_chain) alive_chain[k] = ok ? 1 : 0;
         if (ok && n_valid) atomicAdd(&n_valid[rec], 1);
-        if (work && n_setup) {
-            atomicAdd(&work[0], (unsigned long long)n_setup);
-            atomicAdd(&work[1], (unsigned long long)n_iter);
+        if (work && n_setup) {   // per-item counters: one address per item keeps the atomics uncontended
+            atomicAdd(&work[2 * item], (unsigned long long)n_setup);
+            atomicAdd(&work[2 * item + 1], (unsigned long long)n_iter);
         }
     }
 }
@@ -232,7 +323,10 @@ __global__ void zero_counters(int32_t* p, int n, int istride, unsigned long long
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (p && i < n) p[(int64_t)i * istride] = 0;
-    if (work && i < 2) work[i] = 0;
+    if (work && i < n) {
+        work[2 * i] = 0;
+        work[2 * i + 1] = 0;
+    }
 }
 
 }  // namespace
@@ -257,8 +351,8 @@ extern "C" int vs_track_lk(const uint8_t* prev_frames, const uint8_t* prev_pyrs,
     if (p->max_iter < 1 || !(p->eps >= 0.f) || !(p->min_eig >= 0.f) || !(p->fb_thresh >= 0.f))
         return vs::set_error(VS_ERR_INVALID, "vs_track_lk: bad parameters");
     if (n > 65535) return vs::set_error(VS_ERR_INVALID, "vs_track_lk: more than 65535 items");
-    if ((int64_t)layout->pitch[0] * layout->height[0] >= ((int64_t)1 << 31))
-        return vs::set_error(VS_ERR_UNSUPPORTED, "vs_track_lk: frame larger than 2 GiB");
+    if ((int64_t)layout->pitch[0] * layout->height[0] >= ((int64_t)1 << 31) || layout->pitch[0] >= (1 << 24))
+        return vs::set_error(VS_ERR_UNSUPPORTED, "vs_track_lk: frame larger than 2 GiB or rows of 16 MiB");
     LKConst c;
     c.hw = p->win_half;
     c.cols = 2 * c.hw + 1;

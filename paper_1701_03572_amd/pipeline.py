@@ -81,8 +81,8 @@ class SequenceStabilizer:
         self.n_emitted = torch.zeros(1, dtype=torch.int32, device=dev)
         self.first = torch.zeros(1, dtype=torch.int64, device=dev)
         self.out = torch.empty((n, height, width), dtype=torch.uint8, device=dev)
-        # per tracking step: [window set-ups, iterations] of its vs_track_lk launch
-        self.lk_work = torch.zeros((P.redetect_every, 2), dtype=torch.int64, device=dev)
+        # per tracking step and segment: [window set-ups, iterations] of its vs_track_lk launch
+        self.lk_work = torch.zeros((P.redetect_every, self.n_seg_max, 2), dtype=torch.int64, device=dev)
         self._lkp = _lk_params(P)
         self._dp = _detect_params(P, width, height)
         self._fp = _fit_params(P, width, height)
