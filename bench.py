@@ -31,6 +31,29 @@ sys.path.insert(0, ROOT)
 LK_FLOP_SETUP_PER_SAMPLE = 43
 LK_FLOP_ITER_PER_SAMPLE = 14
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+# rocprofv3 summary of this workload (kernel trace + FETCH_SIZE / WRITE_SIZE passes)
+PROFILE = os.path.join(ROOT, "profiles", "hd1080p_600f_sequence_path.md")
+TRACKER_SOURCES = ("paper_1701_03572_amd/csrc/lk.hip", "paper_1701_03572_amd/csrc/vs_common.hpp")
+
+
+def tracker_traffic_from_profile():
+    """HBM bytes per tracker launch from the committed counter summary, or None when the summary is
+    missing or was taken on other tracker sources (its recorded digest differs from the current one)."""
+    import hashlib
+    import re
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    m_bytes = re.search(r"Tracker HBM traffic per launch[^:]*: (\d+) bytes", text)
+    m_dig = re.search(r"Tracker source digest[^:]*: ([0-9a-f]{16})", text)
+    if not (m_bytes and m_dig):
+        return None
+    h = hashlib.sha256()
+    for f in TRACKER_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return int(m_bytes.group(1)) if h.hexdigest()[:16] == m_dig.group(1) else None
 
 
 def log(*a):
@@ -111,7 +134,8 @@ def main() -> int:
         (avg_lk_ms, flop_per_launch, achieved_tflops, 100 * lk_share))
     roofline = {"kernel": "lk_kernel (vs_track_lk)", "bound": "alu", "achieved": round(achieved_tflops, 4),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 5),
-                "traffic": None, "avg_launch_ms": round(avg_lk_ms, 4), "flop_per_launch": flop_per_launch,
+                "traffic": tracker_traffic_from_profile(), "avg_launch_ms": round(avg_lk_ms, 4),
+                "flop_per_launch": flop_per_launch,
                 "share_of_step": round(lk_share, 4),
                 "iterations_per_setup": float(w[..., 1].sum() / max(w[..., 0].sum(), 1))}
 
