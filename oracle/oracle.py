@@ -81,6 +81,12 @@ def lib():
         _lib.vso_smooth.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                                     P, P, P]
         _lib.vso_warp.argtypes = [P, C.c_int, C.c_int, C.c_int, P, P, C.c_int, C.c_int]
+        _lib.vso_photo_global.argtypes = [P, P, C.c_int, C.c_int, C.c_int, P, C.c_double, C.c_double, C.c_double,
+                                          C.c_int, C.c_int, C.c_int, C.c_int, P]
+        _lib.vso_photo_feature.argtypes = [P, P, C.c_int, C.c_int, C.c_int, P, P, C.c_int, C.c_int, P, P]
+        _lib.vso_photo_refine.argtypes = [P, P, C.c_int, C.c_int, C.c_int, P, C.c_double, C.c_double, C.c_double,
+                                          C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P, P]
+        _lib.vso_photo_refine.restype = C.c_int
     return _lib
 
 
@@ -244,6 +250,79 @@ def warp(img: np.ndarray, M, border: int = 0) -> np.ndarray:
     out = np.empty_like(img)
     lib().vso_warp(_p(img), w, h, w, _p(M), _p(out), w, border)
     return out
+
+
+# ---------------------------------------------------------------------------------------------
+# O-7 photometric loss, gradient and Gauss-Newton refinement (project extension)
+# ---------------------------------------------------------------------------------------------
+
+def photo_frame(w: int, h: int) -> tuple:
+    """Centre c = ((W-1)/2, (H-1)/2) and scale rho = max(W, H) / 2 of the transform parameters."""
+    return (w - 1) / 2.0, (h - 1) / 2.0, max(w, h) / 2.0
+
+
+def theta_from_fit(params4, w: int, h: int) -> np.ndarray:
+    """theta of the fitted similarity (a, b, tx, ty) in centred coordinates: (rho (a - 1), rho b, tx, ty)."""
+    a, b, tx, ty = (float(v) for v in params4)
+    rho = photo_frame(w, h)[2]
+    return np.array([rho * (a - 1.0), rho * b, tx, ty])
+
+
+def photo_omega(theta, w: int, h: int, extra: int = 0) -> tuple:
+    """Inner rectangle (x0, y0, x1, y1) whose margin is ceil(max |T(x) - x|) + 2 + extra over the
+    frame corners (for this transform the displacement is largest at a corner)."""
+    cx, cy, rho = photo_frame(w, h)
+    th = np.asarray(theta, np.float64)
+    best = 0.0
+    for x in (0, w - 1):
+        for y in (0, h - 1):
+            dx, dy = (x - cx) / rho, (y - cy) / rho
+            mx = th[0] * dx - th[1] * dy + th[2]
+            my = th[1] * dx + th[0] * dy + th[3]
+            best = max(best, float(np.hypot(mx, my)))
+    m = int(np.ceil(best)) + 2 + extra
+    return m, m, w - m, h - m
+
+
+def photo_global(f0: np.ndarray, f1: np.ndarray, theta, omega) -> dict:
+    """Global loss, dL/dtheta, J^T J (4x4) and J^T r over the rectangle omega."""
+    f0, f1 = _u8(f0), _u8(f1)
+    h, w = f0.shape
+    cx, cy, rho = photo_frame(w, h)
+    th = np.ascontiguousarray(theta, np.float64)
+    out = np.zeros(19)
+    lib().vso_photo_global(_p(f0), _p(f1), w, h, w, _p(th), cx, cy, rho, *[int(v) for v in omega], _p(out))
+    jtj = np.zeros((4, 4))
+    t = 5
+    for i in range(4):
+        for j in range(i, 4):
+            jtj[i, j] = jtj[j, i] = out[t]
+            t += 1
+    return {"loss": out[0], "grad": out[1:5].copy(), "jtj": jtj, "jtr": out[15:19].copy()}
+
+
+def photo_feature(f0: np.ndarray, f1: np.ndarray, u, d, win_half: int = 10):
+    """Per-point window loss and its gradient with respect to the displacement d."""
+    f0, f1 = _u8(f0), _u8(f1)
+    h, w = f0.shape
+    u = np.ascontiguousarray(u, np.float64).reshape(-1, 2)
+    d = np.ascontiguousarray(d, np.float64).reshape(-1, 2)
+    m = len(u)
+    loss, grad = np.zeros(m), np.zeros((m, 2))
+    lib().vso_photo_feature(_p(f0), _p(f1), w, h, w, _p(u), _p(d), m, win_half, _p(loss), _p(grad))
+    return loss, grad
+
+
+def photo_refine(f0: np.ndarray, f1: np.ndarray, theta0, omega, max_steps: int = 5):
+    """Gauss-Newton refinement; returns (theta, (initial loss, final loss), accepted steps)."""
+    f0, f1 = _u8(f0), _u8(f1)
+    h, w = f0.shape
+    cx, cy, rho = photo_frame(w, h)
+    th0 = np.ascontiguousarray(theta0, np.float64)
+    th, lo = np.zeros(4), np.zeros(2)
+    k = lib().vso_photo_refine(_p(f0), _p(f1), w, h, w, _p(th0), cx, cy, rho, *[int(v) for v in omega], max_steps,
+                               _p(th), _p(lo))
+    return th, (lo[0], lo[1]), int(k)
 
 
 # ---------------------------------------------------------------------------------------------

@@ -701,3 +701,148 @@ VSO_EXPORT void vso_warp(const uint8_t* src, int w, int h, int pitch, const doub
         }
     }
 }
+
+/* =============================================================================================
+ * O-7  Photometric loss and its gradient, and Gauss-Newton refinement of a fitted similarity.
+ *      Not in the paper: a project extension that checks the fitted pair transform of Eq. 7
+ *      against the image intensities (the brightness constancy of Eq. 3 applied to the whole
+ *      frame) and refines it.
+ *      Readings: S(F, p) is the bilinear interpolant of F extended by edge replication; its
+ *      gradient is the derivative of the bilinear piece in cell floor(p) (the right derivative at
+ *      integer crossings). The transform is T_theta(x) = x + [[a, -b], [b, a]] (x - c) / rho + t
+ *      with theta = (a, b, tx, ty), c the frame centre and rho = max(W, H) / 2, so a fitted
+ *      similarity (A, B, TX, TY) in centred coordinates is theta = (rho (A - 1), rho B, TX, TY).
+ *      Global loss L_g = sum over x in the fixed rectangle Omega of (S(F1, T(x)) - F0(x))^2.
+ *      Feature loss of point i with displacement d_i: sum over the (2h+1)^2 window offsets q of
+ *      (S(F1, u_i + d_i + q) - S(F0, u_i + q))^2. Gauss-Newton: solve (J^T J) delta = -J^T r for the
+ *      residual Jacobian J = grad S . dT/dtheta, accept theta + delta only if L_g decreases, stop
+ *      at the first rejected step or after max_steps.
+ * ============================================================================================= */
+static void sample_d(const img_t* im, double x, double y, double* v, double* gx, double* gy)
+{
+    const double fx = floor(x), fy = floor(y);
+    const double a = x - fx, b = y - fy;
+    const int x0 = (int)fx, y0 = (int)fy;
+    const double p00 = px_ext(im, x0, y0), p10 = px_ext(im, x0 + 1, y0);
+    const double p01 = px_ext(im, x0, y0 + 1), p11 = px_ext(im, x0 + 1, y0 + 1);
+    *v = (1.0 - a) * (1.0 - b) * p00 + a * (1.0 - b) * p10 + (1.0 - a) * b * p01 + a * b * p11;
+    if (gx) *gx = (1.0 - b) * (p10 - p00) + b * (p11 - p01);
+    if (gy) *gy = (1.0 - a) * (p01 - p00) + a * (p11 - p10);
+}
+
+/* out[19]: loss, grad[4] (dL/dtheta), the upper triangle of J^T J row by row (00 01 02 03 11 12 13
+ * 22 23 33), J^T r[4]. */
+VSO_EXPORT void vso_photo_global(const uint8_t* f0, const uint8_t* f1, int w, int h, int pitch, const double* theta,
+                                 double cx, double cy, double rho, int ox0, int oy0, int ox1, int oy1, double* out)
+{
+    const img_t I1 = {f1, w, h, pitch};
+    for (int k = 0; k < 19; ++k) out[k] = 0.0;
+    for (int y = oy0; y < oy1; ++y) {
+        for (int x = ox0; x < ox1; ++x) {
+            const double dx = (x - cx) / rho, dy = (y - cy) / rho;
+            const double tx = x + theta[0] * dx - theta[1] * dy + theta[2];
+            const double ty = y + theta[1] * dx + theta[0] * dy + theta[3];
+            double s, sx, sy;
+            sample_d(&I1, tx, ty, &s, &sx, &sy);
+            const double r = s - (double)f0[(size_t)y * pitch + x];
+            /* dT/da = (dx, dy), dT/db = (-dy, dx), dT/dtx = (1, 0), dT/dty = (0, 1) */
+            const double J[4] = {sx * dx + sy * dy, -sx * dy + sy * dx, sx, sy};
+            out[0] += r * r;
+            int t = 5;
+            for (int i = 0; i < 4; ++i) {
+                out[1 + i] += 2.0 * r * J[i];
+                out[15 + i] += J[i] * r;
+                for (int j = i; j < 4; ++j) out[t++] += J[i] * J[j];
+            }
+        }
+    }
+}
+
+/* u, d: [m][2]; loss[m]; grad[m][2] (may be NULL) */
+VSO_EXPORT void vso_photo_feature(const uint8_t* f0, const uint8_t* f1, int w, int h, int pitch, const double* u,
+                                  const double* d, int m, int hw, double* loss, double* grad)
+{
+    const img_t I0 = {f0, w, h, pitch}, I1 = {f1, w, h, pitch};
+    for (int i = 0; i < m; ++i) {
+        double l = 0.0, g0 = 0.0, g1 = 0.0;
+        for (int qy = -hw; qy <= hw; ++qy) {
+            for (int qx = -hw; qx <= hw; ++qx) {
+                double s1, sx, sy, s0;
+                sample_d(&I1, u[2 * i] + d[2 * i] + qx, u[2 * i + 1] + d[2 * i + 1] + qy, &s1, &sx, &sy);
+                sample_d(&I0, u[2 * i] + qx, u[2 * i + 1] + qy, &s0, NULL, NULL);
+                const double r = s1 - s0;
+                l += r * r;
+                g0 += 2.0 * r * sx;
+                g1 += 2.0 * r * sy;
+            }
+        }
+        loss[i] = l;
+        if (grad) {
+            grad[2 * i] = g0;
+            grad[2 * i + 1] = g1;
+        }
+    }
+}
+
+/* Solves the symmetric 4x4 system given by its upper triangle (as in vso_photo_global) for
+ * -rhs, by Gaussian elimination with partial pivoting. Returns 0 if a pivot vanishes. */
+static int solve4_neg(const double* upper, const double* rhs, double* x)
+{
+    double M[4][5];
+    int t = 0;
+    for (int i = 0; i < 4; ++i)
+        for (int j = i; j < 4; ++j) {
+            M[i][j] = upper[t];
+            M[j][i] = upper[t];
+            ++t;
+        }
+    for (int i = 0; i < 4; ++i) M[i][4] = -rhs[i];
+    for (int c = 0; c < 4; ++c) {
+        int p = c;
+        for (int r = c + 1; r < 4; ++r)
+            if (fabs(M[r][c]) > fabs(M[p][c])) p = r;
+        if (M[p][c] == 0.0) return 0;
+        if (p != c)
+            for (int k = 0; k < 5; ++k) {
+                const double tmp = M[c][k];
+                M[c][k] = M[p][k];
+                M[p][k] = tmp;
+            }
+        for (int r = c + 1; r < 4; ++r) {
+            const double f = M[r][c] / M[c][c];
+            for (int k = c; k < 5; ++k) M[r][k] -= f * M[c][k];
+        }
+    }
+    for (int r = 3; r >= 0; --r) {
+        double s = M[r][4];
+        for (int k = r + 1; k < 4; ++k) s -= M[r][k] * x[k];
+        x[r] = s / M[r][r];
+    }
+    return 1;
+}
+
+/* Returns the number of accepted steps; theta_out[4]; loss_out[2] = (initial, final). */
+VSO_EXPORT int vso_photo_refine(const uint8_t* f0, const uint8_t* f1, int w, int h, int pitch, const double* theta0,
+                                double cx, double cy, double rho, int ox0, int oy0, int ox1, int oy1, int max_steps,
+                                double* theta_out, double* loss_out)
+{
+    double th[4] = {theta0[0], theta0[1], theta0[2], theta0[3]};
+    double cur[19];
+    vso_photo_global(f0, f1, w, h, pitch, th, cx, cy, rho, ox0, oy0, ox1, oy1, cur);
+    loss_out[0] = cur[0];
+    int accepted = 0;
+    for (int step = 0; step < max_steps; ++step) {
+        double delta[4];
+        if (!solve4_neg(cur + 5, cur + 15, delta)) break;
+        const double cand[4] = {th[0] + delta[0], th[1] + delta[1], th[2] + delta[2], th[3] + delta[3]};
+        double nxt[19];
+        vso_photo_global(f0, f1, w, h, pitch, cand, cx, cy, rho, ox0, oy0, ox1, oy1, nxt);
+        if (!(nxt[0] < cur[0])) break;
+        for (int k = 0; k < 4; ++k) th[k] = cand[k];
+        for (int k = 0; k < 19; ++k) cur[k] = nxt[k];
+        ++accepted;
+    }
+    for (int k = 0; k < 4; ++k) theta_out[k] = th[k];
+    loss_out[1] = cur[0];
+    return accepted;
+}
