@@ -276,10 +276,12 @@ __global__ __launch_bounds__(64) void lk_kernel(const uint8_t* __restrict__ prev
                                                 const uint8_t* alive_prev, int capacity, LKConst c, int fb,
                                                 float fb_thresh, float* xy_next, uint8_t* status, float* fb_err,
                                                 int32_t* n_valid, float* xy_chain, uint8_t* alive_chain,
-                                                unsigned long long* work)
+                                                unsigned long long* work, int n_items, int by_xcd)
 {
-    const int slot = blockIdx.x;
-    const int item = blockIdx.y;
+    // all point slots of an item run on one XCD, so the overlapping windows of its frame pair are
+    // shared in that XCD's L2
+    int item, slot;
+    if (!vs::xcd_map(blockIdx.x, n_items, capacity, by_xcd != 0, item, slot)) return;
     const int lane = threadIdx.x;
     const int64_t rec = (int64_t)item * istride;
     const int64_t k = rec * capacity + slot;
@@ -370,14 +372,17 @@ extern "C" int vs_track_lk(const uint8_t* prev_frames, const uint8_t* prev_pyrs,
         if (e) return e;
     }
     const vs::LevelDesc d = vs::level_desc(*layout);
-    dim3 grid(capacity, n);
+    const bool by_xcd = n >= VS_XCD_MIN_ITEMS;
+    const int64_t nblk = vs::xcd_grid(n, capacity, by_xcd);
+    if (nblk > 0x7fffffff) return vs::set_error(VS_ERR_INVALID, "vs_track_lk: grid too large");
+    const unsigned grid = (unsigned)nblk;
     if (c.rows <= 7)
         lk_kernel<7><<<grid, 64, 0, s>>>(prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride,
                                          istride, d, xy_prev, alive_prev, capacity, c, p->fb, p->fb_thresh, xy_next,
-                                         status, fb_err, n_valid, xy_chain, alive_chain, wk);
+                                         status, fb_err, n_valid, xy_chain, alive_chain, wk, n, by_xcd);
     else
         lk_kernel<16><<<grid, 64, 0, s>>>(prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride,
                                           istride, d, xy_prev, alive_prev, capacity, c, p->fb, p->fb_thresh, xy_next,
-                                          status, fb_err, n_valid, xy_chain, alive_chain, wk);
+                                          status, fb_err, n_valid, xy_chain, alive_chain, wk, n, by_xcd);
     return vs::check_launch("vs_track_lk");
 }

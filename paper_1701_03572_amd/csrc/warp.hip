@@ -1,7 +1,7 @@
 // warp_frame: inverse-mapped bilinear warp of 8-bit frames, all items of a batch in one launch.
 //
-// A 256-thread workgroup covers a 256 x 16 output tile; each thread produces 4 consecutive pixels in
-// each of 4 rows, stored as one 32-bit word per row when the row allows it. The 2x3 matrix is
+// A 256-thread workgroup covers a 256 x 32 output tile; each thread produces 4 consecutive pixels in
+// each of 8 rows, stored as one 32-bit word per row when the row allows it. The 2x3 matrix is
 // inverted in binary64; per-pixel source coordinates are FP32, relative to the tile's source box.
 //
 // Source box: the map is affine and is evaluated in a form that is monotone in x and in y, so the
@@ -17,11 +17,11 @@
 namespace {
 
 constexpr int TW = 256;                 // tile width: 64 lanes x 4 pixels
-constexpr int RPT = 4;                  // rows per thread
+constexpr int RPT = 8;                  // rows per thread
 constexpr int TH = 4 * RPT;             // 4 waves stacked vertically
 constexpr int LW = 288;                 // LDS row pitch: 18 chunks of 16 bytes
 constexpr int NCH = LW / 16;
-constexpr int MAXR = 48;                // staged rows at most
+constexpr int MAXR = 64;                // staged rows at most
 constexpr int NLD = (NCH * MAXR + 255) / 256;
 constexpr float BIG = 1048576.0f;       // boxes beyond +-2^20 take the direct path
 constexpr uint32_t RSRC_WORD3 = 0x00020000;   // raw (untyped) buffer access on gfx9-family parts
@@ -58,11 +58,14 @@ __device__ __forceinline__ Box corner_box(float f00, float f01, float c0, float 
 __global__ __launch_bounds__(256, 8) void warp_kernel(const uint8_t* __restrict__ src, int64_t src_stride, int W, int H,
                                                       int src_pitch, const double* __restrict__ mats, int64_t mat_stride,
                                                       uint8_t* __restrict__ dst, int64_t dst_stride, int dst_pitch,
-                                                      int border, int tiles_x, int tiles_y, int vec_ok)
+                                                      int border, int tiles_x, int tiles_y, int vec_ok, int n_items,
+                                                      int by_xcd)
 {
     __shared__ __attribute__((aligned(16))) uint8_t tin[MAXR * LW];
-    const int tiles = tiles_x * tiles_y;
-    const int item = blockIdx.x / tiles, tile = blockIdx.x - item * tiles;
+    // the tiles of one frame run on one XCD, so the halo rows of vertically adjacent tiles are
+    // shared in its L2
+    int item, tile;
+    if (!vs::xcd_map(blockIdx.x, n_items, tiles_x * tiles_y, by_xcd != 0, item, tile)) return;
     const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
     const int ox = tx * TW, oy = ty * TH;
     const int x4 = ox + (threadIdx.x & 63) * 4;
@@ -222,13 +225,14 @@ extern "C" int vs_warp_frame(const uint8_t* src, int64_t src_stride, int32_t wid
     if (n > 1 && (mat_stride < 6 || src_stride < (int64_t)src_pitch * height || dst_stride < (int64_t)dst_pitch * height))
         return vs::set_error(VS_ERR_INVALID, "vs_warp_frame: strides overlap items");
     const int tiles_x = (width + TW - 1) / TW, tiles_y = (height + TH - 1) / TH;
-    const int64_t nblk = (int64_t)n * tiles_x * tiles_y;
+    const bool by_xcd = n >= VS_XCD_MIN_ITEMS;
+    const int64_t nblk = vs::xcd_grid(n, tiles_x * tiles_y, by_xcd);
     if (nblk > 0x7fffffff) return vs::set_error(VS_ERR_INVALID, "vs_warp_frame: grid too large");
     // 16-byte staging loads need 16-byte aligned rows in every item
     const int vec_ok = (src_pitch % 16 == 0) && (reinterpret_cast<uintptr_t>(src) % 16 == 0) &&
                        (n == 1 || src_stride % 16 == 0);
     warp_kernel<<<(unsigned)nblk, 256, 0, vs::as_stream(stream)>>>(src, src_stride, width, height, src_pitch, mats,
                                                                    mat_stride, dst, dst_stride, dst_pitch, border,
-                                                                   tiles_x, tiles_y, vec_ok);
+                                                                   tiles_x, tiles_y, vec_ok, n, by_xcd);
     return vs::check_launch("vs_warp_frame");
 }
