@@ -232,6 +232,53 @@ int vs_warp_frame(const uint8_t* src, int64_t src_stride, int32_t width, int32_t
                   int32_t n, int32_t border, void* stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * Photometric check and refinement of fitted pair similarities. An extension beyond the six stages
+ * above: the brightness constancy of Section 3.2 (Eq. 3) applied to the whole frame under the
+ * similarity of Section 4.1 (Eq. 7).
+ * Definitions. S(F, p) is the bilinear interpolant of F extended by edge replication; its gradient is
+ * the derivative of the bilinear piece in cell floor(p). T_theta(x) = x + [[a, -b], [b, a]] (x - c) / rho
+ * + t with theta = (a, b, tx, ty); a fitted similarity (A, B, TX, TY) in centred coordinates
+ * (vs_fit_similarity) is theta = (rho (A - 1), rho B, TX, TY) with c = ((W-1)/2, (H-1)/2). The loss of
+ * a pair is L = sum over x in the rectangle omega of r(x)^2, r = S(next, T(x)) - prev(x), and
+ * J(x) = grad S . dT/dtheta. All arithmetic is binary64.
+ * Items: n pairs, pair i reads prev + i * frame_stride, next + i * frame_stride and
+ * theta[i * theta_stride + 0..3] (device). omega (host) is shared; 0 <= x0, y0 and x1 <= W, y1 <= H.
+ * sums[i * VS_PHOTO_SUMS + k] (device), fully written by the call:
+ *   k = 0 the loss; 1..4 dL/dtheta; 5..14 the upper triangle of J^T J row by row
+ *   (00 01 02 03 11 12 13 22 23 33); 15..18 J^T r. vs_photometric_fwd fills only k = 0 (the rest 0).
+ */
+#define VS_PHOTO_SUMS 19
+typedef struct {
+    int32_t x0, y0, x1, y1;
+} vs_rect;
+
+int vs_photometric_fwd(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width, int32_t height,
+                       int32_t pitch, int32_t n, const double* theta, int64_t theta_stride, double cx, double cy,
+                       double rho, const vs_rect* omega, double* sums, void* stream);
+int vs_photometric_bwd(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width, int32_t height,
+                       int32_t pitch, int32_t n, const double* theta, int64_t theta_stride, double cx, double cy,
+                       double rho, const vs_rect* omega, double* sums, void* stream);
+
+/* Per-feature window loss (same sampler): for point i with u[i][2] and displacement d[i][2] (float,
+ * device), loss[i] = sum over q in [-win_half, win_half]^2 of (S(next, u + d + q) - S(prev, u + q))^2
+ * and grad[i][2] = dloss/dd (may be NULL). One frame pair; 0 <= win_half <= 31. */
+int vs_photometric_features(const uint8_t* prev, const uint8_t* next, int32_t width, int32_t height, int32_t pitch,
+                            const float* u, const float* d, int32_t m, int32_t win_half, double* loss, double* grad,
+                            void* stream);
+
+/* Gauss-Newton refinement of n pairs from theta0: each step solves (J^T J) delta = -J^T r at the
+ * current parameters and accepts theta + delta only if the loss decreases; a pair stops at its first
+ * rejected step, when J^T J is not positive definite, or after max_steps (0..100) accepted steps.
+ * Outputs (device): theta_out[i * theta_stride + 0..3], loss_out[i][2] = (initial, final) (may be NULL),
+ * accepted[i] = accepted steps (may be NULL). workspace: at least vs_photometric_workspace(n) bytes,
+ * 8-byte aligned; no state survives the call. */
+size_t vs_photometric_workspace(int32_t n);
+int vs_photometric_refine(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width, int32_t height,
+                          int32_t pitch, int32_t n, const double* theta0, double* theta_out, int64_t theta_stride,
+                          double cx, double cy, double rho, const vs_rect* omega, int32_t max_steps, double* loss_out,
+                          int32_t* accepted, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------------
  * misc */
 const char* vs_last_error(void);   /* thread-local message of the last failing call */
 int vs_version(void);

@@ -21,8 +21,8 @@ BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("VSTAB_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["common.hip", "pyramid.hip", "corners.hip", "lk.hip", "fit.hip", "smooth.hip", "warp.hip"]
-NO_CONTRACT = {"fit.hip", "smooth.hip", "corners.hip"}
+SOURCES = ["common.hip", "pyramid.hip", "corners.hip", "lk.hip", "fit.hip", "smooth.hip", "warp.hip", "photometric.hip"]
+NO_CONTRACT = {"fit.hip", "smooth.hip", "corners.hip", "photometric.hip"}
 
 BASE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", INCLUDE, "-I", CSRC]

@@ -1,0 +1,418 @@
+// Photometric check and refinement of fitted pair similarities (an extension: the brightness
+// constancy of Eq. 3 applied to the whole frame under the similarity of Eq. 7).
+//
+// The sampler S(F, p) is the bilinear interpolant of F extended by edge replication; its gradient
+// is the derivative of the bilinear piece in cell floor(p). The transform is
+// T(x) = x + [[a, -b], [b, a]] (x - c) / rho + t, theta = (a, b, tx, ty). Per pixel of the rectangle
+// Omega the residual is r = S(F1, T(x)) - F0(x) and its Jacobian row J = grad S . dT/dtheta.
+//
+// Arithmetic is binary64 throughout: vector FP64 issues at the rate of unpacked FP32 on this
+// hardware, and every pass is small next to the tracker.
+//
+// photo_sums_kernel: a 256-thread workgroup covers a 256 x 32 tile of Omega (4 x 8 pixels per thread)
+// and accumulates the loss, the gradient, J^T J (upper triangle) and J^T r; the per-thread sums are
+// reduced over the workgroup and added to the pair's 19 accumulators with one atomic each.
+// photo_feature_kernel: one wave per point; the window's samples are spread over the lanes.
+// Refinement: per step, one sums pass at the candidate parameters and one small kernel per pair that
+// accepts the candidate if its loss is lower, solves (J^T J) delta = -J^T r by Cholesky at the
+// accepted parameters and forms the next candidate. A pair stops at its first rejected step.
+#include "vs_common.hpp"
+
+namespace {
+
+constexpr int NACC = 19;              // loss, grad[4], upper(J^T J)[10], J^T r[4]
+constexpr int TW = 256, RPT = 8, TH = 4 * RPT;
+
+struct PhotoState {
+    double theta[4];                  // accepted parameters
+    double cand[4];                   // candidate of the running step
+    double cur[NACC];                 // sums at theta
+    double nxt[NACC];                 // sums at cand
+    double loss0;
+    int32_t stopped;
+    int32_t accepted;
+};
+
+struct Frame {
+    const uint8_t* p;
+    int w, h, pitch;
+};
+
+__device__ __forceinline__ double px(const Frame& f, int x, int y)
+{
+    x = x < 0 ? 0 : (x > f.w - 1 ? f.w - 1 : x);
+    y = y < 0 ? 0 : (y > f.h - 1 ? f.h - 1 : y);
+    return (double)f.p[(int64_t)y * f.pitch + x];
+}
+
+// bilinear value and gradient at (x, y)
+__device__ __forceinline__ void sample_grad(const Frame& f, double x, double y, double& v, double& gx, double& gy)
+{
+    const double fx = floor(x), fy = floor(y);
+    const double a = x - fx, b = y - fy;
+    const int x0 = (int)fx, y0 = (int)fy;
+    const double p00 = px(f, x0, y0), p10 = px(f, x0 + 1, y0), p01 = px(f, x0, y0 + 1), p11 = px(f, x0 + 1, y0 + 1);
+    const double top = fma(a, p10 - p00, p00), bot = fma(a, p11 - p01, p01);
+    v = fma(b, bot - top, top);
+    gx = fma(b, (p11 - p01) - (p10 - p00), p10 - p00);
+    gy = fma(a, (p11 - p10) - (p01 - p00), p01 - p00);
+}
+
+__device__ __forceinline__ double sample(const Frame& f, double x, double y)
+{
+    const double fx = floor(x), fy = floor(y);
+    const double a = x - fx, b = y - fy;
+    const int x0 = (int)fx, y0 = (int)fy;
+    const double p00 = px(f, x0, y0), p10 = px(f, x0 + 1, y0), p01 = px(f, x0, y0 + 1), p11 = px(f, x0 + 1, y0 + 1);
+    const double top = fma(a, p10 - p00, p00), bot = fma(a, p11 - p01, p01);
+    return fma(b, bot - top, top);
+}
+
+// Which parameters: theta_src[item * tstride] when state == nullptr, else the state's candidate
+// (pairs already stopped are skipped). Sums go to acc[item * astride] (zeroed beforehand).
+__global__ __launch_bounds__(256) void photo_sums_kernel(const uint8_t* __restrict__ prev, const uint8_t* __restrict__ next,
+                                                         int64_t fstride, int W, int H, int pitch, const double* theta_src,
+                                                         int64_t tstride, PhotoState* state, double cx, double cy,
+                                                         double rho, int ox0, int oy0, int ox1, int oy1, int need_grad,
+                                                         double* acc, int64_t astride, int tiles_x, int tiles_y)
+{
+    __shared__ double red[4][NACC];
+    const int tiles = tiles_x * tiles_y;
+    const int item = blockIdx.x / tiles, tile = blockIdx.x - item * tiles;
+    const double* th;
+    double* out;
+    if (state) {
+        if (state[item].stopped) return;
+        th = state[item].cand;
+        out = state[item].nxt;
+    } else {
+        th = theta_src + item * tstride;
+        out = acc + item * astride;
+    }
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const Frame F0{prev + item * fstride, W, H, pitch}, F1{next + item * fstride, W, H, pitch};
+    const double t0 = th[0], t1 = th[1], t2 = th[2], t3 = th[3];
+    const int xb = ox0 + tx * TW + (threadIdx.x & 63) * 4;
+    const int yb = oy0 + ty * TH + (threadIdx.x >> 6) * RPT;
+    double s[NACC];
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) s[k] = 0.0;
+    for (int r = 0; r < RPT; ++r) {
+        const int y = yb + r;
+        if (y >= oy1) break;
+        const double dy = ((double)y - cy) / rho;
+        for (int q = 0; q < 4; ++q) {
+            const int x = xb + q;
+            if (x >= ox1) break;
+            const double dx = ((double)x - cx) / rho;
+            const double px_ = (double)x + t0 * dx - t1 * dy + t2;
+            const double py_ = (double)y + t1 * dx + t0 * dy + t3;
+            double v, gx, gy;
+            sample_grad(F1, px_, py_, v, gx, gy);
+            const double res = v - (double)F0.p[(int64_t)y * pitch + x];
+            s[0] = fma(res, res, s[0]);
+            if (need_grad) {
+                const double J[4] = {gx * dx + gy * dy, gy * dx - gx * dy, gx, gy};
+                int t = 5;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    s[1 + i] = fma(2.0 * res, J[i], s[1 + i]);
+                    s[15 + i] = fma(J[i], res, s[15 + i]);
+#pragma unroll
+                    for (int j = i; j < 4; ++j) {
+                        s[t] = fma(J[i], J[j], s[t]);
+                        ++t;
+                    }
+                }
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nk = need_grad ? NACC : 1;
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) {
+        if (k < nk) {
+            const double t = vs::wave_sum_d(s[k]);
+            if (lane == 0) red[wv][k] = t;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nk) {
+        const int k = threadIdx.x;
+        const double t = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+        atomicAdd(&out[k], t);
+    }
+}
+
+__global__ void zero_kernel(double* p, int64_t stride, int per, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * per) return;
+    const int item = i / per, k = i - item * per;
+    p[item * stride + k] = 0.0;
+}
+
+// Cholesky solve of the SPD 4x4 system in upper-triangle storage for -rhs; false if not positive.
+__device__ bool chol_solve_neg(const double* up, const double* rhs, double* x)
+{
+    double A[4][4];
+    int t = 0;
+    for (int i = 0; i < 4; ++i)
+        for (int j = i; j < 4; ++j) {
+            A[i][j] = up[t];
+            A[j][i] = up[t];
+            ++t;
+        }
+    double L[4][4] = {};
+    for (int j = 0; j < 4; ++j) {
+        double d = A[j][j];
+        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+        if (!(d > 0.0)) return false;
+        L[j][j] = sqrt(d);
+        for (int i = j + 1; i < 4; ++i) {
+            double s = A[i][j];
+            for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+            L[i][j] = s / L[j][j];
+        }
+    }
+    double z[4];
+    for (int i = 0; i < 4; ++i) {
+        double s = -rhs[i];
+        for (int k = 0; k < i; ++k) s -= L[i][k] * z[k];
+        z[i] = s / L[i][i];
+    }
+    for (int i = 3; i >= 0; --i) {
+        double s = z[i];
+        for (int k = i + 1; k < 4; ++k) s -= L[k][i] * x[k];
+        x[i] = s / L[i][i];
+    }
+    return true;
+}
+
+__device__ void propose(PhotoState& s)
+{
+    double delta[4];
+    if (!chol_solve_neg(s.cur + 5, s.cur + 15, delta)) {
+        s.stopped = 1;
+        return;
+    }
+    for (int k = 0; k < 4; ++k) s.cand[k] = s.theta[k] + delta[k];
+    for (int k = 0; k < NACC; ++k) s.nxt[k] = 0.0;
+}
+
+// start: theta = theta0, candidate = theta0 (its pass gives the sums at theta0)
+__global__ void refine_init_kernel(PhotoState* st, const double* theta0, int64_t tstride, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    PhotoState& s = st[i];
+    for (int k = 0; k < 4; ++k) s.theta[k] = s.cand[k] = theta0[i * tstride + k];
+    for (int k = 0; k < NACC; ++k) s.cur[k] = s.nxt[k] = 0.0;
+    s.loss0 = 0.0;
+    s.stopped = 0;
+    s.accepted = 0;
+}
+
+// after the pass at theta0: take its sums, propose the first candidate
+__global__ void refine_first_kernel(PhotoState* st, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    PhotoState& s = st[i];
+    for (int k = 0; k < NACC; ++k) s.cur[k] = s.nxt[k];
+    s.loss0 = s.cur[0];
+    propose(s);
+}
+
+// after a pass at the candidate: accept if the loss decreased, then propose the next candidate
+__global__ void refine_step_kernel(PhotoState* st, int n, int last)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    PhotoState& s = st[i];
+    if (s.stopped) return;
+    if (!(s.nxt[0] < s.cur[0])) {
+        s.stopped = 1;
+        return;
+    }
+    for (int k = 0; k < 4; ++k) s.theta[k] = s.cand[k];
+    for (int k = 0; k < NACC; ++k) s.cur[k] = s.nxt[k];
+    ++s.accepted;
+    if (last) {
+        s.stopped = 1;
+        return;
+    }
+    propose(s);
+}
+
+__global__ void refine_out_kernel(const PhotoState* st, int n, double* theta_out, int64_t tstride, double* loss_out,
+                                  int32_t* accepted)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const PhotoState& s = st[i];
+    for (int k = 0; k < 4; ++k) theta_out[i * tstride + k] = s.theta[k];
+    if (loss_out) {
+        loss_out[2 * i] = s.loss0;
+        loss_out[2 * i + 1] = s.cur[0];
+    }
+    if (accepted) accepted[i] = s.accepted;
+}
+
+__global__ __launch_bounds__(64) void photo_feature_kernel(const uint8_t* __restrict__ prev, const uint8_t* __restrict__ next,
+                                                           int W, int H, int pitch, const float* __restrict__ u,
+                                                           const float* __restrict__ d, int hw, double* loss, double* grad)
+{
+    const int i = blockIdx.x;
+    const int lane = threadIdx.x;
+    const Frame F0{prev, W, H, pitch}, F1{next, W, H, pitch};
+    const double ux = u[2 * i], uy = u[2 * i + 1];
+    const double vx = ux + (double)d[2 * i], vy = uy + (double)d[2 * i + 1];
+    const int side = 2 * hw + 1, nwin = side * side;
+    double l = 0.0, g0 = 0.0, g1 = 0.0;
+    for (int k = lane; k < nwin; k += 64) {
+        const int qy = k / side - hw, qx = k % side - hw;
+        double s1, gx, gy;
+        sample_grad(F1, vx + qx, vy + qy, s1, gx, gy);
+        const double r = s1 - sample(F0, ux + qx, uy + qy);
+        l = fma(r, r, l);
+        g0 = fma(2.0 * r, gx, g0);
+        g1 = fma(2.0 * r, gy, g1);
+    }
+    l = vs::wave_sum_d(l);
+    g0 = vs::wave_sum_d(g0);
+    g1 = vs::wave_sum_d(g1);
+    if (lane == 0) {
+        loss[i] = l;
+        if (grad) {
+            grad[2 * i] = g0;
+            grad[2 * i + 1] = g1;
+        }
+    }
+}
+
+int check_common(const uint8_t* prev, const uint8_t* next, int32_t w, int32_t h, int32_t pitch, int32_t n,
+                 int64_t fstride, const vs_rect* om, const char* who)
+{
+    if (n < 0 || w <= 0 || h <= 0 || pitch < w) return vs::set_error(VS_ERR_INVALID, "%s: bad size", who);
+    if (!om) return vs::set_error(VS_ERR_INVALID, "%s: null omega", who);
+    if (n > 0 && (!prev || !next)) return vs::set_error(VS_ERR_INVALID, "%s: null frame", who);
+    if (n > 65535) return vs::set_error(VS_ERR_INVALID, "%s: more than 65535 items", who);
+    if (n > 1 && fstride < (int64_t)pitch * h) return vs::set_error(VS_ERR_INVALID, "%s: frame stride overlaps items", who);
+    if (om->x0 < 0 || om->y0 < 0 || om->x1 > w || om->y1 > h)
+        return vs::set_error(VS_ERR_INVALID, "%s: omega outside the frame", who);
+    return VS_OK;
+}
+
+void sums_grid(const vs_rect* om, int& tiles_x, int& tiles_y)
+{
+    const int ow = om->x1 > om->x0 ? om->x1 - om->x0 : 0, oh = om->y1 > om->y0 ? om->y1 - om->y0 : 0;
+    tiles_x = (ow + TW - 1) / TW;
+    tiles_y = (oh + TH - 1) / TH;
+}
+
+}  // namespace
+
+namespace {
+
+int photometric_sums(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width, int32_t height,
+                     int32_t pitch, int32_t n, const double* theta, int64_t theta_stride, double cx, double cy, double rho,
+                     const vs_rect* omega, int need_grad, double* out, void* stream)
+{
+    int e = check_common(prev, next, width, height, pitch, n, frame_stride, omega, "vs_photometric_sums");
+    if (e) return e;
+    if (n == 0) return VS_OK;
+    if (!theta || !out) return vs::set_error(VS_ERR_INVALID, "vs_photometric_sums: null argument");
+    if (n > 1 && theta_stride < 4) return vs::set_error(VS_ERR_INVALID, "vs_photometric_sums: theta stride < 4");
+    if (!(rho > 0.0)) return vs::set_error(VS_ERR_INVALID, "vs_photometric_sums: rho must be positive");
+    hipStream_t s = vs::as_stream(stream);
+    zero_kernel<<<(n * VS_PHOTO_SUMS + 255) / 256, 256, 0, s>>>(out, VS_PHOTO_SUMS, VS_PHOTO_SUMS, n);
+    e = vs::check_launch("vs_photometric_sums(zero)");
+    if (e) return e;
+    int tiles_x, tiles_y;
+    sums_grid(omega, tiles_x, tiles_y);
+    if (tiles_x * tiles_y == 0) return VS_OK;
+    photo_sums_kernel<<<(unsigned)(n * tiles_x * tiles_y), 256, 0, s>>>(
+        prev, next, frame_stride, width, height, pitch, theta, theta_stride, nullptr, cx, cy, rho, omega->x0, omega->y0,
+        omega->x1, omega->y1, need_grad != 0, out, VS_PHOTO_SUMS, tiles_x, tiles_y);
+    return vs::check_launch("vs_photometric_sums");
+}
+
+}  // namespace
+
+extern "C" int vs_photometric_fwd(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width,
+                                  int32_t height, int32_t pitch, int32_t n, const double* theta, int64_t theta_stride,
+                                  double cx, double cy, double rho, const vs_rect* omega, double* sums, void* stream)
+{
+    return photometric_sums(prev, next, frame_stride, width, height, pitch, n, theta, theta_stride, cx, cy, rho, omega, 0,
+                            sums, stream);
+}
+
+extern "C" int vs_photometric_bwd(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width,
+                                  int32_t height, int32_t pitch, int32_t n, const double* theta, int64_t theta_stride,
+                                  double cx, double cy, double rho, const vs_rect* omega, double* sums, void* stream)
+{
+    return photometric_sums(prev, next, frame_stride, width, height, pitch, n, theta, theta_stride, cx, cy, rho, omega, 1,
+                            sums, stream);
+}
+
+extern "C" int vs_photometric_features(const uint8_t* prev, const uint8_t* next, int32_t width, int32_t height,
+                                       int32_t pitch, const float* u, const float* d, int32_t m, int32_t win_half,
+                                       double* loss, double* grad, void* stream)
+{
+    if (m < 0 || width <= 0 || height <= 0 || pitch < width)
+        return vs::set_error(VS_ERR_INVALID, "vs_photometric_features: bad size");
+    if (win_half < 0 || win_half > 31) return vs::set_error(VS_ERR_INVALID, "vs_photometric_features: win_half 0..31");
+    if (m == 0) return VS_OK;
+    if (!prev || !next || !u || !d || !loss) return vs::set_error(VS_ERR_INVALID, "vs_photometric_features: null argument");
+    photo_feature_kernel<<<m, 64, 0, vs::as_stream(stream)>>>(prev, next, width, height, pitch, u, d, win_half, loss, grad);
+    return vs::check_launch("vs_photometric_features");
+}
+
+extern "C" size_t vs_photometric_workspace(int32_t n)
+{
+    return n <= 0 ? 0 : sizeof(PhotoState) * (size_t)n;
+}
+
+extern "C" int vs_photometric_refine(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width,
+                                     int32_t height, int32_t pitch, int32_t n, const double* theta0, double* theta_out,
+                                     int64_t theta_stride, double cx, double cy, double rho, const vs_rect* omega,
+                                     int32_t max_steps, double* loss_out, int32_t* accepted, void* workspace,
+                                     size_t ws_bytes, void* stream)
+{
+    int e = check_common(prev, next, width, height, pitch, n, frame_stride, omega, "vs_photometric_refine");
+    if (e) return e;
+    if (n == 0) return VS_OK;
+    if (!theta0 || !theta_out || !workspace) return vs::set_error(VS_ERR_INVALID, "vs_photometric_refine: null argument");
+    if (n > 1 && theta_stride < 4) return vs::set_error(VS_ERR_INVALID, "vs_photometric_refine: theta stride < 4");
+    if (max_steps < 0 || max_steps > 100) return vs::set_error(VS_ERR_INVALID, "vs_photometric_refine: max_steps 0..100");
+    if (!(rho > 0.0)) return vs::set_error(VS_ERR_INVALID, "vs_photometric_refine: rho must be positive");
+    if (ws_bytes < vs_photometric_workspace(n))
+        return vs::set_error(VS_ERR_WORKSPACE, "vs_photometric_refine: workspace %zu < %zu", ws_bytes, vs_photometric_workspace(n));
+    if (reinterpret_cast<uintptr_t>(workspace) & 7)
+        return vs::set_error(VS_ERR_INVALID, "vs_photometric_refine: workspace must be 8-byte aligned");
+    hipStream_t s = vs::as_stream(stream);
+    PhotoState* st = static_cast<PhotoState*>(workspace);
+    const int nb = (n + 63) / 64;
+    int tiles_x, tiles_y;
+    sums_grid(omega, tiles_x, tiles_y);
+    refine_init_kernel<<<nb, 64, 0, s>>>(st, theta0, theta_stride, n);
+    if ((e = vs::check_launch("vs_photometric_refine(init)"))) return e;
+    auto pass = [&]() -> int {
+        if (tiles_x * tiles_y == 0) return VS_OK;
+        photo_sums_kernel<<<(unsigned)(n * tiles_x * tiles_y), 256, 0, s>>>(
+            prev, next, frame_stride, width, height, pitch, nullptr, 0, st, cx, cy, rho, omega->x0, omega->y0, omega->x1,
+            omega->y1, 1, nullptr, 0, tiles_x, tiles_y);
+        return vs::check_launch("vs_photometric_refine(sums)");
+    };
+    if ((e = pass())) return e;
+    refine_first_kernel<<<nb, 64, 0, s>>>(st, n);
+    if ((e = vs::check_launch("vs_photometric_refine(first)"))) return e;
+    for (int step = 0; step < max_steps; ++step) {
+        if ((e = pass())) return e;
+        refine_step_kernel<<<nb, 64, 0, s>>>(st, n, step == max_steps - 1);
+        if ((e = vs::check_launch("vs_photometric_refine(step)"))) return e;
+    }
+    refine_out_kernel<<<nb, 64, 0, s>>>(st, n, theta_out, theta_stride, loss_out, accepted);
+    return vs::check_launch("vs_photometric_refine(out)");
+}

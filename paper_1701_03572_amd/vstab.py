@@ -56,6 +56,13 @@ class vs_fit_info(C.Structure):
                 ("decided_here", C.c_int32), ("pad", C.c_int32), ("err_rigid", C.c_double), ("err_sim", C.c_double)]
 
 
+class vs_rect(C.Structure):
+    _fields_ = [("x0", C.c_int32), ("y0", C.c_int32), ("x1", C.c_int32), ("y1", C.c_int32)]
+
+
+VS_PHOTO_SUMS = 19
+
+
 class vs_smooth_params(C.Structure):
     _fields_ = [("mode", C.c_int32), ("radius", C.c_int32), ("kalman_ratio", C.c_double), ("crop", C.c_double),
                 ("cx", C.c_double), ("cy", C.c_double)]
@@ -86,6 +93,16 @@ _SIGS = {
                                        _P, _P, _P]),
     "vs_warp_frame": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64,
                                 C.c_int32, C.c_int32, C.c_int32, _P]),
+    "vs_photometric_fwd": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64,
+                                     C.c_double, C.c_double, C.c_double, C.POINTER(vs_rect), _P, _P]),
+    "vs_photometric_bwd": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64,
+                                     C.c_double, C.c_double, C.c_double, C.POINTER(vs_rect), _P, _P]),
+    "vs_photometric_features": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.c_int32, _P, _P, C.c_int32, C.c_int32, _P,
+                                          _P, _P]),
+    "vs_photometric_workspace": (C.c_size_t, [C.c_int32]),
+    "vs_photometric_refine": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P,
+                                        C.c_int64, C.c_double, C.c_double, C.c_double, C.POINTER(vs_rect), C.c_int32,
+                                        _P, _P, _P, C.c_size_t, _P]),
     "vs_last_error": (C.c_char_p, []),
     "vs_version": (C.c_int, []),
 }
@@ -211,6 +228,39 @@ def vs_warp_frame(src, src_stride: int, width: int, height: int, src_pitch: int,
                   dst_stride: int, dst_pitch: int, n: int, border: int = 0, stream=None):
     _check(load().vs_warp_frame(_ptr(src), src_stride, width, height, src_pitch, _ptr(mats), mat_stride, _ptr(dst),
                                 dst_stride, dst_pitch, n, border, _stream(stream)), "vs_warp_frame")
+
+
+def vs_photometric_fwd(prev, nxt, frame_stride: int, width: int, height: int, pitch: int, n: int, theta,
+                       theta_stride: int, cx: float, cy: float, rho: float, omega: vs_rect, sums, stream=None):
+    _check(load().vs_photometric_fwd(_ptr(prev), _ptr(nxt), frame_stride, width, height, pitch, n, _ptr(theta),
+                                     theta_stride, cx, cy, rho, C.byref(omega), _ptr(sums), _stream(stream)),
+           "vs_photometric_fwd")
+
+
+def vs_photometric_bwd(prev, nxt, frame_stride: int, width: int, height: int, pitch: int, n: int, theta,
+                       theta_stride: int, cx: float, cy: float, rho: float, omega: vs_rect, sums, stream=None):
+    _check(load().vs_photometric_bwd(_ptr(prev), _ptr(nxt), frame_stride, width, height, pitch, n, _ptr(theta),
+                                     theta_stride, cx, cy, rho, C.byref(omega), _ptr(sums), _stream(stream)),
+           "vs_photometric_bwd")
+
+
+def vs_photometric_features(prev, nxt, width: int, height: int, pitch: int, u, d, m: int, win_half: int, loss,
+                            grad=None, stream=None):
+    _check(load().vs_photometric_features(_ptr(prev), _ptr(nxt), width, height, pitch, _ptr(u), _ptr(d), m, win_half,
+                                          _ptr(loss), _ptr(grad), _stream(stream)), "vs_photometric_features")
+
+
+def vs_photometric_workspace(n: int) -> int:
+    return int(load().vs_photometric_workspace(n))
+
+
+def vs_photometric_refine(prev, nxt, frame_stride: int, width: int, height: int, pitch: int, n: int, theta0,
+                          theta_out, theta_stride: int, cx: float, cy: float, rho: float, omega: vs_rect,
+                          max_steps: int, loss_out, accepted, workspace, ws_bytes: int, stream=None):
+    _check(load().vs_photometric_refine(_ptr(prev), _ptr(nxt), frame_stride, width, height, pitch, n, _ptr(theta0),
+                                        _ptr(theta_out), theta_stride, cx, cy, rho, C.byref(omega), max_steps,
+                                        _ptr(loss_out), _ptr(accepted), _ptr(workspace), ws_bytes, _stream(stream)),
+           "vs_photometric_refine")
 
 
 def fit_info_to_dicts(info_bytes: torch.Tensor) -> list:
