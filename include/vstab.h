@@ -269,14 +269,21 @@ int vs_photometric_features(const uint8_t* prev, const uint8_t* next, int32_t wi
 /* Gauss-Newton refinement of n pairs from theta0: each step solves (J^T J) delta = -J^T r at the
  * current parameters and accepts theta + delta only if the loss decreases; a pair stops at its first
  * rejected step, when J^T J is not positive definite, or after max_steps (0..100) accepted steps.
- * Outputs (device): theta_out[i * theta_stride + 0..3], loss_out[i][2] = (initial, final) (may be NULL),
- * accepted[i] = accepted steps (may be NULL). workspace: at least vs_photometric_workspace(n) bytes,
- * 8-byte aligned; no state survives the call. */
+ * param_kind VS_PHOTO_THETA: theta0/theta_out hold theta; VS_PHOTO_FIT: they hold fitted similarities
+ * (A, B, TX, TY) in centred coordinates (converted with the rho given). skip (may be NULL, device):
+ * pair i is left unchanged (loss_out 0, accepted 0) when skip[i * skip_stride] != 0; this accepts the
+ * `skipped` field of vs_fit_info records (skip = &info[0].skipped, skip_stride = sizeof(vs_fit_info) / 4).
+ * Outputs (device): theta_out[i * theta_stride + 0..3] (may alias theta0), loss_out[i][2] = (initial,
+ * final) (may be NULL), accepted[i] = accepted steps (may be NULL). workspace: at least
+ * vs_photometric_workspace(n) bytes, 8-byte aligned; no state survives the call. */
+#define VS_PHOTO_THETA 0
+#define VS_PHOTO_FIT 1
 size_t vs_photometric_workspace(int32_t n);
 int vs_photometric_refine(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width, int32_t height,
                           int32_t pitch, int32_t n, const double* theta0, double* theta_out, int64_t theta_stride,
-                          double cx, double cy, double rho, const vs_rect* omega, int32_t max_steps, double* loss_out,
-                          int32_t* accepted, void* workspace, size_t ws_bytes, void* stream);
+                          int32_t param_kind, const int32_t* skip, int64_t skip_stride, double cx, double cy, double rho,
+                          const vs_rect* omega, int32_t max_steps, double* loss_out, int32_t* accepted, void* workspace,
+                          size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------------
  * misc */

@@ -349,6 +349,13 @@ def stabilize(frames: np.ndarray, P, warp_frames: bool = True, max_pairs: int | 
         nxt, status, fb_err, iters = track_lk(pyr_prev, pyr_next, pts, alive, P.win_half, P.max_iter, P.eps,
                                               P.min_eig, P.fb, P.fb_thresh)
         prm, info, inl = fit_pair(pts, nxt, status, fp, j - 1, st)
+        steps = getattr(P, "photometric_steps", 0)
+        if steps > 0 and not info["skipped"]:
+            # optional photometric refinement of the fitted similarity (O-7), in its (a, b, tx, ty) form
+            m = P.photometric_margin if getattr(P, "photometric_margin", None) is not None else max(16, min(W, H) // 10)
+            th, _, _ = photo_refine(frames[j - 1], frames[j], theta_from_fit(prm, W, H), (m, m, W - m, H - m), steps)
+            rho = photo_frame(W, H)[2]
+            prm = np.array([1.0 + th[0] / rho, th[1] / rho, th[2], th[3]])
         out["pair_params"][j - 1] = prm
         out["info"].append(info)
         out["tracks"].append({"src": pts.copy(), "dst": nxt, "status": status, "fb_err": fb_err, "iters": iters,

@@ -200,16 +200,25 @@ __device__ void propose(PhotoState& s)
     for (int k = 0; k < NACC; ++k) s.nxt[k] = 0.0;
 }
 
-// start: theta = theta0, candidate = theta0 (its pass gives the sums at theta0)
-__global__ void refine_init_kernel(PhotoState* st, const double* theta0, int64_t tstride, int n)
+// start: theta = theta0, candidate = theta0 (its pass gives the sums at theta0). With fit_kind the
+// inputs are fitted similarities (A, B, TX, TY) in centred coordinates: theta = (rho (A-1), rho B, TX, TY).
+// Pairs whose skip flag is set are stopped before any pass and keep their parameters.
+__global__ void refine_init_kernel(PhotoState* st, const double* theta0, int64_t tstride, int n, int fit_kind, double rho,
+                                   const int32_t* skip, int64_t skip_stride)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     PhotoState& s = st[i];
-    for (int k = 0; k < 4; ++k) s.theta[k] = s.cand[k] = theta0[i * tstride + k];
+    const double* p = theta0 + i * tstride;
+    double th[4] = {p[0], p[1], p[2], p[3]};
+    if (fit_kind) {
+        th[0] = rho * (p[0] - 1.0);
+        th[1] = rho * p[1];
+    }
+    for (int k = 0; k < 4; ++k) s.theta[k] = s.cand[k] = th[k];
     for (int k = 0; k < NACC; ++k) s.cur[k] = s.nxt[k] = 0.0;
     s.loss0 = 0.0;
-    s.stopped = 0;
+    s.stopped = (skip != nullptr && skip[i * skip_stride] != 0) ? 1 : 0;
     s.accepted = 0;
 }
 
@@ -219,6 +228,7 @@ __global__ void refine_first_kernel(PhotoState* st, int n)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     PhotoState& s = st[i];
+    if (s.stopped) return;
     for (int k = 0; k < NACC; ++k) s.cur[k] = s.nxt[k];
     s.loss0 = s.cur[0];
     propose(s);
@@ -246,12 +256,17 @@ __global__ void refine_step_kernel(PhotoState* st, int n, int last)
 }
 
 __global__ void refine_out_kernel(const PhotoState* st, int n, double* theta_out, int64_t tstride, double* loss_out,
-                                  int32_t* accepted)
+                                  int32_t* accepted, int fit_kind, double rho)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const PhotoState& s = st[i];
-    for (int k = 0; k < 4; ++k) theta_out[i * tstride + k] = s.theta[k];
+    double* o = theta_out + i * tstride;
+    for (int k = 0; k < 4; ++k) o[k] = s.theta[k];
+    if (fit_kind) {
+        o[0] = 1.0 + s.theta[0] / rho;
+        o[1] = s.theta[1] / rho;
+    }
     if (loss_out) {
         loss_out[2 * i] = s.loss0;
         loss_out[2 * i + 1] = s.cur[0];
@@ -376,9 +391,9 @@ extern "C" size_t vs_photometric_workspace(int32_t n)
 
 extern "C" int vs_photometric_refine(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width,
                                      int32_t height, int32_t pitch, int32_t n, const double* theta0, double* theta_out,
-                                     int64_t theta_stride, double cx, double cy, double rho, const vs_rect* omega,
-                                     int32_t max_steps, double* loss_out, int32_t* accepted, void* workspace,
-                                     size_t ws_bytes, void* stream)
+                                     int64_t theta_stride, int32_t param_kind, const int32_t* skip, int64_t skip_stride,
+                                     double cx, double cy, double rho, const vs_rect* omega, int32_t max_steps,
+                                     double* loss_out, int32_t* accepted, void* workspace, size_t ws_bytes, void* stream)
 {
     int e = check_common(prev, next, width, height, pitch, n, frame_stride, omega, "vs_photometric_refine");
     if (e) return e;
@@ -386,6 +401,8 @@ extern "C" int vs_photometric_refine(const uint8_t* prev, const uint8_t* next, i
     if (!theta0 || !theta_out || !workspace) return vs::set_error(VS_ERR_INVALID, "vs_photometric_refine: null argument");
     if (n > 1 && theta_stride < 4) return vs::set_error(VS_ERR_INVALID, "vs_photometric_refine: theta stride < 4");
     if (max_steps < 0 || max_steps > 100) return vs::set_error(VS_ERR_INVALID, "vs_photometric_refine: max_steps 0..100");
+    if (param_kind != VS_PHOTO_THETA && param_kind != VS_PHOTO_FIT)
+        return vs::set_error(VS_ERR_INVALID, "vs_photometric_refine: unknown param_kind");
     if (!(rho > 0.0)) return vs::set_error(VS_ERR_INVALID, "vs_photometric_refine: rho must be positive");
     if (ws_bytes < vs_photometric_workspace(n))
         return vs::set_error(VS_ERR_WORKSPACE, "vs_photometric_refine: workspace %zu < %zu", ws_bytes, vs_photometric_workspace(n));
@@ -396,7 +413,8 @@ extern "C" int vs_photometric_refine(const uint8_t* prev, const uint8_t* next, i
     const int nb = (n + 63) / 64;
     int tiles_x, tiles_y;
     sums_grid(omega, tiles_x, tiles_y);
-    refine_init_kernel<<<nb, 64, 0, s>>>(st, theta0, theta_stride, n);
+    const int fit_kind = param_kind == VS_PHOTO_FIT;
+    refine_init_kernel<<<nb, 64, 0, s>>>(st, theta0, theta_stride, n, fit_kind, rho, skip, skip_stride);
     if ((e = vs::check_launch("vs_photometric_refine(init)"))) return e;
     auto pass = [&]() -> int {
         if (tiles_x * tiles_y == 0) return VS_OK;
@@ -413,6 +431,6 @@ extern "C" int vs_photometric_refine(const uint8_t* prev, const uint8_t* next, i
         refine_step_kernel<<<nb, 64, 0, s>>>(st, n, step == max_steps - 1);
         if ((e = vs::check_launch("vs_photometric_refine(step)"))) return e;
     }
-    refine_out_kernel<<<nb, 64, 0, s>>>(st, n, theta_out, theta_stride, loss_out, accepted);
+    refine_out_kernel<<<nb, 64, 0, s>>>(st, n, theta_out, theta_stride, loss_out, accepted, fit_kind, rho);
     return vs::check_launch("vs_photometric_refine(out)");
 }

@@ -39,11 +39,16 @@ class StabParams:
     kalman_ratio: float = 0.02
     crop: float = 0.0
     border: int = 0
+    photometric_steps: int = 0     # Gauss-Newton photometric refinement of each fitted pair (0: off)
+    photometric_margin: int | None = None   # None: max(16, min(W, H) // 10)
 
     def roi(self, w: int, h: int) -> tuple[int, int]:
         mx = self.roi_mx if self.roi_mx is not None else max(16, w // 20)
         my = self.roi_my if self.roi_my is not None else max(16, h // 20)
         return mx, my
+
+    def photo_margin(self, w: int, h: int) -> int:
+        return self.photometric_margin if self.photometric_margin is not None else max(16, min(w, h) // 10)
 
     def replace(self, **kw) -> "StabParams":
         return dataclasses.replace(self, **kw)

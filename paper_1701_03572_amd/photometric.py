@@ -101,7 +101,8 @@ def refine(prev, nxt, theta0, omega, max_steps: int = 5):
     acc = torch.empty(n, dtype=torch.int32, device=prev.device)
     wsb = V.vs_photometric_workspace(n)
     ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=prev.device)
-    V.vs_photometric_refine(prev, nxt, W * H, W, H, W, n, th0, out, 4, cx, cy, rho, omega, max_steps, loss, acc, ws, wsb)
+    V.vs_photometric_refine(prev, nxt, W * H, W, H, W, n, th0, out, 4, V.VS_PHOTO_THETA, None, 0, cx, cy, rho, omega,
+                            max_steps, loss, acc, ws, wsb)
     return out, loss, acc
 
 

@@ -43,6 +43,31 @@ def _smooth_params(P: StabParams, w: int, h: int) -> V.vs_smooth_params:
     return V.vs_smooth_params(P.smooth_mode, P.radius, P.kalman_ratio, P.crop, (w - 1) / 2.0, (h - 1) / 2.0)
 
 
+class _PhotoRefiner:
+    """Buffers and arguments of the optional photometric refinement of fitted pairs (in place, in
+    the fit's (a, b, tx, ty) format; pairs the fit skipped stay unchanged)."""
+
+    def __init__(self, P: StabParams, w: int, h: int, n_pairs_max: int, device):
+        self.steps = P.photometric_steps
+        self.W, self.H = w, h
+        m = P.photo_margin(w, h)
+        self.omega = V.vs_rect(m, m, w - m, h - m)
+        self.cx, self.cy, self.rho = (w - 1) / 2.0, (h - 1) / 2.0, max(w, h) / 2.0
+        n = max(n_pairs_max, 1)
+        self.loss = torch.zeros((n, 2), dtype=torch.float64, device=device)
+        self.accepted = torch.zeros(n, dtype=torch.int32, device=device)
+        self.ws_bytes = V.vs_photometric_workspace(n)
+        self.ws = _bytes(self.ws_bytes, device)
+
+    def __call__(self, prev, nxt, frame_stride: int, n: int, pair_params, info, first_pair: int = 0):
+        if self.steps <= 0 or n <= 0:
+            return
+        skip = info.data_ptr() + first_pair * V.FIT_INFO_BYTES + V.FIT_INFO_SKIPPED_OFFSET
+        V.vs_photometric_refine(prev, nxt, frame_stride, self.W, self.H, self.W, n, pair_params, pair_params, 4,
+                                V.VS_PHOTO_FIT, skip, V.FIT_INFO_BYTES // 4, self.cx, self.cy, self.rho, self.omega,
+                                self.steps, self.loss, self.accepted, self.ws, self.ws_bytes)
+
+
 def _bytes(n: int, device) -> torch.Tensor:
     return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
 
@@ -87,6 +112,7 @@ class SequenceStabilizer:
         self._dp = _detect_params(P, width, height)
         self._fp = _fit_params(P, width, height)
         self._sp = _smooth_params(P, width, height)
+        self.refine_pairs = _PhotoRefiner(P, width, height, n - 1, dev)
 
     def run(self, frames: torch.Tensor, warp: bool = True, lk_events: list | None = None) -> None:
         """Stabilize frames [n, H, W] (uint8, resident on the device). Results stay in the
@@ -134,6 +160,7 @@ class SequenceStabilizer:
             V.vs_fit_state_init(self.fit_state)
             V.vs_fit_similarity(self.src, self.dst, self.status, cap, n_pairs, self._fp, 0, self.fit_state,
                                 self.pair_params, self.info, self.inliers, self.fit_ws, self.fit_ws_bytes)
+            self.refine_pairs(f0, f0 + fs, fs, n_pairs, self.pair_params, self.info)
         V.vs_traj_state_init(self.traj_state)
         V.vs_smooth_trajectory(self.pair_params if n_pairs >= 1 else None, n_pairs, 1, self._sp, self.traj_state,
                                self.mats, n, self.n_emitted, self.first)
@@ -197,6 +224,7 @@ class Stabilizer:
         self._dp = _detect_params(P, width, height)
         self._fp = _fit_params(P, width, height)
         self._sp = _smooth_params(P, width, height)
+        self.refine_pair = _PhotoRefiner(P, width, height, 1, dev)
         self.reset()
 
     def reset(self):
@@ -243,6 +271,7 @@ class Stabilizer:
                           self.n_valid, self.pts[cur], self.alive[cur])
             V.vs_fit_similarity(self.pts[prev], self.dst, self.status, self.cap, 1, self._fp, j - 1, self.fit_state,
                                 self.pair_params, self.info, self.inliers, self.fit_ws, self.fit_ws_bytes)
+            self.refine_pair(self.frames[j - 1], frame, 0, 1, self.pair_params, self.info)
             self._detect(frame, cur, gated=(j % self.P.redetect_every != 0))
             V.vs_smooth_trajectory(self.pair_params, 1, 0, self._sp, self.traj_state, self.mats, self.mats_cap,
                                    self.n_emitted, self.first)

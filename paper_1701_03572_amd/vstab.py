@@ -69,6 +69,7 @@ class vs_smooth_params(C.Structure):
 
 
 FIT_INFO_BYTES = C.sizeof(vs_fit_info)
+FIT_INFO_SKIPPED_OFFSET = vs_fit_info.skipped.offset
 FIT_STATE_BYTES = C.sizeof(vs_fit_state)
 
 # numpy/torch view of vs_fit_info records
@@ -101,8 +102,8 @@ _SIGS = {
                                           _P, _P]),
     "vs_photometric_workspace": (C.c_size_t, [C.c_int32]),
     "vs_photometric_refine": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P,
-                                        C.c_int64, C.c_double, C.c_double, C.c_double, C.POINTER(vs_rect), C.c_int32,
-                                        _P, _P, _P, C.c_size_t, _P]),
+                                        C.c_int64, C.c_int32, _P, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                        C.POINTER(vs_rect), C.c_int32, _P, _P, _P, C.c_size_t, _P]),
     "vs_last_error": (C.c_char_p, []),
     "vs_version": (C.c_int, []),
 }
@@ -254,13 +255,17 @@ def vs_photometric_workspace(n: int) -> int:
     return int(load().vs_photometric_workspace(n))
 
 
+VS_PHOTO_THETA, VS_PHOTO_FIT = 0, 1
+
+
 def vs_photometric_refine(prev, nxt, frame_stride: int, width: int, height: int, pitch: int, n: int, theta0,
-                          theta_out, theta_stride: int, cx: float, cy: float, rho: float, omega: vs_rect,
-                          max_steps: int, loss_out, accepted, workspace, ws_bytes: int, stream=None):
+                          theta_out, theta_stride: int, param_kind: int, skip, skip_stride: int, cx: float, cy: float,
+                          rho: float, omega: vs_rect, max_steps: int, loss_out, accepted, workspace, ws_bytes: int,
+                          stream=None):
     _check(load().vs_photometric_refine(_ptr(prev), _ptr(nxt), frame_stride, width, height, pitch, n, _ptr(theta0),
-                                        _ptr(theta_out), theta_stride, cx, cy, rho, C.byref(omega), max_steps,
-                                        _ptr(loss_out), _ptr(accepted), _ptr(workspace), ws_bytes, _stream(stream)),
-           "vs_photometric_refine")
+                                        _ptr(theta_out), theta_stride, param_kind, _ptr(skip), skip_stride, cx, cy,
+                                        rho, C.byref(omega), max_steps, _ptr(loss_out), _ptr(accepted),
+                                        _ptr(workspace), ws_bytes, _stream(stream)), "vs_photometric_refine")
 
 
 def fit_info_to_dicts(info_bytes: torch.Tensor) -> list:

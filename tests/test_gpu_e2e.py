@@ -137,3 +137,34 @@ def test_full_size_workload_sampled():
         st.push(frames[j])
     st.flush()
     torch.cuda.synchronize()
+
+
+def test_photometric_refinement_in_both_paths():
+    """Optional Gauss-Newton photometric refinement of each fitted pair (an extension): both paths and
+    the oracle agree, pairs the fit skipped are left unchanged, and the refined loss never exceeds the
+    initial one. The refinement's sums use FP64 atomics, so the paths agree to rounding, not bitwise."""
+    sq = synth.make_sequence("tiny", n_frames=14)
+    frames = sq.frames.copy()
+    frames[6] = 90                                    # forces two skipped pairs
+    P = params.PRESETS["tiny"].replace(photometric_steps=3)
+    seq, seq_out, stream_out, ss, st = run_both_paths(frames, P)
+    h, w = frames.shape[1:]
+    base = SequenceStabilizer(w, h, 14, params.PRESETS["tiny"])
+    base.run(dev(frames), warp=False)
+    torch.cuda.synchronize()
+    unrefined = base.pair_params[:13].cpu().numpy()
+    ref = O.stabilize(frames, P, warp_frames=False)
+    loss = ss.refine_pairs.loss[:13].cpu().numpy()
+    acc = ss.refine_pairs.accepted[:13].cpu().numpy()
+    for p in range(13):
+        assert seq["info"][p]["skipped"] == ref["info"][p]["skipped"]
+        if seq["info"][p]["skipped"]:
+            np.testing.assert_array_equal(seq["pair_params"][p], unrefined[p])
+            assert acc[p] == 0
+            continue
+        assert loss[p, 1] <= loss[p, 0]
+        assert transform_err(seq["pair_params"][p], ref["pair_params"][p], w, h) < 0.02
+    say("accepted steps", acc.tolist())
+    assert acc.sum() > 0
+    d = np.abs(stream_out.astype(int) - seq_out.astype(int))
+    assert d.max() <= 1 and (d > 0).mean() < 1e-4

@@ -137,6 +137,7 @@ def test_empty_omega_and_bad_arguments():
     with pytest.raises(V.VsError):
         V.vs_photometric_bwd(f, f, w * h, w, h, w, 1, theta, 4, cx, cy, rho, V.vs_rect(-1, 0, 10, 10), out)
     with pytest.raises(V.VsError):
-        V.vs_photometric_refine(f, f, w * h, w, h, w, 1, theta, theta.clone(), 4, cx, cy, rho, V.vs_rect(4, 4, 60, 44),
-                                5, None, None, torch.empty(8, dtype=torch.uint8, device="cuda"), 8)
+        V.vs_photometric_refine(f, f, w * h, w, h, w, 1, theta, theta.clone(), 4, V.VS_PHOTO_THETA, None, 0, cx, cy, rho,
+                                V.vs_rect(4, 4, 60, 44), 5, None, None, torch.empty(8, dtype=torch.uint8, device="cuda"),
+                                8)
     V.vs_photometric_fwd(f, f, w * h, w, h, w, 0, theta, 4, cx, cy, rho, V.vs_rect(4, 4, 60, 44), out)   # n = 0: no-op
