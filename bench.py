@@ -60,6 +60,53 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def run_batched(n_streams: int, n_frames: int, steps: int, warmup: int) -> dict:
+    """Heterogeneous batch: n_streams independent streams of mixed resolution (320x240 .. 1920x1080),
+    corner budget U[100, 2000] and 3-5 levels, all frames resident; one step stabilizes every frame of
+    every stream. Timed eagerly and as a replayed HIP graph of the same step."""
+    import torch
+    from paper_1701_03572_amd import params, synth
+    from paper_1701_03572_amd.batch import MultiStabilizer, StreamSpec
+
+    specs, frames = [], []
+    for s, (r, k, levels) in enumerate(synth.mixed_streams(n_streams, n_frames)):
+        P = params.PRESETS["vga"].replace(levels=levels, max_corners=k, stream_id=s)
+        specs.append(StreamSpec(r.width, r.height, n_frames, P))
+        frames.append(synth.make_sequence(r, n_frames=n_frames, device="cuda").frames.contiguous())
+    ms = MultiStabilizer(specs)
+    for i, f in enumerate(frames):
+        ms.load(i, f)
+    del frames
+    total = ms.frames_total()
+
+    def timed(fn, k):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(k):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k
+
+    for _ in range(max(warmup, 1)):
+        ms.run()
+    eager_ms = timed(ms.run, steps)
+    ms.capture_graph()
+    ms.replay()
+    graph_ms = timed(ms.replay, steps)
+    res = {"workload": "%d streams x %d frames, resolution U{320x240, 640x480, 1280x720, 1920x1080}, corners "
+                       "U[100, 2000], levels clamp(1 + floor(log2(W / 80)), 3, 5); Kalman smoothing" % (n_streams, n_frames),
+           "streams": n_streams, "frames": total, "classes": len(ms.classes),
+           "ms_per_step_eager": round(eager_ms, 4), "frames_per_s_eager": round(total / (eager_ms / 1e3), 1),
+           "ms_per_step_graph": round(graph_ms, 4), "frames_per_s_graph": round(total / (graph_ms / 1e3), 1)}
+    log("batched: %d streams, %d frames: eager %.2f ms/step (%.0f frames/s), graph %.2f ms/step (%.0f frames/s)" %
+        (n_streams, total, eager_ms, res["frames_per_s_eager"], graph_ms, res["frames_per_s_graph"]))
+    del ms
+    torch.cuda.empty_cache()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +116,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=6)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-streams", type=int, default=64)
+    ap.add_argument("--batched-frames", type=int, default=120)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one elementwise kernel that reads and writes exactly 256 MiB (torch neg of "
                          "float32), the reference for scaling hardware byte counters")
@@ -185,6 +235,10 @@ def main() -> int:
         log("plain path: %.0f frames/s, latency p50 %.3f ms p99 %.3f ms" % (plain_fps, plain["latency_ms_p50"],
                                                                            plain["latency_ms_p99"]))
 
+    batched = None
+    if not args.no_batched:
+        batched = run_batched(args.batched_streams, args.batched_frames, args.steps, args.warmup)
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -217,6 +271,7 @@ def main() -> int:
                    "path": "sequence (segment-parallel, one launch per stage per 5-frame step)",
                    "frames": n, "width": W, "height": H, "corners": P.max_corners, "levels": P.levels},
         "plain_path": plain,
+        "batched": batched,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -93,6 +93,9 @@ typedef struct {
     double quality;
     int32_t min_dist;
     int32_t roi_mx, roi_my;
+    /* optional (device, may be NULL): item i accepts at most min(max_corners_per_item[i], max_corners)
+     * corners; lets one call serve items of different corner budgets */
+    const int32_t* max_corners_per_item;
 } vs_detect_params;
 
 size_t vs_detect_workspace(int32_t width, int32_t height, int32_t n);

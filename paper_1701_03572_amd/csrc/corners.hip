@@ -409,15 +409,22 @@ __device__ __forceinline__ bool before(uint64_t ka, uint32_t ia, uint64_t kb, ui
 }
 
 __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_t item_bytes, int W, int H,
-                                                             int istride, const int32_t* gate, int gate_min, int K,
-                                                             double quality, int min_dist, int capacity,
-                                                             float* __restrict__ xy_out, double* __restrict__ score_out,
+                                                             int istride, const int32_t* gate, int gate_min, int Kmax,
+                                                             const int32_t* k_items, double quality, int min_dist,
+                                                             int capacity, float* __restrict__ xy_out,
+                                                             double* __restrict__ score_out,
                                                              int32_t* __restrict__ count_out,
                                                              uint8_t* __restrict__ alive_out)
 {
     const int item = blockIdx.x;
     const int64_t rec = (int64_t)item * istride;
     if (gated_off(gate, gate_min, rec)) return;
+    // per-item corner budget, clamped to [0, Kmax]
+    int K = Kmax;
+    if (k_items) {
+        const int k = k_items[item];
+        K = k < 0 ? 0 : (k < Kmax ? k : Kmax);
+    }
     __shared__ uint64_t bkey[CAP];
     __shared__ uint32_t bidx[CAP];
     __shared__ uint32_t hist[NBIN];
@@ -690,7 +697,8 @@ extern "C" int vs_detect_corners(const uint8_t* frames, int64_t frame_stride, in
                                                    istride, gate, gate_min, w8, ib);
     e = vs::check_launch("vs_detect_corners(keys)");
     if (e) return e;
-    corner_select_kernel<<<n, 1024, 0, s>>>(w8, ib, width, height, istride, gate, gate_min, p->max_corners, p->quality,
+    corner_select_kernel<<<n, 1024, 0, s>>>(w8, ib, width, height, istride, gate, gate_min, p->max_corners,
+                                            p->max_corners_per_item, p->quality,
                                             p->min_dist, capacity, xy, score, count, alive);
     return vs::check_launch("vs_detect_corners(select)");
 }

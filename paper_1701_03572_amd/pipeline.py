@@ -29,9 +29,11 @@ def _lk_params(P: StabParams) -> V.vs_lk_params:
     return V.vs_lk_params(P.win_half, P.max_iter, P.eps, P.min_eig, int(P.fb), P.fb_thresh)
 
 
-def _detect_params(P: StabParams, w: int, h: int) -> V.vs_detect_params:
+def _detect_params(P: StabParams, w: int, h: int, max_corners: int | None = None,
+                   k_items: torch.Tensor | None = None) -> V.vs_detect_params:
     mx, my = P.roi(w, h)
-    return V.vs_detect_params(P.max_corners, P.quality, P.min_dist, mx, my)
+    k = P.max_corners if max_corners is None else max_corners
+    return V.vs_detect_params(k, P.quality, P.min_dist, mx, my, None if k_items is None else k_items.data_ptr())
 
 
 def _fit_params(P: StabParams, w: int, h: int) -> V.vs_fit_params:

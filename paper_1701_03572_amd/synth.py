@@ -54,11 +54,32 @@ RECIPES = {
     "tiny": SeqRecipe("tiny", 320, 240, 60, "blobs", "iid", seed=1701),
     "vga": SeqRecipe("vga", 640, 480, 300, "blobs", "path", 1.0, 3, 40, seed=1702),
     "hd": SeqRecipe("hd", 1920, 1080, 600, "fbm", "path", 3.0, 3, 120, seed=1703),
+    "hd720": SeqRecipe("hd720", 1280, 720, 300, "fbm", "path", 1.0, 3, 80, seed=1704),
     "paper_forest": SeqRecipe("paper_forest", 320, 240, 1650, "blobs", "path", 1.0, 3, 40, seed=1801),
     "paper_ground": SeqRecipe("paper_ground", 640, 480, 966, "blobs", "path", 1.0, 3, 40, seed=1802),
     "paper_bird": SeqRecipe("paper_bird", 640, 360, 601, "blobs", "path", 1.0, 3, 40, seed=1803),
     "paper_girl": SeqRecipe("paper_girl", 640, 360, 446, "blobs", "path", 1.0, 3, 40, seed=1804),
 }
+
+
+# mixed-stream workload: resolution classes drawn uniformly, corner budgets U[100, 2000], levels
+# clamp(1 + floor(log2(W / 80)), 3, 5), the 640x480 workload's jitter; stream s uses seed base * 1000 + s
+MIXED_CLASSES = (("tiny", 320, 240), ("vga", 640, 480), ("hd720", 1280, 720), ("hd", 1920, 1080))
+
+
+def mixed_streams(n_streams: int, n_frames: int, base_seed: int = 1705) -> list:
+    """Per-stream (recipe, corner budget, levels) of a seeded mixed workload."""
+    rng = np.random.default_rng(base_seed)
+    out = []
+    for s in range(n_streams):
+        name, w, h = MIXED_CLASSES[int(rng.integers(0, len(MIXED_CLASSES)))]
+        k = int(rng.integers(100, 2001))
+        levels = int(min(5, max(3, 1 + math.floor(math.log2(w / 80)))))
+        base = RECIPES[name]
+        r = dataclasses.replace(base, name="%s_s%d" % (name, s), n_frames=max(n_frames, 2), motion="path", jitter=1.0,
+                                seed=base_seed * 1000 + s)
+        out.append((r, k, levels))
+    return out
 
 
 def recipe(name: str, **over) -> SeqRecipe:

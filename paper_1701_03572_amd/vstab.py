@@ -33,7 +33,7 @@ class vs_pyramid(C.Structure):
 
 class vs_detect_params(C.Structure):
     _fields_ = [("max_corners", C.c_int32), ("quality", C.c_double), ("min_dist", C.c_int32),
-                ("roi_mx", C.c_int32), ("roi_my", C.c_int32)]
+                ("roi_mx", C.c_int32), ("roi_my", C.c_int32), ("max_corners_per_item", C.c_void_p)]
 
 
 class vs_lk_params(C.Structure):
