@@ -55,6 +55,7 @@ RECIPES = {
     "vga": SeqRecipe("vga", 640, 480, 300, "blobs", "path", 1.0, 3, 40, seed=1702),
     "hd": SeqRecipe("hd", 1920, 1080, 600, "fbm", "path", 3.0, 3, 120, seed=1703),
     "hd720": SeqRecipe("hd720", 1280, 720, 300, "fbm", "path", 1.0, 3, 80, seed=1704),
+    "uhd": SeqRecipe("uhd", 3840, 2160, 120, "fbm", "path", 1.0, 3, 160, seed=1706),
     "paper_forest": SeqRecipe("paper_forest", 320, 240, 1650, "blobs", "path", 1.0, 3, 40, seed=1801),
     "paper_ground": SeqRecipe("paper_ground", 640, 480, 966, "blobs", "path", 1.0, 3, 40, seed=1802),
     "paper_bird": SeqRecipe("paper_bird", 640, 360, 601, "blobs", "path", 1.0, 3, 40, seed=1803),
