@@ -23,7 +23,7 @@ _SRC = os.path.join(_HERE, "vs_oracle.c")
 _LIB = os.path.join(_HERE, "libvs_oracle.so")
 _lib = None
 
-RIGID, SIMILARITY, HYBRID = 0, 1, 2
+RIGID, SIMILARITY, HYBRID, AFFINE, HYBRID3 = 0, 1, 2, 3, 4
 
 
 def build(force: bool = False) -> str:
@@ -54,7 +54,7 @@ class HybridState(C.Structure):
 class FitInfo(C.Structure):
     _fields_ = [("model", C.c_int32), ("n_valid", C.c_int32), ("n_inliers", C.c_int32), ("skipped", C.c_int32),
                 ("decided_here", C.c_int32), ("pad", C.c_int32), ("err_rigid", C.c_double),
-                ("err_sim", C.c_double)]
+                ("err_sim", C.c_double), ("err_affine", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
@@ -76,8 +76,10 @@ def lib():
         _lib.vso_track_lk.argtypes = [P, P, P, P, P, C.c_int, P, C.c_int, P, C.POINTER(LKParams), P, P, P, P]
         _lib.vso_draw.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int, C.c_int]
         _lib.vso_draw.restype = C.c_uint64
+        _lib.vso_draw3.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int, C.c_int]
+        _lib.vso_draw3.restype = C.c_uint64
         _lib.vso_fit_pair.argtypes = [P, P, P, C.c_int, C.POINTER(FitParams), C.c_int64, C.POINTER(HybridState), P,
-                                      C.POINTER(FitInfo), P]
+                                      P, C.POINTER(FitInfo), P]
         _lib.vso_smooth.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                                     P, P, P]
         _lib.vso_warp.argtypes = [P, C.c_int, C.c_int, C.c_int, P, P, C.c_int, C.c_int]
@@ -207,19 +209,31 @@ def new_hybrid_state() -> HybridState:
     return HybridState(-1, SIMILARITY, 0)
 
 
-def fit_pair(src, dst, valid, fp: FitParams, pair_index: int, state: HybridState | None = None):
-    """Returns (params4 (a, b, tx, ty) centred, info dict, inlier flags per slot)."""
+def draw3(seed: int, stream_id: int, pair_index: int, h: int, k: int) -> int:
+    return int(lib().vso_draw3(seed, stream_id, pair_index, h, k))
+
+
+def fit_pair_affine(src, dst, valid, fp: FitParams, pair_index: int, state: HybridState | None = None):
+    """Returns (params4 (a, b, tx, ty) centred, affine6 (a11, a12, tx, a21, a22, ty) centred, info
+    dict, inlier flags per slot). For an affine result params4 is its nearest similarity."""
     src = np.ascontiguousarray(src, np.float64).reshape(-1, 2)
     dst = np.ascontiguousarray(dst, np.float64).reshape(-1, 2)
     n = len(src)
     v = None if valid is None else np.ascontiguousarray(valid, np.uint8)
     st = state if state is not None else new_hybrid_state()
     out = np.empty(4, np.float64)
+    m6 = np.empty(6, np.float64)
     info = FitInfo()
     inl = np.empty(max(n, 1), np.uint8)
     lib().vso_fit_pair(_p(src), _p(dst), None if v is None else _p(v), n, C.byref(fp), pair_index, C.byref(st),
-                       _p(out), C.byref(info), _p(inl))
-    return out, info.as_dict(), inl[:n].copy()
+                       _p(out), _p(m6), C.byref(info), _p(inl))
+    return out, m6, info.as_dict(), inl[:n].copy()
+
+
+def fit_pair(src, dst, valid, fp: FitParams, pair_index: int, state: HybridState | None = None):
+    """Returns (params4 (a, b, tx, ty) centred, info dict, inlier flags per slot)."""
+    out, _, info, inl = fit_pair_affine(src, dst, valid, fp, pair_index, state)
+    return out, info, inl
 
 
 # ---------------------------------------------------------------------------------------------

@@ -363,7 +363,7 @@ VSO_EXPORT void vso_track_lk(const uint8_t* const* prev_lv, const uint8_t* const
  *      non-skipped pair by fitting both models and comparing the RMS over all valid pairs,
  *      rigid iff E_r < E_s; a pair with fewer than min_valid points is the identity + skipped.
  * ============================================================================================= */
-enum { VSO_RIGID = 0, VSO_SIMILARITY = 1, VSO_HYBRID = 2 };
+enum { VSO_RIGID = 0, VSO_SIMILARITY = 1, VSO_HYBRID = 2, VSO_AFFINE = 3, VSO_HYBRID3 = 4 };
 
 typedef struct {
     int32_t model;          /* VSO_RIGID, VSO_SIMILARITY or VSO_HYBRID */
@@ -390,6 +390,7 @@ typedef struct {
     int32_t decided_here;   /* 1 if this pair made the block's hybrid decision */
     int32_t pad;
     double err_rigid, err_sim;   /* RMS residuals at a decision pair, else NaN */
+    double err_affine;           /* RMS residual of the affine at a three-way decision pair, else NaN */
 } vso_fit_info;
 
 /* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): output number `ctr + 1` of the generator whose
@@ -528,12 +529,173 @@ static int robust_fit(int model, const vso_fit_params* P, int64_t pair_index, co
     return m;
 }
 
+/* ---------------------------------------------------------------------------------------------
+ * O-4b The 6-DOF affine model of Eq. 7-8 as a third candidate (a later variant of the method; the
+ *      paper's hybrid stops at 4 DOF, Section 4.1). Readings (project choices, the paper is silent):
+ *      [A|t] minimises the sum of squared residuals of Eq. 7 over the chosen points, found here
+ *      by solving the 3x3 normal equations of the row form of Eq. 8 (X = [x y 1], one system per
+ *      output row) by Gaussian elimination with partial pivoting; a point set whose centred 2x2
+ *      second-moment matrix is singular (det <= 1e-12 trace^2: collinear or coincident points)
+ *      has no unique affine and takes the similarity least-squares fit instead. RANSAC draws 3
+ *      distinct points (SplitMix64 counters with bit 15 set, so they never meet the 2-point
+ *      draws of at most 8191 hypotheses), solves the affine through them exactly (skipped when
+ *      |det| < 1 px^2), scores residuals <= threshold; at least 3 inliers are needed, else the
+ *      least-squares fit on all points. The three-way hybrid decides rigid against similarity
+ *      as the two-way one (rigid iff E_r < E_s), then takes the affine iff E_a is smaller still.
+ *      The smoother stabilises 4 DOF (Section 4.1, last paragraph): an affine pair is passed on
+ *      as its nearest similarity in the Frobenius norm, a = (a11 + a22)/2, b = (a21 - a12)/2,
+ *      with its translation unchanged.
+ * --------------------------------------------------------------------------------------------- */
+VSO_EXPORT uint64_t vso_draw3(uint64_t seed, int64_t stream_id, int64_t pair_index, int h, int k)
+{
+    const uint64_t ctr = (((uint64_t)stream_id & 0xFFFFFull) << 44) | (((uint64_t)pair_index & 0xFFFFFFFull) << 16) |
+                         0x8000u | (((uint64_t)h & 0x1FFFull) << 2) | ((uint64_t)k & 3u);
+    return splitmix64_at(seed, ctr);
+}
+
+/* m = (a11, a12, tx, a21, a22, ty): x' = a11 x + a12 y + tx, y' = a21 x + a22 y + ty, fixed order */
+static double aff_resid2(const double m[6], double x, double y, double xd, double yd)
+{
+    const double px = (m[0] * x + m[1] * y) + m[2];
+    const double py = (m[3] * x + m[4] * y) + m[5];
+    const double dx = xd - px, dy = yd - py;
+    return dx * dx + dy * dy;
+}
+
+static void sim_to_aff(const double p[4], double m[6])
+{
+    m[0] = p[0]; m[1] = -p[1]; m[2] = p[2];
+    m[3] = p[1]; m[4] = p[0];  m[5] = p[3];
+}
+
+/* Gaussian elimination with partial pivoting on a 3x3 system with two right-hand sides */
+static void solve3x2(double A[3][3], double B[3][2], double X[3][2])
+{
+    for (int c = 0; c < 3; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        for (int k = 0; k < 3; ++k) { const double t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t; }
+        for (int k = 0; k < 2; ++k) { const double t = B[c][k]; B[c][k] = B[piv][k]; B[piv][k] = t; }
+        for (int r = c + 1; r < 3; ++r) {
+            const double f = A[r][c] / A[c][c];
+            for (int k = c; k < 3; ++k) A[r][k] -= f * A[c][k];
+            for (int k = 0; k < 2; ++k) B[r][k] -= f * B[c][k];
+        }
+    }
+    for (int k = 0; k < 2; ++k)
+        for (int r = 2; r >= 0; --r) {
+            double s = B[r][k];
+            for (int j = r + 1; j < 3; ++j) s -= A[r][j] * X[j][k];
+            X[r][k] = s / A[r][r];
+        }
+}
+
+static void ls_affine(const double* xs, const double* ys, const double* xd, const double* yd, const uint8_t* mask,
+                      int n, double m[6])
+{
+    /* degeneracy from the centred second moments */
+    double sx = 0, sy = 0;
+    int cnt = 0;
+    for (int i = 0; i < n; ++i) {
+        if (mask && !mask[i]) continue;
+        sx += xs[i]; sy += ys[i]; ++cnt;
+    }
+    const double mx = sx / cnt, my = sy / cnt;
+    double cxx = 0, cxy = 0, cyy = 0;
+    for (int i = 0; i < n; ++i) {
+        if (mask && !mask[i]) continue;
+        const double x = xs[i] - mx, y = ys[i] - my;
+        cxx += x * x; cxy += x * y; cyy += y * y;
+    }
+    const double tr = cxx + cyy;
+    if (!(cxx * cyy - cxy * cxy > 1e-12 * tr * tr)) {
+        double p[4];
+        ls_fit(VSO_SIMILARITY, xs, ys, xd, yd, mask, n, p);
+        sim_to_aff(p, m);
+        return;
+    }
+    /* normal equations sum X^T X z = sum X^T y' per output row, X = [x y 1] */
+    double A[3][3] = {{0}}, B[3][2] = {{0}}, Z[3][2];
+    for (int i = 0; i < n; ++i) {
+        if (mask && !mask[i]) continue;
+        const double X[3] = {xs[i], ys[i], 1.0};
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c) A[r][c] += X[r] * X[c];
+            B[r][0] += X[r] * xd[i];
+            B[r][1] += X[r] * yd[i];
+        }
+    }
+    solve3x2(A, B, Z);
+    m[0] = Z[0][0]; m[1] = Z[1][0]; m[2] = Z[2][0];
+    m[3] = Z[0][1]; m[4] = Z[1][1]; m[5] = Z[2][1];
+}
+
+static double rms_aff(const double m[6], const double* xs, const double* ys, const double* xd, const double* yd, int n)
+{
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += aff_resid2(m, xs[i], ys[i], xd[i], yd[i]);
+    return sqrt(s / n);
+}
+
+/* robust affine fit: returns the inlier count; inl[n] receives the inlier flags */
+static int robust_affine(const vso_fit_params* P, int64_t pair_index, const double* xs, const double* ys,
+                         const double* xd, const double* yd, int n, double m[6], uint8_t* inl)
+{
+    const double tau2 = P->inlier_thresh * P->inlier_thresh;
+    int best = -1;
+    double bm[6] = {1, 0, 0, 0, 1, 0};
+    for (int h = 0; P->ransac_iters > 0 && n >= 3 && h < P->ransac_iters; ++h) {
+        const int i1 = (int)(vso_draw3(P->seed, P->stream_id, pair_index, h, 0) % (uint64_t)n);
+        int i2 = (int)(vso_draw3(P->seed, P->stream_id, pair_index, h, 1) % (uint64_t)n);
+        int i3 = (int)(vso_draw3(P->seed, P->stream_id, pair_index, h, 2) % (uint64_t)n);
+        if (i2 == i1) i2 = (i2 + 1) % n;
+        while (i3 == i1 || i3 == i2) i3 = (i3 + 1) % n;
+        /* the affine through three points: A [p2 - p1, p3 - p1] = [q2 - q1, q3 - q1] */
+        const double ex = xs[i2] - xs[i1], ey = ys[i2] - ys[i1];
+        const double fx = xs[i3] - xs[i1], fy = ys[i3] - ys[i1];
+        const double det = ex * fy - fx * ey;
+        if (!(fabs(det) >= 1.0)) continue;
+        const double gu = xd[i2] - xd[i1], gv = yd[i2] - yd[i1];
+        const double hu = xd[i3] - xd[i1], hv = yd[i3] - yd[i1];
+        double c[6];
+        c[0] = (gu * fy - hu * ey) / det;
+        c[1] = (hu * ex - gu * fx) / det;
+        c[3] = (gv * fy - hv * ey) / det;
+        c[4] = (hv * ex - gv * fx) / det;
+        c[2] = xd[i1] - (c[0] * xs[i1] + c[1] * ys[i1]);
+        c[5] = yd[i1] - (c[3] * xs[i1] + c[4] * ys[i1]);
+        int score = 0;
+        for (int i = 0; i < n; ++i) score += aff_resid2(c, xs[i], ys[i], xd[i], yd[i]) <= tau2;
+        if (score > best) {
+            best = score;
+            memcpy(bm, c, sizeof(c));
+        }
+    }
+    int cnt = 0;
+    if (best >= 0) {
+        for (int i = 0; i < n; ++i) {
+            inl[i] = aff_resid2(bm, xs[i], ys[i], xd[i], yd[i]) <= tau2;
+            cnt += inl[i];
+        }
+    }
+    if (best < 0 || cnt < 3) {
+        for (int i = 0; i < n; ++i) inl[i] = 1;
+        ls_affine(xs, ys, xd, yd, NULL, n, m);
+        return n;
+    }
+    ls_affine(xs, ys, xd, yd, inl, n, m);
+    return cnt;
+}
+
 /* One pair. src/dst: 2*n_slots pixel coordinates; valid[n_slots] selects the tracked points (kept
  * in slot order). inlier_slots[n_slots] (may be NULL) receives the inlier flags per slot.
- * params4 = (a, b, tx, ty) mapping centred src to centred dst: x' = a x - b y + tx, y' = b x + a y + ty. */
+ * params4 = (a, b, tx, ty) mapping centred src to centred dst: x' = a x - b y + tx, y' = b x + a y + ty
+ * (for an affine result its nearest similarity, O-4b); affine6 (may be NULL) = the returned model as
+ * (a11, a12, tx, a21, a22, ty). */
 VSO_EXPORT void vso_fit_pair(const double* src, const double* dst, const uint8_t* valid, int n_slots,
                              const vso_fit_params* P, int64_t pair_index, vso_hybrid_state* st, double* params4,
-                             vso_fit_info* info, uint8_t* inlier_slots)
+                             double* affine6, vso_fit_info* info, uint8_t* inlier_slots)
 {
     double* xs = (double*)malloc(sizeof(double) * (size_t)(4 * n_slots + 4));
     double* ys = xs + n_slots + 1;
@@ -542,6 +704,8 @@ VSO_EXPORT void vso_fit_pair(const double* src, const double* dst, const uint8_t
     int* slot = (int*)malloc(sizeof(int) * (size_t)(n_slots + 1));
     uint8_t* inl = (uint8_t*)malloc((size_t)n_slots + 1);
     uint8_t* inl2 = (uint8_t*)malloc((size_t)n_slots + 1);
+    uint8_t* inl3 = (uint8_t*)malloc((size_t)n_slots + 1);
+    double m6[6] = {1, 0, 0, 0, 1, 0};
     int n = 0;
     for (int i = 0; i < n_slots; ++i) {
         if (valid && !valid[i]) continue;
@@ -555,8 +719,10 @@ VSO_EXPORT void vso_fit_pair(const double* src, const double* dst, const uint8_t
     memset(info, 0, sizeof(*info));
     info->err_rigid = NAN;
     info->err_sim = NAN;
+    info->err_affine = NAN;
     info->n_valid = n;
     if (inlier_slots) memset(inlier_slots, 0, (size_t)n_slots);
+    const int hybrid = P->model == VSO_HYBRID || P->model == VSO_HYBRID3;
     const int64_t block = pair_index / (P->dwell > 0 ? P->dwell : 1);
     if (st->block != block) {
         st->block = block;
@@ -565,13 +731,13 @@ VSO_EXPORT void vso_fit_pair(const double* src, const double* dst, const uint8_t
     if (n < P->min_valid || n < 2) {
         params4[0] = 1.0; params4[1] = 0.0; params4[2] = 0.0; params4[3] = 0.0;
         info->skipped = 1;
-        info->model = (P->model == VSO_HYBRID) ? st->model : P->model;
+        info->model = hybrid ? st->model : P->model;
         goto done;
     }
     int model;
-    if (P->model == VSO_HYBRID) {
+    if (hybrid) {
         if (!st->decided) {
-            double pr[4], ps[4];
+            double pr[4], ps[4], pa[6];
             const int mr = robust_fit(VSO_RIGID, P, pair_index, xs, ys, xd, yd, n, pr, inl);
             const int ms = robust_fit(VSO_SIMILARITY, P, pair_index, xs, ys, xd, yd, n, ps, inl2);
             const double er = rms_all(pr, xs, ys, xd, yd, n);
@@ -581,14 +747,26 @@ VSO_EXPORT void vso_fit_pair(const double* src, const double* dst, const uint8_t
             info->decided_here = 1;
             st->decided = 1;
             st->model = (er < es) ? VSO_RIGID : VSO_SIMILARITY;
+            int ma = 0;
+            if (P->model == VSO_HYBRID3) {
+                ma = robust_affine(P, pair_index, xs, ys, xd, yd, n, pa, inl3);
+                info->err_affine = rms_aff(pa, xs, ys, xd, yd, n);
+                if (info->err_affine < (st->model == VSO_RIGID ? er : es)) st->model = VSO_AFFINE;
+            }
             model = st->model;
             if (model == VSO_RIGID) {
                 memcpy(params4, pr, sizeof(pr));
+                sim_to_aff(pr, m6);
                 info->n_inliers = mr;
-            } else {
+            } else if (model == VSO_SIMILARITY) {
                 memcpy(params4, ps, sizeof(ps));
+                sim_to_aff(ps, m6);
                 info->n_inliers = ms;
                 memcpy(inl, inl2, (size_t)n);
+            } else {
+                memcpy(m6, pa, sizeof(pa));
+                info->n_inliers = ma;
+                memcpy(inl, inl3, (size_t)n);
             }
             info->model = model;
             goto write_inliers;
@@ -597,13 +775,25 @@ VSO_EXPORT void vso_fit_pair(const double* src, const double* dst, const uint8_t
     } else {
         model = P->model;
     }
-    info->n_inliers = robust_fit(model, P, pair_index, xs, ys, xd, yd, n, params4, inl);
+    if (model == VSO_AFFINE) {
+        info->n_inliers = robust_affine(P, pair_index, xs, ys, xd, yd, n, m6, inl);
+    } else {
+        info->n_inliers = robust_fit(model, P, pair_index, xs, ys, xd, yd, n, params4, inl);
+        sim_to_aff(params4, m6);
+    }
     info->model = model;
 write_inliers:
+    if (model == VSO_AFFINE) {
+        params4[0] = (m6[0] + m6[4]) * 0.5;
+        params4[1] = (m6[3] - m6[1]) * 0.5;
+        params4[2] = m6[2];
+        params4[3] = m6[5];
+    }
     if (inlier_slots)
         for (int i = 0; i < n; ++i) inlier_slots[slot[i]] = inl[i];
 done:
-    free(inl2); free(inl); free(slot); free(xs);
+    if (affine6) memcpy(affine6, m6, sizeof(m6));
+    free(inl3); free(inl2); free(inl); free(slot); free(xs);
 }
 
 /* =============================================================================================
