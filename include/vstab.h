@@ -39,7 +39,7 @@ extern "C" {
 #define VS_TRAJ_RING 256
 
 enum { VS_OK = 0, VS_ERR_INVALID = -1, VS_ERR_UNSUPPORTED = -2, VS_ERR_WORKSPACE = -3, VS_ERR_HIP = -4 };
-enum { VS_RIGID = 0, VS_SIMILARITY = 1, VS_HYBRID = 2 };
+enum { VS_RIGID = 0, VS_SIMILARITY = 1, VS_HYBRID = 2, VS_AFFINE = 3, VS_HYBRID3 = 4 };
 enum { VS_SMOOTH_CENTERED = 0, VS_SMOOTH_CAUSAL = 1, VS_SMOOTH_KALMAN = 2 };
 
 /* ---------------------------------------------------------------------------------------------
@@ -186,6 +186,7 @@ typedef struct {
     int32_t pad;
     double err_rigid;
     double err_sim;
+    double err_affine;   /* VS_HYBRID3 decision pairs only, else NaN */
 } vs_fit_info;
 
 size_t vs_fit_workspace(int32_t n, int32_t capacity);
@@ -193,6 +194,26 @@ int vs_fit_state_init(vs_fit_state* state, void* stream);
 int vs_fit_similarity(const float* src, const float* dst, const uint8_t* valid, int32_t capacity, int32_t n,
                       const vs_fit_params* p, int64_t pair_index0, vs_fit_state* state, double* params,
                       vs_fit_info* info, uint8_t* inliers, void* workspace, size_t ws_bytes, void* stream);
+
+/* fit_motion -- fit_similarity extended by the 6-DOF affine [A|t] of Eq. 7-8 (the least-squares
+ * 2x3 transform the paper starts from before restricting itself to 4 DOF in Section 4.1).
+ * model VS_AFFINE fits the affine alone; VS_HYBRID3 makes the hybrid a three-way choice: at a
+ * block's decision pair rigid is preferred over the similarity iff E_r < E_s, and the affine
+ * replaces that choice iff its RMS residual E_a is smaller still. The affine's RANSAC draws 3
+ * distinct points per hypothesis (SplitMix64 counters disjoint from the 2-point draws), solves the
+ * affine through them exactly (no hypothesis when the sample's doubled triangle area is below
+ * 1 px^2) and needs at least 3 inliers; its refit is binary64 least squares. A point set whose
+ * centred second-moment matrix is singular (det <= 1e-12 trace^2) takes the similarity fit. With
+ * the affine in the mode ransac_iters must be <= 8191.
+ * params[i][4]: as for fit_similarity; for an affine pair its nearest similarity in the Frobenius
+ * norm, a = (a11 + a22)/2, b = (a21 - a12)/2, same translation (the smoother stabilises 4 DOF).
+ * affine6[i][6] (device, may be NULL): the pair's model as (a11, a12, tx, a21, a22, ty),
+ * x' = a11 x + a12 y + tx, y' = a21 x + a22 y + ty in centred coordinates; the identity for a
+ * skipped pair. Every other argument, the workspace size and the errors are those of
+ * fit_similarity, which is fit_motion with affine6 = NULL. */
+int vs_fit_motion(const float* src, const float* dst, const uint8_t* valid, int32_t capacity, int32_t n,
+                  const vs_fit_params* p, int64_t pair_index0, vs_fit_state* state, double* params, double* affine6,
+                  vs_fit_info* info, uint8_t* inliers, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------------
  * smooth_trajectory -- Section 5.1 (accumulate the per-pair parameters into a trajectory, smooth

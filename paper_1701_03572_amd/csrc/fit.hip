@@ -1,4 +1,5 @@
-// fit_similarity: seeded robust rigid / similarity fit, hybrid dwell switch and skip rule.
+// fit_similarity / fit_motion: seeded robust rigid / similarity / affine fit, hybrid dwell switch
+// and skip rule.
 //
 // Kernel 1 (fit_pair): one 256-thread workgroup per pair. The valid slots are compacted in slot
 // order into LDS (raw FP32 coordinates, centred exactly in binary64 when read), then each
@@ -7,9 +8,12 @@
 // counting residuals <= threshold with a wave reduction, and the best (most inliers, then
 // smallest h) is refitted by least squares in binary64: the similarity through its 4x4 normal
 // equations (Gaussian elimination with partial pivoting), the rigid model through the centred
-// closed form atan2. Fixed-order reductions keep the result independent of scheduling.
-// The 2-point hypotheses and residuals use exactly the operation order
-//     px = (ar x - ai y) + br,  py = (ai x + ar y) + bi,  d2 = dx dx + dy dy
+// closed form atan2, the affine through its centroids and the centred 2x2 second moments.
+// Fixed-order reductions keep the result independent of scheduling. The hypotheses (2-point
+// similarity / rigid, 3-point affine) and residuals use exactly the operation order
+//     px = (ar x - ai y) + br,  py = (ai x + ar y) + bi          (similarity, rigid)
+//     px = (a11 x + a12 y) + tx,  py = (a21 x + a22 y) + ty      (affine)
+//     d2 = dx dx + dy dy
 // with floating-point contraction disabled, so inlier decisions are bit-reproducible.
 // Kernel 2 (fit_resolve): walks the pairs of the call in order through the dwell-block state
 // machine. Kernel 3 (fit_emit): one workgroup per pair writes the chosen model's parameters,
@@ -23,21 +27,25 @@
 namespace {
 
 struct ModelFit {
-    double p[4];
+    double p[6];     // (a, b, tx, ty) for rigid / similarity; (a11, a12, tx, a21, a22, ty) for the affine
     double err;
     int32_t n_inl;
     int32_t pad;
 };
 
+constexpr int N_SLOTS = 3;
+__host__ __device__ inline int slot_of_model(int model) { return model == VS_AFFINE ? 2 : model; }
+
 struct PairRec {
     int32_t n_valid;
     int32_t skipped;
     int32_t pad[2];
-    ModelFit m[2];   // [VS_RIGID], [VS_SIMILARITY]
+    ModelFit m[N_SLOTS];   // rigid, similarity, affine
 };
+static_assert(sizeof(PairRec) <= 256, "pair record header");
 
 __host__ __device__ inline int64_t cap_aligned(int cap) { return ((int64_t)cap + 255) & ~(int64_t)255; }
-__host__ __device__ inline int64_t rec_bytes(int cap) { return 256 + 2 * cap_aligned(cap); }
+__host__ __device__ inline int64_t rec_bytes(int cap) { return 256 + N_SLOTS * cap_aligned(cap); }
 
 __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t ctr)
 {
@@ -52,6 +60,23 @@ __device__ __forceinline__ uint64_t draw(uint64_t seed, int64_t stream_id, int64
     const uint64_t ctr = (((uint64_t)stream_id & 0xFFFFFull) << 44) | (((uint64_t)pair & 0xFFFFFFFull) << 16) |
                          (((uint64_t)h & 0x7FFFull) << 1) | ((uint64_t)k & 1u);
     return splitmix64_at(seed, ctr);
+}
+
+// 3-point draws: bit 15 of the low field set, so with at most 8191 hypotheses they never meet the
+// 2-point counters
+__device__ __forceinline__ uint64_t draw3(uint64_t seed, int64_t stream_id, int64_t pair, int h, int k)
+{
+    const uint64_t ctr = (((uint64_t)stream_id & 0xFFFFFull) << 44) | (((uint64_t)pair & 0xFFFFFFFull) << 16) |
+                         0x8000u | (((uint64_t)h & 0x1FFFull) << 2) | ((uint64_t)k & 3u);
+    return splitmix64_at(seed, ctr);
+}
+
+__device__ __forceinline__ double aff_resid2(const double* m, double x, double y, double xd, double yd)
+{
+    const double px = (m[0] * x + m[1] * y) + m[2];
+    const double py = (m[3] * x + m[4] * y) + m[5];
+    const double dx = xd - px, dy = yd - py;
+    return dx * dx + dy * dy;
 }
 
 __device__ __forceinline__ double resid2(double ar, double ai, double br, double bi, double x, double y, double xd,
@@ -119,7 +144,7 @@ __device__ void solve4(double A[4][4], double b[4], double x[4])
 }
 
 // least squares on the flagged points (all when flags == nullptr); result in out[4]
-__device__ void ls_refit(int model, const float* xs, const float* ys, const float* xd, const float* yd, double cx,
+__device__ __forceinline__ void ls_refit(int model, const float* xs, const float* ys, const float* xd, const float* yd, double cx,
                          double cy, const uint8_t* flags, int n, double* red, double* out)
 {
     const int t = threadIdx.x;
@@ -187,6 +212,61 @@ __device__ void ls_refit(int model, const float* xs, const float* ys, const floa
     __syncthreads();
 }
 
+// affine least squares on the flagged points: centroids, then A = C_uv C_xx^-1 from the centred
+// second moments; a singular C_xx (collinear or coincident points) takes the similarity fit.
+__device__ __forceinline__ void ls_affine(const float* xs, const float* ys, const float* xd, const float* yd, double cx, double cy,
+                          const uint8_t* flags, int n, double* red, double* out6, double* tmp4, int* s_flag)
+{
+    const int t = threadIdx.x;
+    double m[5] = {0, 0, 0, 0, 0};
+    for (int i = t; i < n; i += NT) {
+        if (flags && !flags[i]) continue;
+        m[0] += 1.0;
+        m[1] += xs[i] - cx;
+        m[2] += ys[i] - cy;
+        m[3] += xd[i] - cx;
+        m[4] += yd[i] - cy;
+    }
+    block_sum<5>(m, red);
+    const double mx = m[1] / m[0], my = m[2] / m[0], mu = m[3] / m[0], mw = m[4] / m[0];
+    double s[7] = {0, 0, 0, 0, 0, 0, 0};   // xx, xy, yy, xu, yu, xw, yw
+    for (int i = t; i < n; i += NT) {
+        if (flags && !flags[i]) continue;
+        const double x = (xs[i] - cx) - mx, y = (ys[i] - cy) - my, u = (xd[i] - cx) - mu, w = (yd[i] - cy) - mw;
+        s[0] += x * x;
+        s[1] += x * y;
+        s[2] += y * y;
+        s[3] += x * u;
+        s[4] += y * u;
+        s[5] += x * w;
+        s[6] += y * w;
+    }
+    block_sum<7>(s, red);
+    if (t == 0) {
+        const double det = s[0] * s[2] - s[1] * s[1], tr = s[0] + s[2];
+        if (det > 1e-12 * tr * tr) {
+            out6[0] = (s[3] * s[2] - s[4] * s[1]) / det;
+            out6[1] = (s[4] * s[0] - s[3] * s[1]) / det;
+            out6[3] = (s[5] * s[2] - s[6] * s[1]) / det;
+            out6[4] = (s[6] * s[0] - s[5] * s[1]) / det;
+            out6[2] = mu - (out6[0] * mx + out6[1] * my);
+            out6[5] = mw - (out6[3] * mx + out6[4] * my);
+            *s_flag = 0;
+        } else {
+            *s_flag = 1;
+        }
+    }
+    __syncthreads();
+    if (*s_flag) {
+        ls_refit(VS_SIMILARITY, xs, ys, xd, yd, cx, cy, flags, n, red, tmp4);
+        if (t == 0) {
+            out6[0] = tmp4[0]; out6[1] = -tmp4[1]; out6[2] = tmp4[2];
+            out6[3] = tmp4[1]; out6[4] = tmp4[0];  out6[5] = tmp4[3];
+        }
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(NT) void fit_pair_kernel(const float* __restrict__ src, const float* __restrict__ dst,
                                                       const uint8_t* __restrict__ valid, int capacity, FitArgs a,
                                                       int64_t pair_index0, uint8_t* ws)
@@ -197,9 +277,9 @@ __global__ __launch_bounds__(NT) void fit_pair_kernel(const float* __restrict__ 
     __shared__ double red[8 * NT];
     __shared__ int32_t s_cnt[NT];
     __shared__ int32_t w_score[4], w_h[4];
-    __shared__ double w_model[4][4];
-    __shared__ double s_out[4];
-    __shared__ int s_n, s_best_h, s_ninl;
+    __shared__ double w_model[4][6];
+    __shared__ double s_out[6], s_tmp[4];
+    __shared__ int s_n, s_best_h, s_ninl, s_flag;
 
     const int item = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int64_t pair = pair_index0 + item;
@@ -232,7 +312,7 @@ __global__ __launch_bounds__(NT) void fit_pair_kernel(const float* __restrict__ 
             ++o;
         }
     }
-    for (int k = t; k < 2 * cap_aligned(capacity); k += NT) masks[k] = 0;
+    for (int k = t; k < N_SLOTS * cap_aligned(capacity); k += NT) masks[k] = 0;
     __syncthreads();
     const int n = s_n;
     if (t == 0) {
@@ -241,52 +321,84 @@ __global__ __launch_bounds__(NT) void fit_pair_kernel(const float* __restrict__ 
     }
     if (n < a.min_valid || n < 2) return;
 
-    const int m_first = (a.model == VS_HYBRID) ? VS_RIGID : a.model;
-    const int m_last = (a.model == VS_HYBRID) ? VS_SIMILARITY : a.model;
-    for (int model = m_first; model <= m_last; ++model) {
+    // models to fit: one, or the hybrid's two or three candidates
+    const bool hybrid = a.model == VS_HYBRID || a.model == VS_HYBRID3;
+    const int n_models = a.model == VS_HYBRID3 ? 3 : a.model == VS_HYBRID ? 2 : 1;
+    for (int mi = 0; mi < n_models; ++mi) {
+        const int model = !hybrid ? a.model : mi == 0 ? VS_RIGID : mi == 1 ? VS_SIMILARITY : VS_AFFINE;
+        const bool affine = model == VS_AFFINE;
         bool have = false;
-        if (a.iters > 0) {
+        if (a.iters > 0 && (!affine || n >= 3)) {
             int best = -1, best_h = -1;
-            double bm[4] = {1, 0, 0, 0};
+            double bm[6] = {1, 0, 0, 0, 1, 0};
             for (int h = wv; h < a.iters; h += 4) {
-                const int i1 = (int)(draw(a.seed, a.stream_id, pair, h, 0) % (uint64_t)n);
-                int i2 = (int)(draw(a.seed, a.stream_id, pair, h, 1) % (uint64_t)n);
-                if (i2 == i1) i2 = (i2 + 1) % n;
-                const double x1 = xs[i1] - a.cx, y1 = ys[i1] - a.cy, x2 = xs[i2] - a.cx, y2 = ys[i2] - a.cy;
-                const double u1 = xd[i1] - a.cx, w1 = yd[i1] - a.cy, u2 = xd[i2] - a.cx, w2 = yd[i2] - a.cy;
-                const double dzx = x2 - x1, dzy = y2 - y1;
-                const double den = dzx * dzx + dzy * dzy;
-                if (den < 1.0) continue;
-                const double wx = u2 - u1, wy = w2 - w1;
-                double ar = (wx * dzx + wy * dzy) / den;
-                double ai = (wy * dzx - wx * dzy) / den;
-                double br, bi;
-                if (model == VS_RIGID) {
-                    const double mag = sqrt(ar * ar + ai * ai);
-                    if (!(mag > 0.0)) continue;
-                    ar = ar / mag;
-                    ai = ai / mag;
-                    const double sxs = x1 + x2, sys = y1 + y2, sxd = u1 + u2, syd = w1 + w2;
-                    br = (sxd - (ar * sxs - ai * sys)) * 0.5;
-                    bi = (syd - (ai * sxs + ar * sys)) * 0.5;
+                double c[6];
+                if (affine) {
+                    const int i1 = (int)(draw3(a.seed, a.stream_id, pair, h, 0) % (uint64_t)n);
+                    int i2 = (int)(draw3(a.seed, a.stream_id, pair, h, 1) % (uint64_t)n);
+                    int i3 = (int)(draw3(a.seed, a.stream_id, pair, h, 2) % (uint64_t)n);
+                    if (i2 == i1) i2 = (i2 + 1) % n;
+                    while (i3 == i1 || i3 == i2) i3 = (i3 + 1) % n;   // n >= 3: at most two steps
+                    const double x1 = xs[i1] - a.cx, y1 = ys[i1] - a.cy, u1 = xd[i1] - a.cx, w1 = yd[i1] - a.cy;
+                    const double ex = (xs[i2] - a.cx) - x1, ey = (ys[i2] - a.cy) - y1;
+                    const double fx = (xs[i3] - a.cx) - x1, fy = (ys[i3] - a.cy) - y1;
+                    const double det = ex * fy - fx * ey;
+                    if (!(fabs(det) >= 1.0)) continue;          // near-collinear sample: no hypothesis
+                    const double gu = (xd[i2] - a.cx) - u1, gv = (yd[i2] - a.cy) - w1;
+                    const double hu = (xd[i3] - a.cx) - u1, hv = (yd[i3] - a.cy) - w1;
+                    c[0] = (gu * fy - hu * ey) / det;
+                    c[1] = (hu * ex - gu * fx) / det;
+                    c[3] = (gv * fy - hv * ey) / det;
+                    c[4] = (hv * ex - gv * fx) / det;
+                    c[2] = u1 - (c[0] * x1 + c[1] * y1);
+                    c[5] = w1 - (c[3] * x1 + c[4] * y1);
                 } else {
-                    br = u1 - (ar * x1 - ai * y1);
-                    bi = w1 - (ai * x1 + ar * y1);
+                    const int i1 = (int)(draw(a.seed, a.stream_id, pair, h, 0) % (uint64_t)n);
+                    int i2 = (int)(draw(a.seed, a.stream_id, pair, h, 1) % (uint64_t)n);
+                    if (i2 == i1) i2 = (i2 + 1) % n;
+                    const double x1 = xs[i1] - a.cx, y1 = ys[i1] - a.cy, x2 = xs[i2] - a.cx, y2 = ys[i2] - a.cy;
+                    const double u1 = xd[i1] - a.cx, w1 = yd[i1] - a.cy, u2 = xd[i2] - a.cx, w2 = yd[i2] - a.cy;
+                    const double dzx = x2 - x1, dzy = y2 - y1;
+                    const double den = dzx * dzx + dzy * dzy;
+                    if (den < 1.0) continue;
+                    const double wx = u2 - u1, wy = w2 - w1;
+                    double ar = (wx * dzx + wy * dzy) / den;
+                    double ai = (wy * dzx - wx * dzy) / den;
+                    double br, bi;
+                    if (model == VS_RIGID) {
+                        const double mag = sqrt(ar * ar + ai * ai);
+                        if (!(mag > 0.0)) continue;
+                        ar = ar / mag;
+                        ai = ai / mag;
+                        const double sxs = x1 + x2, sys = y1 + y2, sxd = u1 + u2, syd = w1 + w2;
+                        br = (sxd - (ar * sxs - ai * sys)) * 0.5;
+                        bi = (syd - (ai * sxs + ar * sys)) * 0.5;
+                    } else {
+                        br = u1 - (ar * x1 - ai * y1);
+                        bi = w1 - (ai * x1 + ar * y1);
+                    }
+                    c[0] = ar; c[1] = ai; c[2] = br; c[3] = bi; c[4] = 0.0; c[5] = 0.0;
                 }
                 int sc = 0;
-                for (int i = lane; i < n; i += 64) sc += resid2(ar, ai, br, bi, xs[i] - a.cx, ys[i] - a.cy, xd[i] - a.cx,
-                                                                  yd[i] - a.cy) <= a.tau2;
+                if (affine) {
+                    for (int i = lane; i < n; i += 64)
+                        sc += aff_resid2(c, xs[i] - a.cx, ys[i] - a.cy, xd[i] - a.cx, yd[i] - a.cy) <= a.tau2;
+                } else {
+                    for (int i = lane; i < n; i += 64)
+                        sc += resid2(c[0], c[1], c[2], c[3], xs[i] - a.cx, ys[i] - a.cy, xd[i] - a.cx, yd[i] - a.cy) <=
+                              a.tau2;
+                }
                 sc = vs::wave_sum_i(sc);
                 if (sc > best) {
                     best = sc;
                     best_h = h;
-                    bm[0] = ar; bm[1] = ai; bm[2] = br; bm[3] = bi;
+                    for (int k = 0; k < 6; ++k) bm[k] = c[k];
                 }
             }
             if (lane == 0) {
                 w_score[wv] = best;
                 w_h[wv] = best_h;
-                for (int k = 0; k < 4; ++k) w_model[wv][k] = bm[k];
+                for (int k = 0; k < 6; ++k) w_model[wv][k] = bm[k];
             }
             __syncthreads();
             if (t == 0) {
@@ -300,11 +412,12 @@ __global__ __launch_bounds__(NT) void fit_pair_kernel(const float* __restrict__ 
             __syncthreads();
             const int bw = s_best_h;
             if (bw >= 0) {
-                const double ar = w_model[bw][0], ai = w_model[bw][1], br = w_model[bw][2], bi = w_model[bw][3];
+                const double* c = w_model[bw];
                 int m = 0;
                 for (int i = t; i < n; i += NT) {
-                    const uint8_t f =
-                        resid2(ar, ai, br, bi, xs[i] - a.cx, ys[i] - a.cy, xd[i] - a.cx, yd[i] - a.cy) <= a.tau2;
+                    const double x = xs[i] - a.cx, y = ys[i] - a.cy, u = xd[i] - a.cx, w = yd[i] - a.cy;
+                    const uint8_t f = (affine ? aff_resid2(c, x, y, u, w) : resid2(c[0], c[1], c[2], c[3], x, y, u, w)) <=
+                                      a.tau2;
                     inl[i] = f;
                     m += f;
                 }
@@ -316,7 +429,7 @@ __global__ __launch_bounds__(NT) void fit_pair_kernel(const float* __restrict__ 
                     s_ninl = tot;
                 }
                 __syncthreads();
-                have = s_ninl >= 2;
+                have = s_ninl >= (affine ? 3 : 2);
             }
         }
         if (!have) {
@@ -324,20 +437,27 @@ __global__ __launch_bounds__(NT) void fit_pair_kernel(const float* __restrict__ 
             if (t == 0) s_ninl = n;
             __syncthreads();
         }
-        ls_refit(model, xs, ys, xd, yd, a.cx, a.cy, inl, n, red, s_out);
+        if (affine)
+            ls_affine(xs, ys, xd, yd, a.cx, a.cy, inl, n, red, s_out, s_tmp, &s_flag);
+        else
+            ls_refit(model, xs, ys, xd, yd, a.cx, a.cy, inl, n, red, s_out);
         // RMS residual of the refitted model over all valid points
         double e[1] = {0.0};
-        const double p0 = s_out[0], p1 = s_out[1], p2 = s_out[2], p3 = s_out[3];
-        for (int i = t; i < n; i += NT)
-            e[0] += resid2(p0, p1, p2, p3, xs[i] - a.cx, ys[i] - a.cy, xd[i] - a.cx, yd[i] - a.cy);
+        double q[6];
+        for (int k = 0; k < 6; ++k) q[k] = s_out[k];
+        for (int i = t; i < n; i += NT) {
+            const double x = xs[i] - a.cx, y = ys[i] - a.cy, u = xd[i] - a.cx, w = yd[i] - a.cy;
+            e[0] += affine ? aff_resid2(q, x, y, u, w) : resid2(q[0], q[1], q[2], q[3], x, y, u, w);
+        }
         block_sum<1>(e, red);
+        const int slot = slot_of_model(model);
         if (t == 0) {
-            ModelFit& mf = rec->m[model];
-            for (int k = 0; k < 4; ++k) mf.p[k] = s_out[k];
+            ModelFit& mf = rec->m[slot];
+            for (int k = 0; k < 6; ++k) mf.p[k] = (affine || k < 4) ? s_out[k] : 0.0;
             mf.err = sqrt(e[0] / n);
             mf.n_inl = s_ninl;
         }
-        uint8_t* mk = masks + model * cap_aligned(capacity);
+        uint8_t* mk = masks + slot * cap_aligned(capacity);
         for (int i = t; i < n; i += NT) mk[slot_of[i]] = inl[i];
         __syncthreads();
     }
@@ -349,7 +469,7 @@ __global__ __launch_bounds__(NT) void fit_resolve_kernel(int n, int capacity, Fi
                                                          vs_fit_state* state, uint8_t* ws)
 {
     __shared__ int8_t skipped[1024];
-    __shared__ double er[1024], es[1024];
+    __shared__ double er[1024], es[1024], ea[1024];
     __shared__ int8_t choice[1024], decided[1024];
     const int t = threadIdx.x;
     vs_fit_state st;
@@ -359,11 +479,13 @@ __global__ __launch_bounds__(NT) void fit_resolve_kernel(int n, int capacity, Fi
         for (int i = c0 + t; i < c1; i += NT) {
             const PairRec* rec = reinterpret_cast<const PairRec*>(ws + i * rec_bytes(capacity));
             skipped[i - c0] = (int8_t)rec->skipped;
-            er[i - c0] = rec->m[VS_RIGID].err;
-            es[i - c0] = rec->m[VS_SIMILARITY].err;
+            er[i - c0] = rec->m[0].err;
+            es[i - c0] = rec->m[1].err;
+            ea[i - c0] = rec->m[2].err;
         }
         __syncthreads();
         if (t == 0) {
+            const bool hybrid = a.model == VS_HYBRID || a.model == VS_HYBRID3;
             for (int i = c0; i < c1; ++i) {
                 const int64_t pair = pair_index0 + i;
                 const int64_t block = pair / (a.dwell > 0 ? a.dwell : 1);
@@ -373,10 +495,12 @@ __global__ __launch_bounds__(NT) void fit_resolve_kernel(int n, int capacity, Fi
                 }
                 int ch, dh = 0;
                 if (skipped[i - c0]) {
-                    ch = -1 - ((a.model == VS_HYBRID) ? st.model : a.model);   // identity, reported model
-                } else if (a.model == VS_HYBRID) {
+                    ch = -1 - (hybrid ? st.model : a.model);   // identity, reported model
+                } else if (hybrid) {
                     if (!st.decided) {
                         st.model = (er[i - c0] < es[i - c0]) ? VS_RIGID : VS_SIMILARITY;
+                        if (a.model == VS_HYBRID3 && ea[i - c0] < (st.model == VS_RIGID ? er[i - c0] : es[i - c0]))
+                            st.model = VS_AFFINE;
                         st.decided = 1;
                         dh = 1;
                     }
@@ -399,8 +523,11 @@ __global__ __launch_bounds__(NT) void fit_resolve_kernel(int n, int capacity, Fi
     if (t == 0) *state = st;
 }
 
-// One workgroup per pair: writes the chosen model's parameters, info record and inlier flags.
-__global__ __launch_bounds__(NT) void fit_emit_kernel(int capacity, const uint8_t* ws, double* __restrict__ params,
+// One workgroup per pair: writes the chosen model's parameters (an affine as its nearest
+// similarity, a = (a11 + a22) / 2, b = (a21 - a12) / 2), the 2x3 matrices (optional), info record
+// and inlier flags.
+__global__ __launch_bounds__(NT) void fit_emit_kernel(int capacity, int32_t model_mode, const uint8_t* ws,
+                                                      double* __restrict__ params, double* __restrict__ affine6,
                                                       vs_fit_info* __restrict__ info, uint8_t* __restrict__ inliers)
 {
     const int i = blockIdx.x, t = threadIdx.x;
@@ -414,24 +541,40 @@ __global__ __launch_bounds__(NT) void fit_emit_kernel(int capacity, const uint8_
         f.pad = 0;
         f.err_rigid = __longlong_as_double(0x7ff8000000000000ll);
         f.err_sim = f.err_rigid;
+        f.err_affine = f.err_rigid;
         double* po = params + 4 * (int64_t)i;
+        double m6[6] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0};
         if (ch < 0) {
             f.model = -1 - ch;
             f.n_inliers = 0;
             po[0] = 1.0; po[1] = 0.0; po[2] = 0.0; po[3] = 0.0;
         } else {
+            const ModelFit& mf = rec->m[slot_of_model(ch)];
             f.model = ch;
-            f.n_inliers = rec->m[ch].n_inl;
-            for (int k = 0; k < 4; ++k) po[k] = rec->m[ch].p[k];
+            f.n_inliers = mf.n_inl;
+            if (ch == VS_AFFINE) {
+                for (int k = 0; k < 6; ++k) m6[k] = mf.p[k];
+                po[0] = (m6[0] + m6[4]) * 0.5;
+                po[1] = (m6[3] - m6[1]) * 0.5;
+                po[2] = m6[2];
+                po[3] = m6[5];
+            } else {
+                for (int k = 0; k < 4; ++k) po[k] = mf.p[k];
+                m6[0] = mf.p[0]; m6[1] = -mf.p[1]; m6[2] = mf.p[2];
+                m6[3] = mf.p[1]; m6[4] = mf.p[0];  m6[5] = mf.p[3];
+            }
             if (f.decided_here) {
-                f.err_rigid = rec->m[VS_RIGID].err;
-                f.err_sim = rec->m[VS_SIMILARITY].err;
+                f.err_rigid = rec->m[0].err;
+                f.err_sim = rec->m[1].err;
+                if (model_mode == VS_HYBRID3) f.err_affine = rec->m[2].err;
             }
         }
+        if (affine6)
+            for (int k = 0; k < 6; ++k) affine6[6 * (int64_t)i + k] = m6[k];
         info[i] = f;
     }
     if (inliers) {
-        const uint8_t* mk = ws + i * rec_bytes(capacity) + 256 + (ch < 0 ? 0 : ch) * cap_aligned(capacity);
+        const uint8_t* mk = ws + i * rec_bytes(capacity) + 256 + (ch < 0 ? 0 : slot_of_model(ch)) * cap_aligned(capacity);
         uint8_t* o = inliers + (int64_t)i * capacity;
         for (int k = t; k < capacity; k += NT) o[k] = ch < 0 ? 0 : mk[k];
     }
@@ -459,24 +602,26 @@ extern "C" int vs_fit_state_init(vs_fit_state* state, void* stream)
     return vs::check_launch("vs_fit_state_init");
 }
 
-extern "C" int vs_fit_similarity(const float* src, const float* dst, const uint8_t* valid, int32_t capacity, int32_t n,
-                                 const vs_fit_params* p, int64_t pair_index0, vs_fit_state* state, double* params,
-                                 vs_fit_info* info, uint8_t* inliers, void* workspace, size_t ws_bytes, void* stream)
+extern "C" int vs_fit_motion(const float* src, const float* dst, const uint8_t* valid, int32_t capacity, int32_t n,
+                             const vs_fit_params* p, int64_t pair_index0, vs_fit_state* state, double* params,
+                             double* affine6, vs_fit_info* info, uint8_t* inliers, void* workspace, size_t ws_bytes,
+                             void* stream)
 {
-    if (!p) return vs::set_error(VS_ERR_INVALID, "vs_fit_similarity: null params");
-    if (n < 0 || capacity <= 0) return vs::set_error(VS_ERR_INVALID, "vs_fit_similarity: bad count or capacity");
+    if (!p) return vs::set_error(VS_ERR_INVALID, "vs_fit_motion: null params");
+    if (n < 0 || capacity <= 0) return vs::set_error(VS_ERR_INVALID, "vs_fit_motion: bad count or capacity");
     if (n == 0) return VS_OK;
     if (!src || !dst || !valid || !state || !params || !info || !workspace)
-        return vs::set_error(VS_ERR_INVALID, "vs_fit_similarity: null argument");
-    if (capacity > VS_MAX_CORNERS) return vs::set_error(VS_ERR_UNSUPPORTED, "vs_fit_similarity: capacity > %d", VS_MAX_CORNERS);
-    if (p->model < VS_RIGID || p->model > VS_HYBRID || p->ransac_iters < 0 || p->ransac_iters > 32767 ||
-        !(p->inlier_thresh >= 0.0) || p->dwell < 1 || pair_index0 < 0)
-        return vs::set_error(VS_ERR_INVALID, "vs_fit_similarity: bad parameters");
-    if (n > 65535) return vs::set_error(VS_ERR_INVALID, "vs_fit_similarity: more than 65535 pairs");
+        return vs::set_error(VS_ERR_INVALID, "vs_fit_motion: null argument");
+    if (capacity > VS_MAX_CORNERS) return vs::set_error(VS_ERR_UNSUPPORTED, "vs_fit_motion: capacity > %d", VS_MAX_CORNERS);
+    const bool with_affine = p->model == VS_AFFINE || p->model == VS_HYBRID3;
+    if (p->model < VS_RIGID || p->model > VS_HYBRID3 || p->ransac_iters < 0 ||
+        p->ransac_iters > (with_affine ? 8191 : 32767) || !(p->inlier_thresh >= 0.0) || p->dwell < 1 || pair_index0 < 0)
+        return vs::set_error(VS_ERR_INVALID, "vs_fit_motion: bad parameters");
+    if (n > 65535) return vs::set_error(VS_ERR_INVALID, "vs_fit_motion: more than 65535 pairs");
     const size_t need = vs_fit_workspace(n, capacity);
-    if (ws_bytes < need) return vs::set_error(VS_ERR_WORKSPACE, "vs_fit_similarity: workspace %zu < %zu", ws_bytes, need);
+    if (ws_bytes < need) return vs::set_error(VS_ERR_WORKSPACE, "vs_fit_motion: workspace %zu < %zu", ws_bytes, need);
     if (reinterpret_cast<uintptr_t>(workspace) & 255)
-        return vs::set_error(VS_ERR_INVALID, "vs_fit_similarity: workspace must be 256-byte aligned");
+        return vs::set_error(VS_ERR_INVALID, "vs_fit_motion: workspace must be 256-byte aligned");
     FitArgs a;
     a.model = p->model;
     a.iters = p->ransac_iters;
@@ -490,11 +635,19 @@ extern "C" int vs_fit_similarity(const float* src, const float* dst, const uint8
     hipStream_t s = vs::as_stream(stream);
     uint8_t* w8 = static_cast<uint8_t*>(workspace);
     fit_pair_kernel<<<n, NT, 0, s>>>(src, dst, valid, capacity, a, pair_index0, w8);
-    int e = vs::check_launch("vs_fit_similarity(pairs)");
+    int e = vs::check_launch("vs_fit_motion(pairs)");
     if (e) return e;
     fit_resolve_kernel<<<1, NT, 0, s>>>(n, capacity, a, pair_index0, state, w8);
-    e = vs::check_launch("vs_fit_similarity(resolve)");
+    e = vs::check_launch("vs_fit_motion(resolve)");
     if (e) return e;
-    fit_emit_kernel<<<n, NT, 0, s>>>(capacity, w8, params, info, inliers);
-    return vs::check_launch("vs_fit_similarity(emit)");
+    fit_emit_kernel<<<n, NT, 0, s>>>(capacity, a.model, w8, params, affine6, info, inliers);
+    return vs::check_launch("vs_fit_motion(emit)");
+}
+
+extern "C" int vs_fit_similarity(const float* src, const float* dst, const uint8_t* valid, int32_t capacity, int32_t n,
+                                 const vs_fit_params* p, int64_t pair_index0, vs_fit_state* state, double* params,
+                                 vs_fit_info* info, uint8_t* inliers, void* workspace, size_t ws_bytes, void* stream)
+{
+    return vs_fit_motion(src, dst, valid, capacity, n, p, pair_index0, state, params, nullptr, info, inliers, workspace,
+                         ws_bytes, stream);
 }

@@ -13,7 +13,6 @@ namespace {
 
 constexpr int TW = 128;                // output tile width
 constexpr int TH = 32;                 // output tile height
-constexpr int IW = 2 * TW + 3;         // input columns 2*x0-2 .. 2*(x0+TW-1)+2
 constexpr int IH = 2 * TH + 3;
 constexpr int OFF = 14;                // LDS byte offset of input column 2*x0-2 (16-byte aligned staging)
 constexpr int LP = 288;                // LDS row pitch: OFF + IW rounded up to 16

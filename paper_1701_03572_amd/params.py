@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import dataclasses
 
-RIGID, SIMILARITY, HYBRID = 0, 1, 2
+RIGID, SIMILARITY, HYBRID, AFFINE, HYBRID3 = 0, 1, 2, 3, 4
 SMOOTH_CENTERED, SMOOTH_CAUSAL, SMOOTH_KALMAN = 0, 1, 2
 
 

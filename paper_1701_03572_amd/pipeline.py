@@ -103,6 +103,8 @@ class SequenceStabilizer:
         self.pair_params = torch.zeros((max(n - 1, 1), 4), dtype=torch.float64, device=dev)
         self.info = _bytes(max(n - 1, 1) * V.FIT_INFO_BYTES, dev)
         self.inliers = torch.zeros((max(n - 1, 1), cap), dtype=torch.uint8, device=dev)
+        # per-pair 2x3 models (a11, a12, tx, a21, a22, ty), centred; the smoother uses pair_params
+        self.affine6 = torch.zeros((max(n - 1, 1), 6), dtype=torch.float64, device=dev)
         self.traj_state = _bytes(V.vs_traj_state_bytes(), dev)
         self.mats = torch.zeros((n, 6), dtype=torch.float64, device=dev)
         self.n_emitted = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -160,8 +162,8 @@ class SequenceStabilizer:
                                         self.count.data_ptr() + (s + 1) * 4, al + (s + 1) * rec1, self.det_ws,
                                         self.det_ws_bytes)
             V.vs_fit_state_init(self.fit_state)
-            V.vs_fit_similarity(self.src, self.dst, self.status, cap, n_pairs, self._fp, 0, self.fit_state,
-                                self.pair_params, self.info, self.inliers, self.fit_ws, self.fit_ws_bytes)
+            V.vs_fit_motion(self.src, self.dst, self.status, cap, n_pairs, self._fp, 0, self.fit_state,
+                            self.pair_params, self.affine6, self.info, self.inliers, self.fit_ws, self.fit_ws_bytes)
             self.refine_pairs(f0, f0 + fs, fs, n_pairs, self.pair_params, self.info)
         V.vs_traj_state_init(self.traj_state)
         V.vs_smooth_trajectory(self.pair_params if n_pairs >= 1 else None, n_pairs, 1, self._sp, self.traj_state,
@@ -183,6 +185,7 @@ class SequenceStabilizer:
             "fb_err": self.fb_err[:n_pairs].cpu().numpy(),
             "n_valid": self.n_valid[:n_pairs].cpu().numpy(),
             "inliers": self.inliers[:n_pairs].cpu().numpy(),
+            "affine6": self.affine6[:n_pairs].cpu().numpy(),
         }
 
 
@@ -214,6 +217,7 @@ class Stabilizer:
         self.pair_params = torch.zeros((1, 4), dtype=torch.float64, device=dev)
         self.info = _bytes(V.FIT_INFO_BYTES, dev)
         self.inliers = torch.zeros(cap, dtype=torch.uint8, device=dev)
+        self.affine6 = torch.zeros((1, 6), dtype=torch.float64, device=dev)   # last pair's 2x3 model
         self.traj_state = _bytes(V.vs_traj_state_bytes(), dev)
         self.lag = P.radius if P.smooth_mode == V.VS_SMOOTH_CENTERED else 0
         self.mats_cap = self.lag + 2
@@ -271,8 +275,8 @@ class Stabilizer:
             V.vs_track_lk(self.frames[j - 1], self.pyr.data_ptr() + prev * bytes_, frame, pyr_cur, 0, 0, 1, 1, L,
                           self.pts[prev], self.alive[prev], self.cap, self._lkp, self.dst, self.status, self.fb_err,
                           self.n_valid, self.pts[cur], self.alive[cur])
-            V.vs_fit_similarity(self.pts[prev], self.dst, self.status, self.cap, 1, self._fp, j - 1, self.fit_state,
-                                self.pair_params, self.info, self.inliers, self.fit_ws, self.fit_ws_bytes)
+            V.vs_fit_motion(self.pts[prev], self.dst, self.status, self.cap, 1, self._fp, j - 1, self.fit_state,
+                            self.pair_params, self.affine6, self.info, self.inliers, self.fit_ws, self.fit_ws_bytes)
             self.refine_pair(self.frames[j - 1], frame, 0, 1, self.pair_params, self.info)
             self._detect(frame, cur, gated=(j % self.P.redetect_every != 0))
             V.vs_smooth_trajectory(self.pair_params, 1, 0, self._sp, self.traj_state, self.mats, self.mats_cap,

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libvstab.so")
 VS_MAX_LEVELS = 8
 VS_MAX_CORNERS = 4096
 VS_TRAJ_RING = 256
-VS_RIGID, VS_SIMILARITY, VS_HYBRID = 0, 1, 2
+VS_RIGID, VS_SIMILARITY, VS_HYBRID, VS_AFFINE, VS_HYBRID3 = 0, 1, 2, 3, 4
 VS_SMOOTH_CENTERED, VS_SMOOTH_CAUSAL, VS_SMOOTH_KALMAN = 0, 1, 2
 
 
@@ -53,7 +53,8 @@ class vs_fit_state(C.Structure):
 
 class vs_fit_info(C.Structure):
     _fields_ = [("model", C.c_int32), ("n_valid", C.c_int32), ("n_inliers", C.c_int32), ("skipped", C.c_int32),
-                ("decided_here", C.c_int32), ("pad", C.c_int32), ("err_rigid", C.c_double), ("err_sim", C.c_double)]
+                ("decided_here", C.c_int32), ("pad", C.c_int32), ("err_rigid", C.c_double), ("err_sim", C.c_double),
+                ("err_affine", C.c_double)]
 
 
 class vs_rect(C.Structure):
@@ -88,6 +89,8 @@ _SIGS = {
     "vs_fit_state_init": (C.c_int, [_P, _P]),
     "vs_fit_similarity": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.POINTER(vs_fit_params), C.c_int64, _P, _P,
                                     _P, _P, _P, C.c_size_t, _P]),
+    "vs_fit_motion": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.POINTER(vs_fit_params), C.c_int64, _P, _P, _P,
+                                _P, _P, _P, C.c_size_t, _P]),
     "vs_traj_state_bytes": (C.c_size_t, []),
     "vs_traj_state_init": (C.c_int, [_P, _P]),
     "vs_smooth_trajectory": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(vs_smooth_params), _P, _P, C.c_int32,
@@ -208,6 +211,13 @@ def vs_fit_similarity(src, dst, valid, capacity: int, n: int, params: vs_fit_par
     _check(load().vs_fit_similarity(_ptr(src), _ptr(dst), _ptr(valid), capacity, n, C.byref(params), pair_index0,
                                     _ptr(state), _ptr(out_params), _ptr(info), _ptr(inliers), _ptr(workspace),
                                     ws_bytes, _stream(stream)), "vs_fit_similarity")
+
+
+def vs_fit_motion(src, dst, valid, capacity: int, n: int, params: vs_fit_params, pair_index0: int, state,
+                  out_params, affine6, info, inliers, workspace, ws_bytes: int, stream=None):
+    _check(load().vs_fit_motion(_ptr(src), _ptr(dst), _ptr(valid), capacity, n, C.byref(params), pair_index0,
+                                _ptr(state), _ptr(out_params), _ptr(affine6), _ptr(info), _ptr(inliers),
+                                _ptr(workspace), ws_bytes, _stream(stream)), "vs_fit_motion")
 
 
 def vs_traj_state_bytes() -> int:

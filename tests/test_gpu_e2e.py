@@ -168,3 +168,30 @@ def test_photometric_refinement_in_both_paths():
     assert acc.sum() > 0
     d = np.abs(stream_out.astype(int) - seq_out.astype(int))
     assert d.max() <= 1 and (d > 0).mean() < 1e-4
+
+
+def test_three_way_hybrid_with_the_affine_candidate():
+    """The hybrid extended by the 6-DOF affine of Eq. 7-8 (a variant): both paths agree bit for bit,
+    decisions and skips equal the oracle's, the smoothed similarity parts within 0.02 px."""
+    sq = synth.make_sequence("tiny", n_frames=26)
+    P = params.PRESETS["tiny"].replace(model=params.HYBRID3)
+    seq, seq_out, stream_out, ss, st = run_both_paths(sq.frames, P)
+    np.testing.assert_array_equal(stream_out, seq_out)
+    ref = O.stabilize(sq.frames, P, warp_frames=False)
+    h, w = sq.frames.shape[1:]
+    models = []
+    for p in range(25):
+        gi, ri = seq["info"][p], ref["info"][p]
+        assert gi["skipped"] == ri["skipped"] and gi["decided_here"] == ri["decided_here"], p
+        errs = [ri["err_rigid"], ri["err_sim"], ri["err_affine"]]
+        tie = ri["decided_here"] and any(abs(x - y) < 1e-6 * max(x, y) for i, x in enumerate(errs) for y in errs[i + 1:])
+        if not tie:
+            assert gi["model"] == ri["model"], p
+        models.append(gi["model"])
+        assert transform_err(seq["pair_params"][p], ref["pair_params"][p], w, h) < 0.02
+        if gi["model"] == params.AFFINE:
+            m = seq["affine6"][p]
+            np.testing.assert_allclose(seq["pair_params"][p], [(m[0] + m[4]) / 2, (m[3] - m[1]) / 2, m[2], m[5]],
+                                       rtol=0, atol=1e-15)
+    say("three-way models", models)
+
