@@ -15,8 +15,10 @@
 // per gradient component that depend only on the iterate's integer position (the bilinear form of
 // the next-frame 2 x 2 blocks; see residual_partials). They are recomputed, from the lane's (R+1) x 2
 // next-frame block, only when the integer position moves; an iteration that stays on the same
-// pixel costs a few wave-uniform operations. The first block of each level is read with the set-up,
-// and its eight sums share the set-up's reduction with the three tensor sums. Reductions are
+// pixel costs a few wave-uniform operations. The lanes accumulate plain sums of products of raw
+// next-frame pixels with the gradients (no per-sample differences), and the E sums are formed from
+// the reduced totals. The first block of each level is read with the set-up, and its eight sums
+// share the set-up's reduction with the three tensor sums and the two sums of I times the gradient. Reductions are
 // transposing DPP row sums, so several sums cost little more than one; every lane ends with the
 // same totals, and the iteration control is wave-uniform. One wave per workgroup lets every point
 // retire independently.
@@ -67,12 +69,12 @@ struct LKConst {
 
 __device__ __forceinline__ bool wave_all(bool c) { return __ballot(!c) == 0; }
 
-// Next-frame 2-pixel rows x0, x0 + 1 of rows y0 .. y0 + RMAX: qa = P(x0), qd = P(x0 + 1) - P(x0). When
-// every active lane's block is inside the level, one (unaligned) 16-bit load per row; otherwise
+// Next-frame 2-pixel rows x0, x0 + 1 of rows y0 .. y0 + RMAX: qa = P(x0), qb = P(x0 + 1). When every
+// active lane's block is inside the level, one (unaligned) 16-bit load per row; otherwise
 // edge-clamped byte loads.
 template <int RMAX>
 __device__ __forceinline__ void load_next_block(const Img& B, int x0, int y0, bool active, float (&qa)[RMAX + 1],
-                                                float (&qd)[RMAX + 1])
+                                                float (&qb)[RMAX + 1])
 {
     const bool b_in = wave_all(!active || (x0 >= 0 && x0 + 1 <= B.w - 1 && y0 >= 0 && y0 + RMAX <= B.h - 1));
     if (b_in) {
@@ -81,7 +83,7 @@ __device__ __forceinline__ void load_next_block(const Img& B, int x0, int y0, bo
             const uint32_t w = __builtin_amdgcn_raw_buffer_load_b16(
                 B.rs, (int)__umul24((unsigned)(y0 + k), (unsigned)B.pitch) + x0, 0, 0);
             qa[k] = (float)(w & 0xff);
-            qd[k] = (float)(w >> 8) - qa[k];
+            qb[k] = (float)((w >> 8) & 0xff);
         }
     } else {
         const int c0 = vs::clampi(x0, 0, B.w - 1), c1 = vs::clampi(x0 + 1, 0, B.w - 1);
@@ -89,36 +91,47 @@ __device__ __forceinline__ void load_next_block(const Img& B, int x0, int y0, bo
         for (int k = 0; k <= RMAX; ++k) {
             const int base = (int)__umul24((unsigned)vs::clampi(y0 + k, 0, B.h - 1), (unsigned)B.pitch);
             qa[k] = ld(B, base + c0);
-            qd[k] = ld(B, base + c1) - qa[k];
+            qb[k] = ld(B, base + c1);
         }
     }
 }
 
-// Lane partials of the residual sums for the next-frame block (qa, qd) at integer offset (x0, y0).
+// Lane partials of the residual sums for the next-frame block (qa, qb) at integer offset (x0, y0).
 // With the iterate's fraction (ja, jb), the bilinear next-frame sample of window pixel k is
-// P00 + ja d10 + jb d01 + ja jb d11 with d10 = qd_k, d01 = qa_{k+1} - qa_k, d11 = qd_{k+1} - qd_k, so
-//   sum_k (I_k - J_k) Ix_k = E0x - ja E1x - jb E2x - ja jb E3x,  E0x = sum (I_k - P00_k) Ix_k,
-// E1x = sum d10 Ix, E2x = sum d01 Ix, E3x = sum d11 Ix (likewise for Iy). The E sums depend on the
-// integer offset only. Output order: E0x E1x E2x E3x E0y E1y E2y E3y.
+// P00 + ja d10 + jb d01 + ja jb d11 with P00 = qa_k, d10 = qb_k - qa_k, d01 = qa_{k+1} - qa_k and
+// d11 = (qb_{k+1} - qa_{k+1}) - (qb_k - qa_k), so
+//   sum_k (I_k - J_k) Ix_k = E0x - ja E1x - jb E2x - ja jb E3x,
+// with, from the plain sums A0 = sum qa_k Ix_k, A1 = sum qa_{k+1} Ix_k, B0 = sum qb_k Ix_k,
+// B1 = sum qb_{k+1} Ix_k and S = sum I_k Ix_k:
+//   E0x = S - A0, E1x = B0 - A0, E2x = A1 - A0, E3x = (B1 - A1) - (B0 - A0)
+// (likewise for Iy). The sums depend on the integer offset only. Output order:
+// A0x A1x B0x B1x A0y A1y B0y B1y.
 template <int RMAX>
-__device__ __forceinline__ void residual_partials(const float (&I)[RMAX], const float (&Ix)[RMAX], const float (&Iy)[RMAX],
-                                                  const float (&qa)[RMAX + 1], const float (&qd)[RMAX + 1], float* e)
+__device__ __forceinline__ void residual_partials(const float (&Ix)[RMAX], const float (&Iy)[RMAX],
+                                                  const float (&qa)[RMAX + 1], const float (&qb)[RMAX + 1], float* e)
 {
 #pragma unroll
     for (int j = 0; j < 8; ++j) e[j] = 0.f;
 #pragma unroll
     for (int k = 0; k < RMAX; ++k) {
-        const float e0 = I[k] - qa[k], d10 = qd[k];
-        const float d01 = qa[k + 1] - qa[k], d11 = qd[k + 1] - qd[k];
-        e[0] = fmaf(e0, Ix[k], e[0]);
-        e[1] = fmaf(d10, Ix[k], e[1]);
-        e[2] = fmaf(d01, Ix[k], e[2]);
-        e[3] = fmaf(d11, Ix[k], e[3]);
-        e[4] = fmaf(e0, Iy[k], e[4]);
-        e[5] = fmaf(d10, Iy[k], e[5]);
-        e[6] = fmaf(d01, Iy[k], e[6]);
-        e[7] = fmaf(d11, Iy[k], e[7]);
+        e[0] = fmaf(qa[k], Ix[k], e[0]);
+        e[1] = fmaf(qa[k + 1], Ix[k], e[1]);
+        e[2] = fmaf(qb[k], Ix[k], e[2]);
+        e[3] = fmaf(qb[k + 1], Ix[k], e[3]);
+        e[4] = fmaf(qa[k], Iy[k], e[4]);
+        e[5] = fmaf(qa[k + 1], Iy[k], e[5]);
+        e[6] = fmaf(qb[k], Iy[k], e[6]);
+        e[7] = fmaf(qb[k + 1], Iy[k], e[7]);
     }
+}
+
+// E sums of one gradient component from its reduced plain sums (see residual_partials)
+__device__ __forceinline__ void e_from_sums(float S, float A0, float A1, float B0, float B1, float* E)
+{
+    E[0] = S - A0;
+    E[1] = B0 - A0;
+    E[2] = A1 - A0;
+    E[3] = (B1 - A1) - (B0 - A0);
 }
 
 // Previous-frame samples of one lane: I, and the gradient terms 0.5 * central differences (zero
@@ -197,27 +210,33 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
         else
             window_samples<RMAX, false>(A, ix, iy, a, b, nrows, I, Ix, Iy);
         // the first iterate's next-frame block is read here, so its residual sums share the set-up's
-        // reduction: 3 tensor sums + 8 residual sums in one transposing reduction
+        // reduction: 3 tensor sums + 2 sums of I times the gradient + 8 residual sums in one
+        // transposing reduction
         int cjx = (int)floorf(cx + gx), cjy = (int)floorf(cy + gy);
-        float qa[RMAX + 1], qd[RMAX + 1];
-        load_next_block<RMAX>(B, cjx + qx, cjy + qy0, active, qa, qd);
+        float qa[RMAX + 1], qb[RMAX + 1];
+        load_next_block<RMAX>(B, cjx + qx, cjy + qy0, active, qa, qb);
         float v[16];
-        residual_partials<RMAX>(I, Ix, Iy, qa, qd, v + 3);
-        v[0] = v[1] = v[2] = 0.f;
+        residual_partials<RMAX>(Ix, Iy, qa, qb, v + 5);
+        v[0] = v[1] = v[2] = v[3] = v[4] = 0.f;
 #pragma unroll
         for (int k = 0; k < RMAX; ++k) {
             v[0] = fmaf(Ix[k], Ix[k], v[0]);
             v[1] = fmaf(Ix[k], Iy[k], v[1]);
             v[2] = fmaf(Iy[k], Iy[k], v[2]);
+            v[3] = fmaf(I[k], Ix[k], v[3]);
+            v[4] = fmaf(I[k], Iy[k], v[4]);
         }
 #pragma unroll
-        for (int j = 11; j < 16; ++j) v[j] = 0.f;
+        for (int j = 13; j < 16; ++j) v[j] = 0.f;
         const float tot = vs::wave_transpose_sum<16>(v);
         const float g11 = vs::transposed_total<16>(tot, 0), g12 = vs::transposed_total<16>(tot, 1);
         const float g22 = vs::transposed_total<16>(tot, 2);
+        const float Sx = vs::transposed_total<16>(tot, 3), Sy = vs::transposed_total<16>(tot, 4);
         float E[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) E[j] = vs::transposed_total<16>(tot, 3 + j);
+        e_from_sums(Sx, vs::transposed_total<16>(tot, 5), vs::transposed_total<16>(tot, 6),
+                    vs::transposed_total<16>(tot, 7), vs::transposed_total<16>(tot, 8), E);
+        e_from_sums(Sy, vs::transposed_total<16>(tot, 9), vs::transposed_total<16>(tot, 10),
+                    vs::transposed_total<16>(tot, 11), vs::transposed_total<16>(tot, 12), E + 4);
         ++n_setup;
         const float tr = g11 + g22;
         const float sq = sqrtf((g11 - g22) * (g11 - g22) + 4.0f * g12 * g12);
@@ -238,12 +257,14 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
                     // the integer position moved: new block, new residual sums
                     cjx = jx;
                     cjy = jy;
-                    load_next_block<RMAX>(B, jx + qx, jy + qy0, active, qa, qd);
+                    load_next_block<RMAX>(B, jx + qx, jy + qy0, active, qa, qb);
                     float e[8];
-                    residual_partials<RMAX>(I, Ix, Iy, qa, qd, e);
+                    residual_partials<RMAX>(Ix, Iy, qa, qb, e);
                     const float t8 = vs::wave_transpose_sum<8>(e);
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) E[j] = vs::transposed_total<8>(t8, j);
+                    e_from_sums(Sx, vs::transposed_total<8>(t8, 0), vs::transposed_total<8>(t8, 1),
+                                vs::transposed_total<8>(t8, 2), vs::transposed_total<8>(t8, 3), E);
+                    e_from_sums(Sy, vs::transposed_total<8>(t8, 4), vs::transposed_total<8>(t8, 5),
+                                vs::transposed_total<8>(t8, 6), vs::transposed_total<8>(t8, 7), E + 4);
                 }
                 const float b1 = E[0] - fmaf(ja, fmaf(jb, E[3], E[1]), jb * E[2]);
                 const float b2 = E[4] - fmaf(ja, fmaf(jb, E[7], E[5]), jb * E[6]);
