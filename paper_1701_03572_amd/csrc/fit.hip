@@ -1,9 +1,10 @@
 // fit_similarity / fit_motion: seeded robust rigid / similarity / affine fit, hybrid dwell switch
 // and skip rule.
 //
-// Kernel 1 (fit_pair): one 256-thread workgroup per pair. The valid slots are compacted in slot
-// order into LDS (raw FP32 coordinates, centred exactly in binary64 when read), then each
-// requested model is fitted:
+// Kernel 1 (fit_pair): one 256-thread workgroup per pair, with LDS sized to the capacity (19 bytes
+// per point slot) and registers capped for three workgroups per CU, so pairs overlap each other's
+// LDS and FP64 latencies. The valid slots are compacted in slot order into LDS (raw FP32
+// coordinates, centred exactly in binary64 when read), then each requested model is fitted:
 // the 4 waves share the RANSAC hypotheses (wave w takes h = w, w + 4, ...), score them by
 // counting residuals <= threshold with a wave reduction, and the best (most inliers, then
 // smallest h) is refitted by least squares in binary64: the similarity through its 4x4 normal
@@ -15,8 +16,8 @@
 //     px = (a11 x + a12 y) + tx,  py = (a21 x + a22 y) + ty      (affine)
 //     d2 = dx dx + dy dy
 // with floating-point contraction disabled, so inlier decisions are bit-reproducible.
-// Kernel 2 (fit_resolve): walks the pairs of the call in order through the dwell-block state
-// machine. Kernel 3 (fit_emit): one workgroup per pair writes the chosen model's parameters,
+// Kernel 2 (fit_resolve): the dwell-block state machine over the pairs of the call, evaluated
+// block-parallel. Kernel 3 (fit_emit): one workgroup per pair writes the chosen model's parameters,
 // info and inlier flags.
 #include <cmath>
 
@@ -101,21 +102,39 @@ struct FitArgs {
     double cx, cy;
 };
 
-// deterministic block sum of NV doubles per thread: fixed tree over the 256 threads
+// deterministic block sum of NV doubles per thread: a butterfly within each wave (every lane gets
+// the same bits), then the four wave totals added in a fixed order; every thread gets the total
 template <int NV>
-__device__ void block_sum(double (&v)[NV], double* red /* [NV][NT] */)
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* [NV][4] */)
 {
-    const int t = threadIdx.x;
-    for (int j = 0; j < NV; ++j) red[j * NT + t] = v[j];
+    const int t = threadIdx.x, wv = t >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = vs::wave_sum_d(v[j]);
+    if ((t & 63) == 0)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) red[j * 4 + wv] = v[j];
     __syncthreads();
-    for (int o = NT / 2; o > 0; o >>= 1) {
-        if (t < o)
-            for (int j = 0; j < NV; ++j) red[j * NT + t] += red[j * NT + t + o];
-        __syncthreads();
-    }
-    for (int j = 0; j < NV; ++j) v[j] = red[j * NT];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = (red[j * 4] + red[j * 4 + 1]) + (red[j * 4 + 2] + red[j * 4 + 3]);
     __syncthreads();
 }
+
+// deterministic block sum of one int per thread (wave sums, then the four in order)
+__device__ __forceinline__ int block_sum_i(int v, int* red4)
+{
+    const int t = threadIdx.x;
+    v = vs::wave_sum_i(v);
+    if ((t & 63) == 0) red4[t >> 6] = v;
+    __syncthreads();
+    v = (red4[0] + red4[1]) + (red4[2] + red4[3]);
+    __syncthreads();
+    return v;
+}
+
+// per-pair LDS: the compacted points (4 float arrays), their slots and inlier flags, for a capacity
+// rounded up to 64
+__host__ __device__ inline int lds_cap(int capacity) { return (capacity + 63) & ~63; }
+__host__ __device__ inline size_t pair_lds_bytes(int capacity) { return (size_t)lds_cap(capacity) * 19; }
 
 __device__ void solve4(double A[4][4], double b[4], double x[4])
 {
@@ -267,15 +286,20 @@ __device__ __forceinline__ void ls_affine(const float* xs, const float* ys, cons
     }
 }
 
-__global__ __launch_bounds__(NT) void fit_pair_kernel(const float* __restrict__ src, const float* __restrict__ dst,
+__global__ __launch_bounds__(NT, 3) void fit_pair_kernel(const float* __restrict__ src, const float* __restrict__ dst,
                                                       const uint8_t* __restrict__ valid, int capacity, FitArgs a,
                                                       int64_t pair_index0, uint8_t* ws)
 {
-    __shared__ float xs[VS_MAX_CORNERS], ys[VS_MAX_CORNERS], xd[VS_MAX_CORNERS], yd[VS_MAX_CORNERS];
-    __shared__ uint16_t slot_of[VS_MAX_CORNERS];
-    __shared__ uint8_t inl[VS_MAX_CORNERS];
-    __shared__ double red[8 * NT];
-    __shared__ int32_t s_cnt[NT];
+    extern __shared__ __attribute__((aligned(16))) unsigned char pair_lds[];
+    const int capA = lds_cap(capacity);
+    float* xs = reinterpret_cast<float*>(pair_lds);
+    float* ys = xs + capA;
+    float* xd = ys + capA;
+    float* yd = xd + capA;
+    uint16_t* slot_of = reinterpret_cast<uint16_t*>(yd + capA);
+    uint8_t* inl = reinterpret_cast<uint8_t*>(slot_of + capA);
+    __shared__ double red[8 * 4];
+    __shared__ int32_t red4[4];
     __shared__ int32_t w_score[4], w_h[4];
     __shared__ double w_model[4][6];
     __shared__ double s_out[6], s_tmp[4];
@@ -287,21 +311,26 @@ __global__ __launch_bounds__(NT) void fit_pair_kernel(const float* __restrict__ 
     uint8_t* masks = ws + item * rec_bytes(capacity) + 256;
     const int64_t base = (int64_t)item * capacity;
 
-    // ---- stable compaction of the valid slots
+    // ---- stable compaction of the valid slots: thread t owns a run of consecutive slots; an
+    // exclusive prefix of the per-thread counts (wave scan, then the wave totals in order) places them
     const int chunk = (capacity + NT - 1) / NT;
     const int c0 = t * chunk, c1 = min(capacity, c0 + chunk);
     int cnt = 0;
     for (int k = c0; k < c1; ++k) cnt += valid[base + k] != 0;
-    s_cnt[t] = cnt;
-    __syncthreads();
-    if (t == 0) {
-        int run = 0;
-        for (int i = 0; i < NT; ++i) { const int c = s_cnt[i]; s_cnt[i] = run; run += c; }
-        s_n = run;
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
     }
+    if (lane == 63) red4[wv] = incl;
+    __syncthreads();
+    int wbase = 0;
+    for (int w = 0; w < wv; ++w) wbase += red4[w];
+    if (t == 0) s_n = (red4[0] + red4[1]) + (red4[2] + red4[3]);
     __syncthreads();
     {
-        int o = s_cnt[t];
+        int o = wbase + incl - cnt;
         for (int k = c0; k < c1; ++k) {
             if (!valid[base + k]) continue;
             xs[o] = src[2 * (base + k)];          // raw FP32 pixel coordinates; centred in binary64
@@ -421,13 +450,8 @@ __global__ __launch_bounds__(NT) void fit_pair_kernel(const float* __restrict__ 
                     inl[i] = f;
                     m += f;
                 }
-                s_cnt[t] = m;
-                __syncthreads();
-                if (t == 0) {
-                    int tot = 0;
-                    for (int i = 0; i < NT; ++i) tot += s_cnt[i];
-                    s_ninl = tot;
-                }
+                m = block_sum_i(m, red4);
+                if (t == 0) s_ninl = m;
                 __syncthreads();
                 have = s_ninl >= (affine ? 3 : 2);
             }
@@ -463,64 +487,99 @@ __global__ __launch_bounds__(NT) void fit_pair_kernel(const float* __restrict__ 
     }
 }
 
-// Runs the dwell-block state machine over the pairs of the call in order (one thread, on
-// per-pair fields staged in LDS) and records each pair's choice in its workspace record.
+// Runs the dwell-block state machine over the pairs of the call and records each pair's choice in
+// its workspace record. It is evaluated block-parallel, with the same result as walking the pairs in
+// order: a block's decision pair is its first non-skipped pair in the call (none if the incoming
+// state already decided that block); the model in force before it is the last decision of an earlier
+// block (or the incoming model); pairs from the decision on use the block's decision. Blocks are
+// taken in chunks of NB: one thread per block finds the decision, one thread carries the model
+// across the chunk's blocks, then every pair of the chunk writes its choice.
+constexpr int NB = 1024;
+
+__device__ __forceinline__ int decide(int model_mode, double er, double es, double ea)
+{
+    int m = (er < es) ? VS_RIGID : VS_SIMILARITY;
+    if (model_mode == VS_HYBRID3 && ea < (m == VS_RIGID ? er : es)) m = VS_AFFINE;
+    return m;
+}
+
 __global__ __launch_bounds__(NT) void fit_resolve_kernel(int n, int capacity, FitArgs a, int64_t pair_index0,
                                                          vs_fit_state* state, uint8_t* ws)
 {
-    __shared__ int8_t skipped[1024];
-    __shared__ double er[1024], es[1024], ea[1024];
-    __shared__ int8_t choice[1024], decided[1024];
+    __shared__ int32_t dec_pair[NB];
+    __shared__ int8_t dec_model[NB], model_before[NB];
+    __shared__ int32_t s_carry;
     const int t = threadIdx.x;
-    vs_fit_state st;
-    if (t == 0) st = *state;
-    for (int c0 = 0; c0 < n; c0 += 1024) {
-        const int c1 = min(n, c0 + 1024);
-        for (int i = c0 + t; i < c1; i += NT) {
-            const PairRec* rec = reinterpret_cast<const PairRec*>(ws + i * rec_bytes(capacity));
-            skipped[i - c0] = (int8_t)rec->skipped;
-            er[i - c0] = rec->m[0].err;
-            es[i - c0] = rec->m[1].err;
-            ea[i - c0] = rec->m[2].err;
-        }
-        __syncthreads();
-        if (t == 0) {
-            const bool hybrid = a.model == VS_HYBRID || a.model == VS_HYBRID3;
-            for (int i = c0; i < c1; ++i) {
-                const int64_t pair = pair_index0 + i;
-                const int64_t block = pair / (a.dwell > 0 ? a.dwell : 1);
-                if (st.block != block) {
-                    st.block = block;
-                    st.decided = 0;
-                }
-                int ch, dh = 0;
-                if (skipped[i - c0]) {
-                    ch = -1 - (hybrid ? st.model : a.model);   // identity, reported model
-                } else if (hybrid) {
-                    if (!st.decided) {
-                        st.model = (er[i - c0] < es[i - c0]) ? VS_RIGID : VS_SIMILARITY;
-                        if (a.model == VS_HYBRID3 && ea[i - c0] < (st.model == VS_RIGID ? er[i - c0] : es[i - c0]))
-                            st.model = VS_AFFINE;
-                        st.decided = 1;
-                        dh = 1;
+    const vs_fit_state st_in = *state;
+    const bool hybrid = a.model == VS_HYBRID || a.model == VS_HYBRID3;
+    const int64_t dw = a.dwell > 0 ? a.dwell : 1;
+    const int64_t blk_first = pair_index0 / dw, blk_last = (pair_index0 + n - 1) / dw;
+    const bool first_done = st_in.block == blk_first && st_in.decided;   // block decided by an earlier call
+    if (t == 0) s_carry = st_in.model;
+    __syncthreads();
+    for (int64_t b0 = blk_first; b0 <= blk_last; b0 += NB) {
+        const int nb = (int)min((int64_t)NB, blk_last - b0 + 1);
+        // 1. decision pair and model of every block of the chunk
+        for (int k = t; k < nb; k += NT) {
+            const int64_t b = b0 + k;
+            const int64_t p0 = max(b * dw, pair_index0) - pair_index0;
+            const int64_t p1 = min((b + 1) * dw, pair_index0 + n) - pair_index0;
+            int dp = -1, dm = -1;
+            if (hybrid && !(b == blk_first && first_done)) {
+                for (int64_t i = p0; i < p1; ++i) {
+                    const PairRec* rec = reinterpret_cast<const PairRec*>(ws + i * rec_bytes(capacity));
+                    if (!rec->skipped) {
+                        dp = (int)i;
+                        dm = decide(a.model, rec->m[0].err, rec->m[1].err, rec->m[2].err);
+                        break;
                     }
-                    ch = st.model;
-                } else {
-                    ch = a.model;
                 }
-                choice[i - c0] = (int8_t)ch;
-                decided[i - c0] = (int8_t)dh;
             }
+            dec_pair[k] = dp;
+            dec_model[k] = (int8_t)dm;
         }
         __syncthreads();
-        for (int i = c0 + t; i < c1; i += NT) {
+        // 2. model in force at the start of every block
+        if (t == 0) {
+            int carry = s_carry;
+            for (int k = 0; k < nb; ++k) {
+                model_before[k] = (int8_t)carry;
+                if (dec_model[k] >= 0) carry = dec_model[k];
+            }
+            s_carry = carry;
+        }
+        __syncthreads();
+        // 3. every pair of the chunk's blocks
+        const int64_t q0 = max(b0 * dw, pair_index0) - pair_index0;
+        const int64_t q1 = min((b0 + nb) * dw, pair_index0 + n) - pair_index0;
+        for (int64_t i = q0 + t; i < q1; i += NT) {
             PairRec* rec = reinterpret_cast<PairRec*>(ws + i * rec_bytes(capacity));
-            rec->pad[0] = choice[i - c0];
-            rec->pad[1] = decided[i - c0];
+            const int k = (int)((pair_index0 + i) / dw - b0);
+            int m = a.model, dh = 0;
+            if (hybrid) {
+                const int dp = dec_pair[k];
+                m = (dp >= 0 && i >= dp) ? dec_model[k] : model_before[k];
+                dh = dp == (int)i;
+            }
+            rec->pad[0] = rec->skipped ? -1 - m : m;   // a skipped pair is the identity under the reported model
+            rec->pad[1] = dh;
         }
         __syncthreads();
     }
-    if (t == 0) *state = st;
+    if (t == 0) {
+        vs_fit_state st = st_in;
+        if (st.block != blk_last) {
+            st.block = blk_last;
+            st.decided = 0;
+        }
+        if (hybrid) {
+            st.model = s_carry;
+            // the last block is decided if its decision pair lies in this call (or an earlier call made it)
+            const int64_t k_last = (blk_last - blk_first) % NB;
+            if (dec_pair[k_last] >= 0) st.decided = 1;
+        }
+        *state = st;
+    }
 }
 
 // One workgroup per pair: writes the chosen model's parameters (an affine as its nearest
@@ -634,7 +693,14 @@ extern "C" int vs_fit_motion(const float* src, const float* dst, const uint8_t* 
     a.cy = p->cy;
     hipStream_t s = vs::as_stream(stream);
     uint8_t* w8 = static_cast<uint8_t*>(workspace);
-    fit_pair_kernel<<<n, NT, 0, s>>>(src, dst, valid, capacity, a, pair_index0, w8);
+    const size_t lds = pair_lds_bytes(capacity);
+    if (lds > 65536) {
+        // capacities above ~3400 points need more than the default 64 KiB of dynamic LDS
+        const hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(&fit_pair_kernel),
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (he != hipSuccess) return vs::set_error(VS_ERR_HIP, "vs_fit_motion: %s", hipGetErrorString(he));
+    }
+    fit_pair_kernel<<<n, NT, lds, s>>>(src, dst, valid, capacity, a, pair_index0, w8);
     int e = vs::check_launch("vs_fit_motion(pairs)");
     if (e) return e;
     fit_resolve_kernel<<<1, NT, 0, s>>>(n, capacity, a, pair_index0, state, w8);

@@ -142,6 +142,30 @@ def test_hybrid_blocks_skips_and_split_calls():
             assert a[k] == b[k] or (a[k] != a[k] and b[k] != b[k]), k     # equal, or both NaN
 
 
+@pytest.mark.parametrize("dwell", [1, 3, 7])
+@pytest.mark.parametrize("model", [V.VS_HYBRID, V.VS_HYBRID3])
+def test_dwell_state_machine_random_skips_and_splits(dwell, model):
+    """The block-parallel dwell resolution equals the oracle's pair-by-pair walk: random skip runs,
+    several dwell lengths, the stream fed in calls of random lengths."""
+    rng = np.random.default_rng(dwell * 10 + model)
+    n_pairs = 47
+    small = set(np.nonzero(rng.random(n_pairs) < 0.3)[0].tolist()) | {5, 6, 7}
+    src, dst, valid = make_pairs(n_pairs, 64, 40 + dwell, small=small, shear=0.02 if model == V.VS_HYBRID3 else 0.0)
+    r, _ = oracle_fit(src, dst, valid, model, 8, dwell=dwell)
+    whole = gpu_fit(src, dst, valid, model, 8, dwell=dwell, with_affine=True)
+    check(whole[:3], r, whole[4])
+    st = torch.zeros(V.FIT_STATE_BYTES, dtype=torch.uint8, device="cuda")
+    V.vs_fit_state_init(st)
+    cuts = sorted(set([0, n_pairs] + rng.integers(1, n_pairs, 6).tolist()))
+    infos = []
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        part = gpu_fit(src[a:b], dst[a:b], valid[a:b], model, 8, pair0=a, state=st, dwell=dwell)
+        infos += part[1]
+        np.testing.assert_array_equal(part[0], whole[0][a:b])
+    for p, (g, w) in enumerate(zip(infos, whole[1])):
+        assert g["model"] == w["model"] and g["decided_here"] == w["decided_here"] and g["skipped"] == w["skipped"], p
+
+
 def test_capacity_4096_and_exact_recovery():
     say("fit 4096")
     rng = np.random.default_rng(3)
