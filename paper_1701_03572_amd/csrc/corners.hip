@@ -408,6 +408,28 @@ __device__ __forceinline__ bool before(uint64_t ka, uint32_t ia, uint64_t kb, ui
     return ka > kb || (ka == kb && ia < ib);
 }
 
+// Calls f(key, index) for every candidate of the list, thread tid taking i = tid, tid + 1024, ...
+// Eight loads per thread are issued before any is used, so a pass is not a chain of dependent
+// global-memory latencies.
+template <typename F>
+__device__ __forceinline__ void for_each_key(const uint64_t* keys, const uint32_t* idx, uint32_t N, int tid, F f)
+{
+    constexpr int UNR = 8;
+    for (uint32_t i0 = tid; i0 < N; i0 += 1024 * UNR) {
+        uint64_t kb[UNR];
+        uint32_t ix[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const uint32_t i = i0 + 1024u * u;
+            kb[u] = i < N ? keys[i] : 0;
+            ix[u] = i < N ? idx[i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+            if (i0 + 1024u * u < N) f(kb[u], ix[u]);
+    }
+}
+
 __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_t item_bytes, int W, int H,
                                                              int istride, const int32_t* gate, int gate_min, int Kmax,
                                                              const int32_t* k_items, double quality, int min_dist,
@@ -458,12 +480,9 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
     while (!s_done) {
         // ---- 1) count the eligible keys below U
         uint32_t cnt = 0;
-        for (uint32_t i = tid; i < N; i += 1024) {
-            const uint64_t kb = keys[i];
-            if (kb < base) continue;
-            if (!unbounded && comp(kb, idx[i], base) >= U) continue;
-            ++cnt;
-        }
+        for_each_key(keys, idx, N, tid, [&](uint64_t kb, uint32_t ix) {
+            if (kb >= base && (unbounded || comp(kb, ix, base) < U)) ++cnt;
+        });
         cnt = (uint32_t)vs::wave_sum_i((int)cnt);
         if (lane == 0) s_red[wv] = cnt;
         __syncthreads();
@@ -485,14 +504,13 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
                 shift -= db;
                 for (int b = tid; b < NBIN; b += 1024) hist[b] = 0;
                 __syncthreads();
-                for (uint32_t i = tid; i < N; i += 1024) {
-                    const uint64_t kb = keys[i];
-                    if (kb < base) continue;
-                    const u128 v = comp(kb, idx[i], base);
-                    if (!unbounded && v >= U) continue;
-                    if (pshift < 128 && (v >> pshift) != prefix) continue;
+                for_each_key(keys, idx, N, tid, [&](uint64_t kb, uint32_t ix) {
+                    if (kb < base) return;
+                    const u128 v = comp(kb, ix, base);
+                    if (!unbounded && v >= U) return;
+                    if (pshift < 128 && (v >> pshift) != prefix) return;
                     atomicAdd(&hist[(uint32_t)(v >> shift) & ((1u << db) - 1u)], 1u);
-                }
+                });
                 __syncthreads();
                 // suffix sums from the top digit (Hillis-Steele in place over NBIN bins)
                 for (int o = 1; o < NBIN; o <<= 1) {
@@ -536,18 +554,16 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
         // ---- 3) gather [T, U) into LDS
         if (tid == 0) s_bcount = 0;
         __syncthreads();
-        for (uint32_t i = tid; i < N; i += 1024) {
-            const uint64_t kb = keys[i];
-            if (kb < base) continue;
-            const uint32_t ix = idx[i];
+        for_each_key(keys, idx, N, tid, [&](uint64_t kb, uint32_t ix) {
+            if (kb < base) return;
             const u128 v = comp(kb, ix, base);
-            if (v < T || (!unbounded && v >= U)) continue;
+            if (v < T || (!unbounded && v >= U)) return;
             const int slot = atomicAdd(&s_bcount, 1);
             if (slot < CAP) {          // always true by construction of T; keeps LDS writes in range
                 bkey[slot] = kb;
                 bidx[slot] = ix;
             }
-        }
+        });
         __syncthreads();
         const int bc = s_bcount < CAP ? s_bcount : CAP;
         int p2 = 1;
@@ -588,9 +604,16 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
             if (g0 + lane < bc) {
                 const int cx = s_cx[lane], cy = s_cy[lane];
                 bool conf = false;
-                for (int j = wv; j < na; j += 16) {
-                    const int64_t dx = cx - acc_x[j], dy = cy - acc_y[j];
-                    if (dx * dx + dy * dy < d2) { conf = true; break; }
+                // wave wv checks accepted corners wv, wv + 16, ...; four independent reads per step
+                for (int j = wv; j < na && !conf; j += 64) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int jj = j + 16 * u;
+                        if (jj < na) {
+                            const int64_t dx = cx - acc_x[jj], dy = cy - acc_y[jj];
+                            conf = conf || dx * dx + dy * dy < d2;
+                        }
+                    }
                 }
                 if (conf) s_conf[lane] = 1;
             }
@@ -607,12 +630,15 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
                 const uint32_t pre = valid ? s_conf[lane] : 1u;
                 uint64_t acc_mask = 0;
                 int cnt_acc = na;
-                for (int k = 0; k < 64; ++k) {
-                    const uint32_t pk = __builtin_amdgcn_readlane(pre, k);
+                // in group order, over the members not already too close to an accepted corner
+                uint64_t todo = __ballot(pre == 0);
+                while (todo && cnt_acc < K) {
+                    const int k = __builtin_ctzll(todo);
+                    todo &= todo - 1;
                     const uint32_t mlo = __builtin_amdgcn_readlane((uint32_t)mask, k);
                     const uint32_t mhi = __builtin_amdgcn_readlane((uint32_t)(mask >> 32), k);
                     const uint64_t mk = ((uint64_t)mhi << 32) | mlo;
-                    if (!pk && !(mk & acc_mask) && cnt_acc < K) {
+                    if (!(mk & acc_mask)) {
                         acc_mask |= 1ull << k;
                         ++cnt_acc;
                     }
