@@ -16,6 +16,7 @@ CPU oracle timed on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -156,6 +157,11 @@ def main() -> int:
     ap.add_argument("--batched-frames", type=int, default=120)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-seconds", type=float, default=4.0)
+    ap.add_argument("--tuning", choices=["auto", "default", "cached"], default="auto",
+                    help="launch tuning: autotune on the workload before timing (default), the library defaults, "
+                         "or the cached choice for this class (--tuning-cache)")
+    ap.add_argument("--tuning-cache", default=None, help="JSON cache of the autotuner (default: its per-user cache)")
+    ap.add_argument("--tune-only", action="store_true", help="autotune, store the choice, print it and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one elementwise kernel that reads and writes exactly 256 MiB (torch neg of "
                          "float32), the reference for scaling hardware byte counters")
@@ -185,7 +191,30 @@ def main() -> int:
     torch.cuda.synchronize()
     log("generated in %.1f s" % (time.time() - t0))
 
+    from paper_1701_03572_amd import tuning as T
+    tuning = {"mode": args.tuning}
     ss = SequenceStabilizer(W, H, n, P)
+    if args.tuning == "auto" or args.tune_only:
+        # every candidate timed on the whole sequence step (ms per step in timings_ms)
+        t, timings = T.autotune(frames, P.max_corners, P.levels, path=args.tuning_cache, reps=1, rounds=3,
+                                step=lambda: ss.run(frames))
+        tuning.update(choice=dataclasses.asdict(t), timings_ms={k: {c: round(v, 4) for c, v in d.items()}
+                                                                 for k, d in timings.items()})
+        log("autotuned launch choices: %s" % (t,))
+        if args.tune_only:
+            print(json.dumps(tuning))
+            return 0
+    elif args.tuning == "cached":
+        t = T.apply(W, H, P.max_corners, args.tuning_cache)
+        if t is None:
+            print("no cached tuning for this class in %s" % (args.tuning_cache or T.default_cache_path()),
+                  file=sys.stderr)
+            return 2
+        tuning["choice"] = dataclasses.asdict(t)
+    else:
+        T.set_tuning(None)
+        tuning["choice"] = dataclasses.asdict(T.get_tuning())
+
     for i in range(args.warmup):
         ss.run(frames)
         torch.cuda.synchronize()
@@ -314,6 +343,7 @@ def main() -> int:
         "plain_path": plain,
         "batched": batched,
         "serving": serving,
+        "tuning": tuning,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

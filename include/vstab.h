@@ -310,6 +310,25 @@ int vs_photometric_refine(const uint8_t* prev, const uint8_t* next, int64_t fram
                           size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * tuning -- launch-shape choices that change speed only, never a result bit (the choices only
+ * reorder independent workgroups or group independent waves). Process-wide; a call reads the
+ * values current when it is made, so settings may change between calls from any thread.
+ *   xcd_min_items_{pyramid,lk,warp}: batches of at least this many items keep each item's
+ *     workgroups on one XCD (one L2); 0 selects the default (8); 1 always, 65536 never.
+ *   lk_points_per_group: points (one wave each) per tracking workgroup, 1, 2 or 4; 0: default (1).
+ * vs_set_tuning(NULL) restores the defaults. Values out of range: VS_ERR_INVALID, nothing changed.
+ * vs_get_tuning reports the values in force (defaults resolved). Both are host-only. */
+typedef struct {
+    int32_t xcd_min_items_pyramid;
+    int32_t xcd_min_items_lk;
+    int32_t xcd_min_items_warp;
+    int32_t lk_points_per_group;
+} vs_tuning;
+
+int vs_set_tuning(const vs_tuning* t);
+int vs_get_tuning(vs_tuning* t);
+
+/* ---------------------------------------------------------------------------------------------
  * misc */
 const char* vs_last_error(void);   /* thread-local message of the last failing call */
 int vs_version(void);

@@ -1,4 +1,5 @@
-// Error reporting, version and the pyramid layout query of libvstab.
+// Error reporting, version, launch tuning and the pyramid layout query of libvstab.
+#include <atomic>
 #include <cstdarg>
 
 #include "vs_common.hpp"
@@ -23,7 +24,49 @@ int check_launch(const char* what)
     return VS_OK;
 }
 
+// launch tuning: speed-only choices, read by each call when it launches
+static std::atomic<int> g_xcd_pyr{VS_XCD_MIN_ITEMS}, g_xcd_lk{VS_XCD_MIN_ITEMS}, g_xcd_warp{VS_XCD_MIN_ITEMS};
+static std::atomic<int> g_lk_ppg{1};
+
+int xcd_min_items(int kernel)
+{
+    switch (kernel) {
+    case XCD_PYRAMID: return g_xcd_pyr.load(std::memory_order_relaxed);
+    case XCD_LK: return g_xcd_lk.load(std::memory_order_relaxed);
+    default: return g_xcd_warp.load(std::memory_order_relaxed);
+    }
+}
+
+int lk_points_per_group() { return g_lk_ppg.load(std::memory_order_relaxed); }
+
 }  // namespace vs
+
+extern "C" int vs_set_tuning(const vs_tuning* t)
+{
+    vs_tuning v{0, 0, 0, 0};
+    if (t) v = *t;
+    const int xs[3] = {v.xcd_min_items_pyramid, v.xcd_min_items_lk, v.xcd_min_items_warp};
+    for (int x : xs)
+        if (x < 0 || x > 65536) return vs::set_error(VS_ERR_INVALID, "vs_set_tuning: xcd_min_items must be 0..65536");
+    if (!(v.lk_points_per_group == 0 || v.lk_points_per_group == 1 || v.lk_points_per_group == 2 ||
+          v.lk_points_per_group == 4))
+        return vs::set_error(VS_ERR_INVALID, "vs_set_tuning: lk_points_per_group must be 0, 1, 2 or 4");
+    vs::g_xcd_pyr.store(xs[0] ? xs[0] : VS_XCD_MIN_ITEMS);
+    vs::g_xcd_lk.store(xs[1] ? xs[1] : VS_XCD_MIN_ITEMS);
+    vs::g_xcd_warp.store(xs[2] ? xs[2] : VS_XCD_MIN_ITEMS);
+    vs::g_lk_ppg.store(v.lk_points_per_group ? v.lk_points_per_group : 1);
+    return VS_OK;
+}
+
+extern "C" int vs_get_tuning(vs_tuning* t)
+{
+    if (!t) return vs::set_error(VS_ERR_INVALID, "vs_get_tuning: null output");
+    t->xcd_min_items_pyramid = vs::g_xcd_pyr.load();
+    t->xcd_min_items_lk = vs::g_xcd_lk.load();
+    t->xcd_min_items_warp = vs::g_xcd_warp.load();
+    t->lk_points_per_group = vs::g_lk_ppg.load();
+    return VS_OK;
+}
 
 extern "C" const char* vs_last_error(void) { return vs::g_err; }
 

@@ -289,7 +289,7 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
 }
 
 template <int RMAX>
-__global__ __launch_bounds__(64) void lk_kernel(const uint8_t* __restrict__ prev_frames,
+__global__ __launch_bounds__(256) void lk_kernel(const uint8_t* __restrict__ prev_frames,
                                                 const uint8_t* __restrict__ prev_pyrs,
                                                 const uint8_t* __restrict__ next_frames,
                                                 const uint8_t* __restrict__ next_pyrs, int64_t frame_stride,
@@ -299,11 +299,16 @@ __global__ __launch_bounds__(64) void lk_kernel(const uint8_t* __restrict__ prev
                                                 int32_t* n_valid, float* xy_chain, uint8_t* alive_chain,
                                                 unsigned long long* work, int n_items, int by_xcd)
 {
-    // all point slots of an item run on one XCD, so the overlapping windows of its frame pair are
-    // shared in that XCD's L2
-    int item, slot;
-    if (!vs::xcd_map(blockIdx.x, n_items, capacity, by_xcd != 0, item, slot)) return;
-    const int lane = threadIdx.x;
+    // each wave of the workgroup tracks one point slot on its own (no barriers): slot = group *
+    // waves + wave. All point slots of an item run on one XCD, so the overlapping windows of its
+    // frame pair are shared in that XCD's L2.
+    const int ppg = blockDim.x >> 6;
+    const int groups = (capacity + ppg - 1) / ppg;
+    int item, group;
+    if (!vs::xcd_map(blockIdx.x, n_items, groups, by_xcd != 0, item, group)) return;
+    const int slot = group * ppg + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
+    if (slot >= capacity) return;
+    const int lane = threadIdx.x & 63;
     const int64_t rec = (int64_t)item * istride;
     const int64_t k = rec * capacity + slot;
     const float ux = xy_prev[2 * k], uy = xy_prev[2 * k + 1];
@@ -393,16 +398,18 @@ extern "C" int vs_track_lk(const uint8_t* prev_frames, const uint8_t* prev_pyrs,
         if (e) return e;
     }
     const vs::LevelDesc d = vs::level_desc(*layout);
-    const bool by_xcd = n >= VS_XCD_MIN_ITEMS;
-    const int64_t nblk = vs::xcd_grid(n, capacity, by_xcd);
+    const bool by_xcd = n >= vs::xcd_min_items(vs::XCD_LK);
+    const int ppg = vs::lk_points_per_group();
+    const int64_t nblk = vs::xcd_grid(n, (capacity + ppg - 1) / ppg, by_xcd);
     if (nblk > 0x7fffffff) return vs::set_error(VS_ERR_INVALID, "vs_track_lk: grid too large");
     const unsigned grid = (unsigned)nblk;
+    const unsigned threads = 64u * (unsigned)ppg;
     if (c.rows <= 7)
-        lk_kernel<7><<<grid, 64, 0, s>>>(prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride,
+        lk_kernel<7><<<grid, threads, 0, s>>>(prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride,
                                          istride, d, xy_prev, alive_prev, capacity, c, p->fb, p->fb_thresh, xy_next,
                                          status, fb_err, n_valid, xy_chain, alive_chain, wk, n, by_xcd);
     else
-        lk_kernel<16><<<grid, 64, 0, s>>>(prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride,
+        lk_kernel<16><<<grid, threads, 0, s>>>(prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride,
                                           istride, d, xy_prev, alive_prev, capacity, c, p->fb, p->fb_thresh, xy_next,
                                           status, fb_err, n_valid, xy_chain, alive_chain, wk, n, by_xcd);
     return vs::check_launch("vs_track_lk");

@@ -137,7 +137,7 @@ extern "C" int vs_build_pyramid(const uint8_t* frames, int64_t frame_stride, uin
     if ((int64_t)layout->pitch[0] * layout->height[0] >= ((int64_t)1 << 31))
         return vs::set_error(VS_ERR_UNSUPPORTED, "vs_build_pyramid: frame larger than 2 GiB");
     hipStream_t s = vs::as_stream(stream);
-    const bool by_xcd = n >= VS_XCD_MIN_ITEMS;
+    const bool by_xcd = n >= vs::xcd_min_items(vs::XCD_PYRAMID);
     for (int l = 1; l < layout->levels; ++l) {
         const uint8_t* src = (l == 1) ? frames : pyrs + layout->offset[l - 1];
         const int64_t sstride = (l == 1) ? frame_stride : pyr_stride;

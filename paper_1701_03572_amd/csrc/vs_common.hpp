@@ -19,6 +19,12 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // Checks the launch that was just enqueued.
 int check_launch(const char* what);
 
+// Launch tuning in force (vs_set_tuning): batches of at least xcd_min_items(k) items use the
+// per-XCD mapping for kernel family k; tracking workgroups hold lk_points_per_group() points.
+enum { XCD_PYRAMID = 0, XCD_LK = 1, XCD_WARP = 2 };
+int xcd_min_items(int kernel);
+int lk_points_per_group();
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Wave64 butterfly sum: every lane ends with the same, bit-identical total (each stage adds the

@@ -225,7 +225,7 @@ extern "C" int vs_warp_frame(const uint8_t* src, int64_t src_stride, int32_t wid
     if (n > 1 && (mat_stride < 6 || src_stride < (int64_t)src_pitch * height || dst_stride < (int64_t)dst_pitch * height))
         return vs::set_error(VS_ERR_INVALID, "vs_warp_frame: strides overlap items");
     const int tiles_x = (width + TW - 1) / TW, tiles_y = (height + TH - 1) / TH;
-    const bool by_xcd = n >= VS_XCD_MIN_ITEMS;
+    const bool by_xcd = n >= vs::xcd_min_items(vs::XCD_WARP);
     const int64_t nblk = vs::xcd_grid(n, tiles_x * tiles_y, by_xcd);
     if (nblk > 0x7fffffff) return vs::set_error(VS_ERR_INVALID, "vs_warp_frame: grid too large");
     // 16-byte staging loads need 16-byte aligned rows in every item

@@ -26,6 +26,11 @@ class VsError(RuntimeError):
     pass
 
 
+class vs_tuning(C.Structure):
+    _fields_ = [("xcd_min_items_pyramid", C.c_int32), ("xcd_min_items_lk", C.c_int32),
+                ("xcd_min_items_warp", C.c_int32), ("lk_points_per_group", C.c_int32)]
+
+
 class vs_pyramid(C.Structure):
     _fields_ = [("levels", C.c_int32), ("width", C.c_int32 * VS_MAX_LEVELS), ("height", C.c_int32 * VS_MAX_LEVELS),
                 ("pitch", C.c_int32 * VS_MAX_LEVELS), ("offset", C.c_int64 * VS_MAX_LEVELS), ("bytes", C.c_int64)]
@@ -107,6 +112,8 @@ _SIGS = {
     "vs_photometric_refine": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P,
                                         C.c_int64, C.c_int32, _P, C.c_int64, C.c_double, C.c_double, C.c_double,
                                         C.POINTER(vs_rect), C.c_int32, _P, _P, _P, C.c_size_t, _P]),
+    "vs_set_tuning": (C.c_int, [C.POINTER(vs_tuning)]),
+    "vs_get_tuning": (C.c_int, [C.POINTER(vs_tuning)]),
     "vs_last_error": (C.c_char_p, []),
     "vs_version": (C.c_int, []),
 }
@@ -164,6 +171,16 @@ def _check(rc: int, what: str):
 
 def vs_version() -> int:
     return load().vs_version()
+
+
+def vs_set_tuning(t: "vs_tuning | None"):
+    _check(load().vs_set_tuning(None if t is None else C.byref(t)), "vs_set_tuning")
+
+
+def vs_get_tuning() -> vs_tuning:
+    t = vs_tuning()
+    _check(load().vs_get_tuning(C.byref(t)), "vs_get_tuning")
+    return t
 
 
 def vs_pyramid_layout(width: int, height: int, pitch0: int, levels: int) -> vs_pyramid:
