@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 LK_FLOP_SETUP_PER_SAMPLE = 43
 LK_FLOP_ITER_PER_SAMPLE = 14
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
 # rocprofv3 summary of this workload (kernel trace + FETCH_SIZE / WRITE_SIZE passes)
 PROFILE = os.path.join(ROOT, "profiles", "hd1080p_600f_sequence_path.md")
 TRACKER_SOURCES = ("paper_1701_03572_amd/csrc/lk.hip", "paper_1701_03572_amd/csrc/vs_common.hpp")
@@ -61,7 +62,50 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_batched(n_streams: int, n_frames: int, steps: int, warmup: int) -> dict:
+def hbm_figures(V, ss, frames, P, n: int, W: int, H: int, ms_per_step: float) -> dict:
+    """Achieved bandwidth of the HBM-bound launches (pyramid, warp) over all frames, timed with HIP
+    events on the launch stream after the timed steps, and the whole step's algorithmic bytes over
+    the step time. Algorithmic bytes per frame: pyramid = every level read once and every level above
+    0 written once; warp = frame read + frame written; detection = one frame read every 5th frame;
+    tracking = per level the window footprints of the K points (a (2h+3)^2 block on the set-up
+    frame, (2h+2)^2 on the other), counted once and capped at the level size, doubled by the
+    backward check."""
+    import torch
+    L = ss.layout
+    sizes = [L.width[l] * L.height[l] for l in range(L.levels)]
+    pyr_b = float(sum(sizes[:-1]) + sum(sizes[1:]))
+    warp_b = 2.0 * W * H
+    det_b = W * H / P.redetect_every
+    w_set, w_oth = (2 * P.win_half + 3) ** 2, (2 * P.win_half + 2) ** 2
+    lk_b = sum(min(s, P.max_corners * w_set) + min(s, P.max_corners * w_oth) for s in sizes) * (2 if P.fb else 1)
+    fs = W * H
+
+    def timed(fn, k=3):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(k):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k
+
+    pyr_ms = timed(lambda: V.vs_build_pyramid(frames, fs, ss.pyr, L.bytes, n, L))
+    warp_ms = timed(lambda: V.vs_warp_frame(frames, fs, W, H, W, ss.mats, 6, ss.out, fs, W, n, P.border))
+    per_frame = pyr_b + warp_b + det_b + lk_b
+
+    def fig(b, ms):
+        gbs = b * n / (ms / 1e3) / 1e9
+        return {"bytes_per_frame": b, "ms": round(ms, 4), "achieved_gb_s": round(gbs, 1),
+                "peak_gb_s": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+    return {"pyramid": fig(pyr_b, pyr_ms), "warp": fig(warp_b, warp_ms),
+            "step": dict(fig(per_frame, ms_per_step), parts_per_frame={"pyramid": pyr_b, "warp": warp_b,
+                                                                        "detect": det_b, "track": lk_b})}
+
+
+def run_batched(n_streams: int, n_frames: int, steps: int, warmup: int, cpu_frames: int = 0) -> dict:
     """Heterogeneous batch: n_streams independent streams of mixed resolution (320x240 .. 1920x1080),
     corner budget U[100, 2000] and 3-5 levels, all frames resident; one step stabilizes every frame of
     every stream. Timed eagerly and as a replayed HIP graph of the same step."""
@@ -105,7 +149,35 @@ def run_batched(n_streams: int, n_frames: int, steps: int, warmup: int) -> dict:
         (n_streams, total, eager_ms, res["frames_per_s_eager"], graph_ms, res["frames_per_s_graph"]))
     del ms
     torch.cuda.empty_cache()
+    if cpu_frames > 0:
+        res["cpu_baseline"] = batched_cpu_baseline(n_streams, n_frames, cpu_frames)
+        log("batched oracle: %.2f frames/s on %d threads" % (res["cpu_baseline"]["value"], res["cpu_baseline"]["cores"]))
     return res
+
+
+def batched_cpu_baseline(n_streams: int, n_frames: int, cpu_frames: int) -> dict:
+    """The oracle on a bounded sample of the same mix: the first ``cpu_frames`` frames of the first
+    W streams, one stream per host thread (W = the host threads available, at most 16). The oracle is
+    C behind ctypes, which releases the interpreter lock during each call, and keeps no global state,
+    so the threads run in parallel."""
+    import concurrent.futures as cf
+
+    from oracle import oracle as O
+    from paper_1701_03572_amd import params, synth
+
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    mix = synth.mixed_streams(n_streams, n_frames)[:workers]
+    jobs = []
+    for s, (r, k, levels) in enumerate(mix):
+        P = params.PRESETS["vga"].replace(levels=levels, max_corners=k, stream_id=s)
+        jobs.append((synth.make_sequence(r, n_frames=cpu_frames).frames, P))
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(workers) as ex:
+        list(ex.map(lambda j: O.stabilize(j[0], j[1]), jobs))
+    wall = time.perf_counter() - t0
+    return {"value": round(len(jobs) * cpu_frames / wall, 3), "unit": "frames/s", "cores": workers, "kind": "oracle",
+            "sample": "first %d frames of the first %d streams of the same mix (%s), one stream per thread" %
+                      (cpu_frames, len(jobs), ", ".join("%dx%d" % (r.width, r.height) for r, _, _ in mix))}
 
 
 def run_serving(seconds: float) -> dict:
@@ -255,6 +327,11 @@ def main() -> int:
                 "share_of_step": round(lk_share, 4),
                 "iterations_per_setup": float(w[..., 1].sum() / max(w[..., 0].sum(), 1))}
 
+    hbm = hbm_figures(V, ss, frames, P, n, W, H, ms_per_step)
+    log("hbm: pyramid %.0f GB/s, warp %.0f GB/s; whole step %.2f MB/frame algorithmic, %.0f GB/s (%.3f of 8 TB/s)" %
+        (hbm["pyramid"]["achieved_gb_s"], hbm["warp"]["achieved_gb_s"], hbm["step"]["bytes_per_frame"] / 1e6,
+         hbm["step"]["achieved_gb_s"], hbm["step"]["frac"]))
+
     if args.calibrate_copy:
         a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -303,7 +380,8 @@ def main() -> int:
 
     batched = None
     if not args.no_batched:
-        batched = run_batched(args.batched_streams, args.batched_frames, args.steps, args.warmup)
+        batched = run_batched(args.batched_streams, args.batched_frames, args.steps, args.warmup,
+                              0 if args.no_cpu_baseline else args.cpu_frames)
 
     serving = None
     if not args.no_serving:
@@ -345,6 +423,7 @@ def main() -> int:
         "serving": serving,
         "tuning": tuning,
         "roofline": roofline,
+        "hbm": hbm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
