@@ -310,6 +310,77 @@ int vs_photometric_refine(const uint8_t* prev, const uint8_t* next, int64_t fram
                           size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * stream_push -- the real-time version of Section 6 on one stream, frame by frame, driven from
+ * native code: one call per pushed frame enqueues its pyramid, the tracking of the previous
+ * frame's points with the backward check (Sections 3.2, 4.1), the fit with the dwell switch and
+ * the skip rule (Section 4), the optional photometric refinement, the re-detection (every
+ * redetect_every frames, and on the device after a pair with fewer than min_valid points), the
+ * smoother's step with the sliding parameter store (Sections 5.1, 6) and the warps of the frames
+ * it emits (Section 5). The result equals the whole-sequence path's, frame for frame.
+ * The caller sets the geometry, parameters and device buffers below, keeps the struct (host
+ * memory) and every buffer alive while the stream runs, and keeps each pushed frame (device,
+ * width x height, pitch = width) unchanged until it has been emitted. vs_stream_reset starts a new
+ * stream (progress fields, fit and trajectory state). The library allocates nothing and never
+ * synchronises the host; all work goes to `stream`. Emitted frames: *first_emitted (host) is the
+ * index of the first frame emitted by the call and *n_emitted (host) their count; frame e is
+ * complete in out + (e % out_slots) * width * height once the stream reaches the call's end.
+ * The smoother's lag is radius for VS_SMOOTH_CENTERED and 0 otherwise; radius <= 127.
+ * Errors: VS_ERR_INVALID for a null struct, frame or output, or a bad size; errors of the
+ * underlying calls are passed on (work enqueued before a failing launch stays enqueued). */
+#define VS_STREAM_MAX_FRAMES 160
+typedef struct {
+    /* geometry and parameters */
+    int32_t width, height;
+    vs_pyramid layout;
+    vs_detect_params detect;
+    vs_lk_params lk;
+    vs_fit_params fit;
+    vs_smooth_params smooth;
+    int32_t capacity;          /* point slots, >= detect.max_corners */
+    int32_t redetect_every;
+    int32_t min_valid;
+    int32_t border;
+    int32_t out_slots;         /* output ring length */
+    int32_t photo_steps;       /* photometric refinement steps per pair (0: off) */
+    vs_rect photo_omega;
+    /* device buffers */
+    uint8_t* pyr;              /* 2 * layout.bytes */
+    float* pts;                /* [2][capacity][2] */
+    uint8_t* alive;            /* [2][capacity] */
+    float* dst;                /* [capacity][2] */
+    uint8_t* status;           /* [capacity] */
+    float* fb_err;             /* [capacity] */
+    int32_t* n_valid;          /* [1] */
+    int32_t* count;            /* [1] */
+    void* detect_ws;           /* vs_detect_workspace(width, height, 1) bytes */
+    size_t detect_ws_bytes;
+    void* fit_ws;              /* vs_fit_workspace(1, capacity) bytes */
+    size_t fit_ws_bytes;
+    vs_fit_state* fit_state;
+    double* pair_params;       /* [1][4], the last pair's (a, b, tx, ty) */
+    double* affine6;           /* [1][6], the last pair's 2x3 model */
+    vs_fit_info* info;         /* [1] */
+    uint8_t* inliers;          /* [capacity] */
+    void* traj_state;          /* vs_traj_state_bytes() bytes */
+    double* mats;              /* [lag + 2][6] */
+    int32_t* n_emitted;        /* [1] */
+    int64_t* first_frame;      /* [1] */
+    double* photo_loss;        /* [1][2], when photo_steps > 0 */
+    int32_t* photo_accepted;   /* [1], when photo_steps > 0 */
+    void* photo_ws;            /* vs_photometric_workspace(1) bytes, when photo_steps > 0 */
+    size_t photo_ws_bytes;
+    uint8_t* out;              /* [out_slots][height][width] */
+    /* progress, maintained by the library */
+    int64_t next_frame;        /* index of the next pushed frame */
+    int64_t emitted;           /* frames emitted so far */
+    const uint8_t* frames[VS_STREAM_MAX_FRAMES];   /* frame j at [j % (lag + 2)] until emitted */
+} vs_stream;
+
+int vs_stream_reset(vs_stream* s, void* stream);
+int vs_stream_push(vs_stream* s, const uint8_t* frame, int64_t* first_emitted, int32_t* n_emitted, void* stream);
+int vs_stream_flush(vs_stream* s, int64_t* first_emitted, int32_t* n_emitted, void* stream);
+
+/* ---------------------------------------------------------------------------------------------
  * tuning -- launch-shape choices that change speed only, never a result bit (the choices only
  * reorder independent workgroups or group independent waves). Process-wide; a call reads the
  * values current when it is made, so settings may change between calls from any thread.

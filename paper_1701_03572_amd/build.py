@@ -21,7 +21,8 @@ BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("VSTAB_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["common.hip", "pyramid.hip", "corners.hip", "lk.hip", "fit.hip", "smooth.hip", "warp.hip", "photometric.hip"]
+SOURCES = ["common.hip", "pyramid.hip", "corners.hip", "lk.hip", "fit.hip", "smooth.hip", "warp.hip", "photometric.hip",
+           "stream.hip"]
 NO_CONTRACT = {"fit.hip", "smooth.hip", "corners.hip", "photometric.hip"}
 
 BASE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -191,9 +191,9 @@ class SequenceStabilizer:
 
 class Stabilizer:
     """Plain per-frame streaming path. ``push`` enqueues all work for one frame on the current
-    stream and returns the indices and output views of the frames it emits (the outputs are
-    complete once the stream reaches this point). Pushed frames must stay unchanged until they
-    are emitted; no frame is copied."""
+    stream through one native call (``vs_stream_push``) and returns the indices and output views of
+    the frames it emits (the outputs are complete once the stream reaches this point). Pushed
+    frames must stay unchanged until they are emitted; no frame is copied."""
 
     def __init__(self, width: int, height: int, P: StabParams, device="cuda", out_slots: int | None = None):
         self.W, self.H, self.P = width, height, P
@@ -226,69 +226,48 @@ class Stabilizer:
         self.first = torch.zeros(1, dtype=torch.int64, device=dev)
         self.out_slots = out_slots or (self.lag + 2)
         self.out = torch.empty((self.out_slots, height, width), dtype=torch.uint8, device=dev)
-        self._lkp = _lk_params(P)
-        self._dp = _detect_params(P, width, height)
-        self._fp = _fit_params(P, width, height)
-        self._sp = _smooth_params(P, width, height)
         self.refine_pair = _PhotoRefiner(P, width, height, 1, dev)
+        s = self._s = V.vs_stream()
+        s.width, s.height, s.layout = width, height, self.layout
+        s.detect, s.lk = _detect_params(P, width, height), _lk_params(P)
+        s.fit, s.smooth = _fit_params(P, width, height), _smooth_params(P, width, height)
+        s.capacity, s.redetect_every, s.min_valid, s.border = cap, P.redetect_every, P.min_valid, P.border
+        s.out_slots = self.out_slots
+        s.photo_steps, s.photo_omega = max(P.photometric_steps, 0), self.refine_pair.omega
+        for name in ("pyr", "pts", "alive", "dst", "status", "fb_err", "n_valid", "count", "fit_state", "pair_params",
+                     "affine6", "info", "inliers", "traj_state", "mats", "n_emitted", "out"):
+            setattr(s, name, getattr(self, name).data_ptr())
+        s.detect_ws, s.detect_ws_bytes = self.det_ws.data_ptr(), self.det_ws_bytes
+        s.fit_ws, s.fit_ws_bytes = self.fit_ws.data_ptr(), self.fit_ws_bytes
+        s.first_frame = self.first.data_ptr()
+        rp = self.refine_pair
+        s.photo_loss, s.photo_accepted = rp.loss.data_ptr(), rp.accepted.data_ptr()
+        s.photo_ws, s.photo_ws_bytes = rp.ws.data_ptr(), rp.ws_bytes
         self.reset()
 
     def reset(self):
+        V.vs_stream_reset(self._s)
         self.j = 0
-        self.emitted = 0
-        self.frames = {}
-        V.vs_fit_state_init(self.fit_state)
-        V.vs_traj_state_init(self.traj_state)
+        self.frames = {}           # frames pushed and not yet emitted (held alive for the device)
 
-    def _detect(self, frame: torch.Tensor, slot: int, gated: bool):
-        V.vs_detect_corners(frame, 0, self.W, self.H, self.W, 1, 1, self.n_valid if gated else None,
-                            self.P.min_valid, self._dp, self.cap, self.pts[slot], None, self.count,
-                            self.alive[slot], self.det_ws, self.det_ws_bytes)
-
-    def _emit(self, end: int) -> list:
-        out = []
-        for k, e in enumerate(range(self.emitted, end)):
-            dst = self.out[e % self.out_slots]
-            V.vs_warp_frame(self.frames[e], 0, self.W, self.H, self.W, self.mats[k], 6, dst, 0, self.W, 1,
-                            self.P.border)
-            out.append((e, dst))
-        for e in range(self.emitted, end):
-            if e < self.j - 1:
-                self.frames.pop(e, None)
-        self.emitted = end
+    def _collect(self, first: int, n: int) -> list:
+        out = [(e, self.out[e % self.out_slots]) for e in range(first, first + n)]
+        keep = min(first + n, self.j - 1)
+        for e in [e for e in self.frames if e < keep]:
+            del self.frames[e]
         return out
 
     def push(self, frame: torch.Tensor) -> list:
         assert frame.is_cuda and frame.dtype == torch.uint8 and frame.shape == (self.H, self.W)
         assert frame.is_contiguous()
-        j = self.j
-        L, bytes_ = self.layout, self.layout.bytes
-        cur, prev = j % 2, (j - 1) % 2
-        pyr_cur = self.pyr.data_ptr() + cur * bytes_
-        V.vs_build_pyramid(frame, 0, pyr_cur, 0, 1, L)
-        self.frames[j] = frame
-        if j == 0:
-            self._detect(frame, cur, gated=False)
-            V.vs_smooth_trajectory(None, 0, 0, self._sp, self.traj_state, self.mats, self.mats_cap, self.n_emitted,
-                                   self.first)
-        else:
-            V.vs_track_lk(self.frames[j - 1], self.pyr.data_ptr() + prev * bytes_, frame, pyr_cur, 0, 0, 1, 1, L,
-                          self.pts[prev], self.alive[prev], self.cap, self._lkp, self.dst, self.status, self.fb_err,
-                          self.n_valid, self.pts[cur], self.alive[cur])
-            V.vs_fit_motion(self.pts[prev], self.dst, self.status, self.cap, 1, self._fp, j - 1, self.fit_state,
-                            self.pair_params, self.affine6, self.info, self.inliers, self.fit_ws, self.fit_ws_bytes)
-            self.refine_pair(self.frames[j - 1], frame, 0, 1, self.pair_params, self.info)
-            self._detect(frame, cur, gated=(j % self.P.redetect_every != 0))
-            V.vs_smooth_trajectory(self.pair_params, 1, 0, self._sp, self.traj_state, self.mats, self.mats_cap,
-                                   self.n_emitted, self.first)
-        self.j = j + 1
-        end = self.j - self.lag if self.lag else self.j
-        return self._emit(max(end, self.emitted))
+        self.frames[self.j] = frame
+        first, n = V.vs_stream_push(self._s, frame)
+        self.j += 1
+        return self._collect(first, n)
 
     def flush(self) -> list:
         """End of stream: emit the frames still waiting for their smoothing window."""
-        V.vs_smooth_trajectory(None, 0, 1, self._sp, self.traj_state, self.mats, self.mats_cap, self.n_emitted,
-                               self.first)
-        out = self._emit(self.j)
+        first, n = V.vs_stream_flush(self._s)
+        out = [(e, self.out[e % self.out_slots]) for e in range(first, first + n)]
         self.frames.clear()
         return out

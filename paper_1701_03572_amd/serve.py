@@ -2,8 +2,10 @@
 
 Each admitted stream owns device-resident state (a streaming Stabilizer: pyramid ping-pong, point
 records, fit and trajectory state, output slots) plus a small device ring for its incoming frames;
-its frames arrive in host memory (pinned) and are copied to the ring on the serving stream, so the
-measured latency includes the host-to-device copy. Admission reserves each stream's device memory
+its frames arrive in host memory (pinned) and are copied to the ring on the stream's HIP stream, so
+the measured latency includes the host-to-device copy. Streams are spread round-robin over a small
+pool of HIP streams (default priority), so the mostly single-workgroup launches of different
+streams run concurrently instead of queueing behind each other. Admission reserves each stream's device memory
 against an HBM budget (measured when its state is built); a stream that does not fit waits in a FIFO
 queue until memory is released. Streams never share state, so a stream's outputs do not depend on
 what else is being served (tested: alone vs in a mix).
@@ -31,24 +33,33 @@ class _Stream:
     stab: Stabilizer
     ring: torch.Tensor
     reserved: int
+    queue: torch.cuda.Stream
     pushed: int = 0
 
 
 class StreamServer:
-    def __init__(self, hbm_budget: int, device="cuda"):
+    def __init__(self, hbm_budget: int, device="cuda", queues: int = 4):
         self.budget = int(hbm_budget)
         self.used = 0
         self.dev = torch.device(device)
         self.streams: dict = {}
         self.waiting: collections.deque = collections.deque()
         self.rejected = 0
+        self.queues = [torch.cuda.Stream(device=self.dev) for _ in range(max(1, queues))]
+        self._next_queue = 0
 
     def _build(self, sid, width, height, P: StabParams) -> _Stream:
+        q = self.queues[self._next_queue % len(self.queues)]
+        self._next_queue += 1
+        # the new state is initialised on the stream's own queue, after what the current stream
+        # has enqueued so far
+        q.wait_stream(torch.cuda.current_stream(self.dev))
         before = torch.cuda.memory_allocated(self.dev)
-        stab = Stabilizer(width, height, P, device=self.dev)
-        ring = torch.empty((stab.lag + 2, height, width), dtype=torch.uint8, device=self.dev)
+        with torch.cuda.stream(q):
+            stab = Stabilizer(width, height, P, device=self.dev)
+            ring = torch.empty((stab.lag + 2, height, width), dtype=torch.uint8, device=self.dev)
         reserved = torch.cuda.memory_allocated(self.dev) - before
-        return _Stream(sid, stab, ring, reserved)
+        return _Stream(sid, stab, ring, reserved, q)
 
     def open(self, sid, width: int, height: int, P: StabParams) -> bool:
         """Admit a stream if its state fits the budget; otherwise queue it. Returns True if admitted."""
@@ -65,15 +76,17 @@ class StreamServer:
         """Copy one arriving frame (host, uint8 [H, W]) to the device and enqueue its processing.
         Returns (frame index, output view) for the frames this push emits."""
         st = self.streams[sid]
-        slot = st.ring[st.pushed % st.ring.shape[0]]
-        slot.copy_(frame_host, non_blocking=True)
-        st.pushed += 1
-        return st.stab.push(slot)
+        with torch.cuda.stream(st.queue):
+            slot = st.ring[st.pushed % st.ring.shape[0]]
+            slot.copy_(frame_host, non_blocking=True)
+            st.pushed += 1
+            return st.stab.push(slot)
 
     def close(self, sid) -> list:
         """End a stream: emit what is left, release its memory and admit queued streams that now fit."""
         st = self.streams.pop(sid)
-        out = st.stab.flush()
+        with torch.cuda.stream(st.queue):
+            out = st.stab.flush()
         self.used -= st.reserved
         admitted = []
         while self.waiting:
@@ -154,14 +167,17 @@ def simulate(server: StreamServer, workload: list, pools: list, paced: bool) -> 
             continue                                  # still queued: its frames are dropped until admitted
         pool = pools[s.clip]
         frame = pool[(s.offset + j) % pool.shape[0]]
+        queue = server.streams[s.sid].queue
         emitted = server.submit(s.sid, frame)
         if kind == 1:
             emitted += server.close(s.sid)
         if emitted:
             ev = torch.cuda.Event(enable_timing=True)
-            ev.record()
+            ev.record(queue)                          # on the stream's own queue, after its warps
             done.append((t, ev, len(emitted)))
             n_out += len(emitted)
+    for q in server.queues:
+        torch.cuda.current_stream().wait_stream(q)
     end = torch.cuda.Event(enable_timing=True)
     end.record()
     torch.cuda.synchronize()

@@ -74,6 +74,25 @@ class vs_smooth_params(C.Structure):
                 ("cx", C.c_double), ("cy", C.c_double)]
 
 
+VS_STREAM_MAX_FRAMES = 160
+
+
+class vs_stream(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("layout", vs_pyramid), ("detect", vs_detect_params),
+                ("lk", vs_lk_params), ("fit", vs_fit_params), ("smooth", vs_smooth_params), ("capacity", C.c_int32),
+                ("redetect_every", C.c_int32), ("min_valid", C.c_int32), ("border", C.c_int32),
+                ("out_slots", C.c_int32), ("photo_steps", C.c_int32), ("photo_omega", vs_rect),
+                ("pyr", C.c_void_p), ("pts", C.c_void_p), ("alive", C.c_void_p), ("dst", C.c_void_p),
+                ("status", C.c_void_p), ("fb_err", C.c_void_p), ("n_valid", C.c_void_p), ("count", C.c_void_p),
+                ("detect_ws", C.c_void_p), ("detect_ws_bytes", C.c_size_t), ("fit_ws", C.c_void_p),
+                ("fit_ws_bytes", C.c_size_t), ("fit_state", C.c_void_p), ("pair_params", C.c_void_p),
+                ("affine6", C.c_void_p), ("info", C.c_void_p), ("inliers", C.c_void_p), ("traj_state", C.c_void_p),
+                ("mats", C.c_void_p), ("n_emitted", C.c_void_p), ("first_frame", C.c_void_p),
+                ("photo_loss", C.c_void_p), ("photo_accepted", C.c_void_p), ("photo_ws", C.c_void_p),
+                ("photo_ws_bytes", C.c_size_t), ("out", C.c_void_p), ("next_frame", C.c_int64),
+                ("emitted", C.c_int64), ("frames", C.c_void_p * VS_STREAM_MAX_FRAMES)]
+
+
 FIT_INFO_BYTES = C.sizeof(vs_fit_info)
 FIT_INFO_SKIPPED_OFFSET = vs_fit_info.skipped.offset
 FIT_STATE_BYTES = C.sizeof(vs_fit_state)
@@ -112,6 +131,9 @@ _SIGS = {
     "vs_photometric_refine": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P,
                                         C.c_int64, C.c_int32, _P, C.c_int64, C.c_double, C.c_double, C.c_double,
                                         C.POINTER(vs_rect), C.c_int32, _P, _P, _P, C.c_size_t, _P]),
+    "vs_stream_reset": (C.c_int, [C.POINTER(vs_stream), _P]),
+    "vs_stream_push": (C.c_int, [C.POINTER(vs_stream), _P, C.POINTER(C.c_int64), C.POINTER(C.c_int32), _P]),
+    "vs_stream_flush": (C.c_int, [C.POINTER(vs_stream), C.POINTER(C.c_int64), C.POINTER(C.c_int32), _P]),
     "vs_set_tuning": (C.c_int, [C.POINTER(vs_tuning)]),
     "vs_get_tuning": (C.c_int, [C.POINTER(vs_tuning)]),
     "vs_last_error": (C.c_char_p, []),
@@ -171,6 +193,24 @@ def _check(rc: int, what: str):
 
 def vs_version() -> int:
     return load().vs_version()
+
+
+def vs_stream_reset(s: vs_stream, stream=None):
+    _check(load().vs_stream_reset(C.byref(s), _stream(stream)), "vs_stream_reset")
+
+
+def vs_stream_push(s: vs_stream, frame, stream=None) -> tuple[int, int]:
+    """Returns (index of the first frame emitted by this push, number emitted)."""
+    first, n = C.c_int64(0), C.c_int32(0)
+    _check(load().vs_stream_push(C.byref(s), _ptr(frame), C.byref(first), C.byref(n), _stream(stream)),
+           "vs_stream_push")
+    return first.value, n.value
+
+
+def vs_stream_flush(s: vs_stream, stream=None) -> tuple[int, int]:
+    first, n = C.c_int64(0), C.c_int32(0)
+    _check(load().vs_stream_flush(C.byref(s), C.byref(first), C.byref(n), _stream(stream)), "vs_stream_flush")
+    return first.value, n.value
 
 
 def vs_set_tuning(t: "vs_tuning | None"):

@@ -25,19 +25,23 @@ def host_clip(name, n, seed):
 
 def serve_stream(server, sid, clip, P, others=()):
     """Push ``clip`` through stream ``sid``, interleaving one frame of every other (sid, clip, P)
-    after each frame; returns host copies of sid's outputs in order."""
+    after each frame; returns host copies of sid's outputs in order. Outputs are copied on the
+    stream's own queue (ordered after the warp that wrote them, before a later push reuses the slot)."""
     h, w = clip.shape[1:]
     assert server.open(sid, w, h, P)
     for osid, oclip, oP in others:
         assert server.open(osid, oclip.shape[2], oclip.shape[1], oP)
+    q = server.streams[sid].queue
     outs = {}
     for j in range(clip.shape[0]):
         for e, t in server.submit(sid, clip[j]):
-            outs[e] = t.clone()
+            with torch.cuda.stream(q):
+                outs[e] = t.clone()
         for osid, oclip, oP in others:
             server.submit(osid, oclip[j % oclip.shape[0]])
     for e, t in server.close(sid):
-        outs[e] = t.clone()
+        with torch.cuda.stream(q):
+            outs[e] = t.clone()
     for osid, _, _ in others:
         server.close(osid)
     torch.cuda.synchronize()
@@ -51,8 +55,8 @@ def test_stream_alone_equals_stream_in_a_mix():
     PA = StabParams(levels=3, max_corners=200, smooth_mode=SMOOTH_CAUSAL, stream_id=7)
     PB = StabParams(levels=4, max_corners=500, smooth_mode=SMOOTH_CAUSAL, stream_id=8)
     PC = StabParams(levels=3, max_corners=100, smooth_mode=SMOOTH_CAUSAL, stream_id=9)
-    alone = serve_stream(StreamServer(4 * GB), 1, a, PA)
-    mixed = serve_stream(StreamServer(4 * GB), 1, a, PA, others=[(2, b, PB), (3, c, PC)])
+    alone = serve_stream(StreamServer(4 * GB, queues=1), 1, a, PA)
+    mixed = serve_stream(StreamServer(4 * GB, queues=3), 1, a, PA, others=[(2, b, PB), (3, c, PC)])
     assert len(alone) == len(mixed) == 16
     for x, y in zip(alone, mixed):
         np.testing.assert_array_equal(x, y)
