@@ -1,11 +1,14 @@
 // fit_similarity / fit_motion: seeded robust rigid / similarity / affine fit, hybrid dwell switch
 // and skip rule.
 //
-// Kernel 1 (fit_pair): one 256-thread workgroup per pair, with LDS sized to the capacity (19 bytes
-// per point slot) and registers capped for three workgroups per CU, so pairs overlap each other's
-// LDS and FP64 latencies. The valid slots are compacted in slot order into LDS (raw FP32
-// coordinates, centred exactly in binary64 when read), then each requested model is fitted:
-// the 4 waves share the RANSAC hypotheses (wave w takes h = w, w + 4, ...), score them by
+// Kernel 1a (fit_hyp): the RANSAC hypotheses of each pair, spread over up to 8 workgroups per pair
+// when there are few pairs; each records its best. Kernel 1b (fit_pair): one 256-thread workgroup
+// per pair, with LDS sized to the capacity (19 bytes per point slot) and registers capped for three
+// workgroups per CU, so pairs overlap each other's LDS and FP64 latencies. The valid slots are
+// compacted in slot order into LDS (raw FP32 coordinates, centred exactly in binary64 when read),
+// then each requested model is fitted:
+// the hypothesis workgroups' waves share the RANSAC hypotheses (wave w of workgroup s of S takes
+// h = s + S (w + 4k)), score them by
 // counting residuals <= threshold with a wave reduction, and the best (most inliers, then
 // smallest h) is refitted by least squares in binary64: the similarity through its 4x4 normal
 // equations (Gaussian elimination with partial pivoting), the rigid model through the centred
@@ -19,6 +22,7 @@
 // Kernel 2 (fit_resolve): the dwell-block state machine over the pairs of the call, evaluated
 // block-parallel. Kernel 3 (fit_emit): one workgroup per pair writes the chosen model's parameters,
 // info and inlier flags.
+#include <algorithm>
 #include <cmath>
 
 #include "vs_common.hpp"
@@ -45,8 +49,19 @@ struct PairRec {
 };
 static_assert(sizeof(PairRec) <= 256, "pair record header");
 
+// best hypothesis of one hypothesis workgroup for one model (score -1: none)
+struct HypRec {
+    int32_t score;
+    int32_t h;
+    double p[6];
+    double pad;
+};
+static_assert(sizeof(HypRec) == 64, "hypothesis record");
+constexpr int MAX_SPLIT = 8;    // hypothesis workgroups per pair at most
+
 __host__ __device__ inline int64_t cap_aligned(int cap) { return ((int64_t)cap + 255) & ~(int64_t)255; }
-__host__ __device__ inline int64_t rec_bytes(int cap) { return 256 + N_SLOTS * cap_aligned(cap); }
+__host__ __device__ inline int64_t hyp_offset(int cap) { return 256 + N_SLOTS * cap_aligned(cap); }
+__host__ __device__ inline int64_t rec_bytes(int cap) { return hyp_offset(cap) + MAX_SPLIT * N_SLOTS * sizeof(HypRec); }
 
 __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t ctr)
 {
@@ -286,33 +301,15 @@ __device__ __forceinline__ void ls_affine(const float* xs, const float* ys, cons
     }
 }
 
-__global__ __launch_bounds__(NT, 3) void fit_pair_kernel(const float* __restrict__ src, const float* __restrict__ dst,
-                                                      const uint8_t* __restrict__ valid, int capacity, FitArgs a,
-                                                      int64_t pair_index0, uint8_t* ws)
+// Stable compaction of one pair's valid slots into LDS, in slot order: thread t owns a run of
+// consecutive slots; an exclusive prefix of the per-thread counts (wave scan, then the wave totals in
+// order) places them. Raw FP32 coordinates are stored (centred in binary64 at use, so every side sees
+// identical values). Returns the number of valid slots (every thread).
+__device__ __forceinline__ int compact_valid(const float* __restrict__ src, const float* __restrict__ dst,
+                                             const uint8_t* __restrict__ valid, int64_t base, int capacity, float* xs,
+                                             float* ys, float* xd, float* yd, uint16_t* slot_of, int32_t* red4)
 {
-    extern __shared__ __attribute__((aligned(16))) unsigned char pair_lds[];
-    const int capA = lds_cap(capacity);
-    float* xs = reinterpret_cast<float*>(pair_lds);
-    float* ys = xs + capA;
-    float* xd = ys + capA;
-    float* yd = xd + capA;
-    uint16_t* slot_of = reinterpret_cast<uint16_t*>(yd + capA);
-    uint8_t* inl = reinterpret_cast<uint8_t*>(slot_of + capA);
-    __shared__ double red[8 * 4];
-    __shared__ int32_t red4[4];
-    __shared__ int32_t w_score[4], w_h[4];
-    __shared__ double w_model[4][6];
-    __shared__ double s_out[6], s_tmp[4];
-    __shared__ int s_n, s_best_h, s_ninl, s_flag;
-
-    const int item = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int64_t pair = pair_index0 + item;
-    PairRec* rec = reinterpret_cast<PairRec*>(ws + item * rec_bytes(capacity));
-    uint8_t* masks = ws + item * rec_bytes(capacity) + 256;
-    const int64_t base = (int64_t)item * capacity;
-
-    // ---- stable compaction of the valid slots: thread t owns a run of consecutive slots; an
-    // exclusive prefix of the per-thread counts (wave scan, then the wave totals in order) places them
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int chunk = (capacity + NT - 1) / NT;
     const int c0 = t * chunk, c1 = min(capacity, c0 + chunk);
     int cnt = 0;
@@ -327,23 +324,182 @@ __global__ __launch_bounds__(NT, 3) void fit_pair_kernel(const float* __restrict
     __syncthreads();
     int wbase = 0;
     for (int w = 0; w < wv; ++w) wbase += red4[w];
-    if (t == 0) s_n = (red4[0] + red4[1]) + (red4[2] + red4[3]);
+    const int n = (red4[0] + red4[1]) + (red4[2] + red4[3]);
+    int o = wbase + incl - cnt;
+    for (int k = c0; k < c1; ++k) {
+        if (!valid[base + k]) continue;
+        xs[o] = src[2 * (base + k)];
+        ys[o] = src[2 * (base + k) + 1];
+        xd[o] = dst[2 * (base + k)];
+        yd[o] = dst[2 * (base + k) + 1];
+        if (slot_of) slot_of[o] = (uint16_t)k;
+        ++o;
+    }
     __syncthreads();
-    {
-        int o = wbase + incl - cnt;
-        for (int k = c0; k < c1; ++k) {
-            if (!valid[base + k]) continue;
-            xs[o] = src[2 * (base + k)];          // raw FP32 pixel coordinates; centred in binary64
-            ys[o] = src[2 * (base + k) + 1];      // at use, so every side sees identical values
-            xd[o] = dst[2 * (base + k)];
-            yd[o] = dst[2 * (base + k) + 1];
-            slot_of[o] = (uint16_t)k;
-            ++o;
+    return n;
+}
+
+// The calling wave's best hypothesis of `model` among h = h0, h0 + hs, ... < iters: most inliers,
+// the first such h on ties (best = -1, best_h = -1 when none). Every lane returns the same values.
+__device__ void ransac_wave(int model, const float* xs, const float* ys, const float* xd, const float* yd, int n,
+                            const FitArgs& a, int64_t pair, int h0, int hs, int& best, int& best_h, double (&bm)[6])
+{
+    const int lane = threadIdx.x & 63;
+    const bool affine = model == VS_AFFINE;
+    best = -1;
+    best_h = -1;
+    for (int k = 0; k < 6; ++k) bm[k] = (k == 0 || k == 4) ? 1.0 : 0.0;
+    for (int h = h0; h < a.iters; h += hs) {
+        double c[6];
+        if (affine) {
+            const int i1 = (int)(draw3(a.seed, a.stream_id, pair, h, 0) % (uint64_t)n);
+            int i2 = (int)(draw3(a.seed, a.stream_id, pair, h, 1) % (uint64_t)n);
+            int i3 = (int)(draw3(a.seed, a.stream_id, pair, h, 2) % (uint64_t)n);
+            if (i2 == i1) i2 = (i2 + 1) % n;
+            while (i3 == i1 || i3 == i2) i3 = (i3 + 1) % n;   // n >= 3: at most two steps
+            const double x1 = xs[i1] - a.cx, y1 = ys[i1] - a.cy, u1 = xd[i1] - a.cx, w1 = yd[i1] - a.cy;
+            const double ex = (xs[i2] - a.cx) - x1, ey = (ys[i2] - a.cy) - y1;
+            const double fx = (xs[i3] - a.cx) - x1, fy = (ys[i3] - a.cy) - y1;
+            const double det = ex * fy - fx * ey;
+            if (!(fabs(det) >= 1.0)) continue;          // near-collinear sample: no hypothesis
+            const double gu = (xd[i2] - a.cx) - u1, gv = (yd[i2] - a.cy) - w1;
+            const double hu = (xd[i3] - a.cx) - u1, hv = (yd[i3] - a.cy) - w1;
+            c[0] = (gu * fy - hu * ey) / det;
+            c[1] = (hu * ex - gu * fx) / det;
+            c[3] = (gv * fy - hv * ey) / det;
+            c[4] = (hv * ex - gv * fx) / det;
+            c[2] = u1 - (c[0] * x1 + c[1] * y1);
+            c[5] = w1 - (c[3] * x1 + c[4] * y1);
+        } else {
+            const int i1 = (int)(draw(a.seed, a.stream_id, pair, h, 0) % (uint64_t)n);
+            int i2 = (int)(draw(a.seed, a.stream_id, pair, h, 1) % (uint64_t)n);
+            if (i2 == i1) i2 = (i2 + 1) % n;
+            const double x1 = xs[i1] - a.cx, y1 = ys[i1] - a.cy, x2 = xs[i2] - a.cx, y2 = ys[i2] - a.cy;
+            const double u1 = xd[i1] - a.cx, w1 = yd[i1] - a.cy, u2 = xd[i2] - a.cx, w2 = yd[i2] - a.cy;
+            const double dzx = x2 - x1, dzy = y2 - y1;
+            const double den = dzx * dzx + dzy * dzy;
+            if (den < 1.0) continue;
+            const double wx = u2 - u1, wy = w2 - w1;
+            double ar = (wx * dzx + wy * dzy) / den;
+            double ai = (wy * dzx - wx * dzy) / den;
+            double br, bi;
+            if (model == VS_RIGID) {
+                const double mag = sqrt(ar * ar + ai * ai);
+                if (!(mag > 0.0)) continue;
+                ar = ar / mag;
+                ai = ai / mag;
+                const double sxs = x1 + x2, sys = y1 + y2, sxd = u1 + u2, syd = w1 + w2;
+                br = (sxd - (ar * sxs - ai * sys)) * 0.5;
+                bi = (syd - (ai * sxs + ar * sys)) * 0.5;
+            } else {
+                br = u1 - (ar * x1 - ai * y1);
+                bi = w1 - (ai * x1 + ar * y1);
+            }
+            c[0] = ar; c[1] = ai; c[2] = br; c[3] = bi; c[4] = 0.0; c[5] = 0.0;
+        }
+        int sc = 0;
+        if (affine) {
+            for (int i = lane; i < n; i += 64)
+                sc += aff_resid2(c, xs[i] - a.cx, ys[i] - a.cy, xd[i] - a.cx, yd[i] - a.cy) <= a.tau2;
+        } else {
+            for (int i = lane; i < n; i += 64)
+                sc += resid2(c[0], c[1], c[2], c[3], xs[i] - a.cx, ys[i] - a.cy, xd[i] - a.cx, yd[i] - a.cy) <= a.tau2;
+        }
+        sc = vs::wave_sum_i(sc);
+        if (sc > best) {
+            best = sc;
+            best_h = h;
+            for (int k = 0; k < 6; ++k) bm[k] = c[k];
         }
     }
+}
+
+__device__ __forceinline__ int model_of(int mode, int mi)
+{
+    const bool hybrid = mode == VS_HYBRID || mode == VS_HYBRID3;
+    return !hybrid ? mode : mi == 0 ? VS_RIGID : mi == 1 ? VS_SIMILARITY : VS_AFFINE;
+}
+
+__device__ __forceinline__ int models_in(int mode) { return mode == VS_HYBRID3 ? 3 : mode == VS_HYBRID ? 2 : 1; }
+
+// Kernel 1a (fit_hyp): workgroup (pair, s) of `split` per pair scores the hypotheses h = s, s + split,
+// ... of every requested model (wave w takes h = s + split (w + 4k)) and records its best in the
+// pair's workspace record. Splitting a pair's hypotheses over several workgroups shortens the
+// dependent FP64 chains when there are few pairs.
+__global__ __launch_bounds__(NT, 3) void fit_hyp_kernel(const float* __restrict__ src, const float* __restrict__ dst,
+                                                     const uint8_t* __restrict__ valid, int capacity, FitArgs a,
+                                                     int64_t pair_index0, int split, uint8_t* ws)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char pair_lds[];
+    const int capA = lds_cap(capacity);
+    float* xs = reinterpret_cast<float*>(pair_lds);
+    float* ys = xs + capA;
+    float* xd = ys + capA;
+    float* yd = xd + capA;
+    __shared__ int32_t red4[4];
+    __shared__ int32_t w_score[4], w_h[4];
+    __shared__ double w_model[4][6];
+    const int item = blockIdx.x / split, sp = blockIdx.x - item * split;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t pair = pair_index0 + item;
+    HypRec* hyp = reinterpret_cast<HypRec*>(ws + item * rec_bytes(capacity) + hyp_offset(capacity));
+    const int n = compact_valid(src, dst, valid, (int64_t)item * capacity, capacity, xs, ys, xd, yd, nullptr, red4);
+    const int nm = models_in(a.model);
+    for (int mi = 0; mi < nm; ++mi) {
+        const int model = model_of(a.model, mi);
+        int best = -1, best_h = -1;
+        double bm[6];
+        const bool run = !(n < a.min_valid || n < 2) && a.iters > 0 && (model != VS_AFFINE || n >= 3);
+        if (run) ransac_wave(model, xs, ys, xd, yd, n, a, pair, sp + split * wv, 4 * split, best, best_h, bm);
+        if (lane == 0) {
+            w_score[wv] = best;
+            w_h[wv] = best_h;
+            for (int k = 0; k < 6; ++k) w_model[wv][k] = run ? bm[k] : 0.0;
+        }
+        __syncthreads();
+        if (t == 0) {
+            int bw = -1;
+            for (int w = 0; w < 4; ++w) {
+                if (w_h[w] < 0) continue;
+                if (bw < 0 || w_score[w] > w_score[bw] || (w_score[w] == w_score[bw] && w_h[w] < w_h[bw])) bw = w;
+            }
+            HypRec& r = hyp[sp * N_SLOTS + slot_of_model(model)];
+            r.score = bw < 0 ? -1 : w_score[bw];
+            r.h = bw < 0 ? -1 : w_h[bw];
+            for (int k = 0; k < 6; ++k) r.p[k] = bw < 0 ? 0.0 : w_model[bw][k];
+            r.pad = 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(NT, 3) void fit_pair_kernel(const float* __restrict__ src, const float* __restrict__ dst,
+                                                      const uint8_t* __restrict__ valid, int capacity, FitArgs a,
+                                                      int64_t pair_index0, int split, uint8_t* ws)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char pair_lds[];
+    const int capA = lds_cap(capacity);
+    float* xs = reinterpret_cast<float*>(pair_lds);
+    float* ys = xs + capA;
+    float* xd = ys + capA;
+    float* yd = xd + capA;
+    uint16_t* slot_of = reinterpret_cast<uint16_t*>(yd + capA);
+    uint8_t* inl = reinterpret_cast<uint8_t*>(slot_of + capA);
+    __shared__ double red[8 * 4];
+    __shared__ int32_t red4[4];
+    __shared__ double w_model[1][6];
+    __shared__ double s_out[6], s_tmp[4];
+    __shared__ int s_best_h, s_ninl, s_flag;
+
+    const int item = blockIdx.x, t = threadIdx.x;
+    PairRec* rec = reinterpret_cast<PairRec*>(ws + item * rec_bytes(capacity));
+    uint8_t* masks = ws + item * rec_bytes(capacity) + 256;
+    const int64_t base = (int64_t)item * capacity;
+
+    const int n = compact_valid(src, dst, valid, base, capacity, xs, ys, xd, yd, slot_of, red4);
+    const HypRec* hyp = reinterpret_cast<const HypRec*>(ws + item * rec_bytes(capacity) + hyp_offset(capacity));
     for (int k = t; k < N_SLOTS * cap_aligned(capacity); k += NT) masks[k] = 0;
     __syncthreads();
-    const int n = s_n;
     if (t == 0) {
         rec->n_valid = n;
         rec->skipped = (n < a.min_valid || n < 2) ? 1 : 0;
@@ -358,85 +514,20 @@ __global__ __launch_bounds__(NT, 3) void fit_pair_kernel(const float* __restrict
         const bool affine = model == VS_AFFINE;
         bool have = false;
         if (a.iters > 0 && (!affine || n >= 3)) {
-            int best = -1, best_h = -1;
-            double bm[6] = {1, 0, 0, 0, 1, 0};
-            for (int h = wv; h < a.iters; h += 4) {
-                double c[6];
-                if (affine) {
-                    const int i1 = (int)(draw3(a.seed, a.stream_id, pair, h, 0) % (uint64_t)n);
-                    int i2 = (int)(draw3(a.seed, a.stream_id, pair, h, 1) % (uint64_t)n);
-                    int i3 = (int)(draw3(a.seed, a.stream_id, pair, h, 2) % (uint64_t)n);
-                    if (i2 == i1) i2 = (i2 + 1) % n;
-                    while (i3 == i1 || i3 == i2) i3 = (i3 + 1) % n;   // n >= 3: at most two steps
-                    const double x1 = xs[i1] - a.cx, y1 = ys[i1] - a.cy, u1 = xd[i1] - a.cx, w1 = yd[i1] - a.cy;
-                    const double ex = (xs[i2] - a.cx) - x1, ey = (ys[i2] - a.cy) - y1;
-                    const double fx = (xs[i3] - a.cx) - x1, fy = (ys[i3] - a.cy) - y1;
-                    const double det = ex * fy - fx * ey;
-                    if (!(fabs(det) >= 1.0)) continue;          // near-collinear sample: no hypothesis
-                    const double gu = (xd[i2] - a.cx) - u1, gv = (yd[i2] - a.cy) - w1;
-                    const double hu = (xd[i3] - a.cx) - u1, hv = (yd[i3] - a.cy) - w1;
-                    c[0] = (gu * fy - hu * ey) / det;
-                    c[1] = (hu * ex - gu * fx) / det;
-                    c[3] = (gv * fy - hv * ey) / det;
-                    c[4] = (hv * ex - gv * fx) / det;
-                    c[2] = u1 - (c[0] * x1 + c[1] * y1);
-                    c[5] = w1 - (c[3] * x1 + c[4] * y1);
-                } else {
-                    const int i1 = (int)(draw(a.seed, a.stream_id, pair, h, 0) % (uint64_t)n);
-                    int i2 = (int)(draw(a.seed, a.stream_id, pair, h, 1) % (uint64_t)n);
-                    if (i2 == i1) i2 = (i2 + 1) % n;
-                    const double x1 = xs[i1] - a.cx, y1 = ys[i1] - a.cy, x2 = xs[i2] - a.cx, y2 = ys[i2] - a.cy;
-                    const double u1 = xd[i1] - a.cx, w1 = yd[i1] - a.cy, u2 = xd[i2] - a.cx, w2 = yd[i2] - a.cy;
-                    const double dzx = x2 - x1, dzy = y2 - y1;
-                    const double den = dzx * dzx + dzy * dzy;
-                    if (den < 1.0) continue;
-                    const double wx = u2 - u1, wy = w2 - w1;
-                    double ar = (wx * dzx + wy * dzy) / den;
-                    double ai = (wy * dzx - wx * dzy) / den;
-                    double br, bi;
-                    if (model == VS_RIGID) {
-                        const double mag = sqrt(ar * ar + ai * ai);
-                        if (!(mag > 0.0)) continue;
-                        ar = ar / mag;
-                        ai = ai / mag;
-                        const double sxs = x1 + x2, sys = y1 + y2, sxd = u1 + u2, syd = w1 + w2;
-                        br = (sxd - (ar * sxs - ai * sys)) * 0.5;
-                        bi = (syd - (ai * sxs + ar * sys)) * 0.5;
-                    } else {
-                        br = u1 - (ar * x1 - ai * y1);
-                        bi = w1 - (ai * x1 + ar * y1);
-                    }
-                    c[0] = ar; c[1] = ai; c[2] = br; c[3] = bi; c[4] = 0.0; c[5] = 0.0;
-                }
-                int sc = 0;
-                if (affine) {
-                    for (int i = lane; i < n; i += 64)
-                        sc += aff_resid2(c, xs[i] - a.cx, ys[i] - a.cy, xd[i] - a.cx, yd[i] - a.cy) <= a.tau2;
-                } else {
-                    for (int i = lane; i < n; i += 64)
-                        sc += resid2(c[0], c[1], c[2], c[3], xs[i] - a.cx, ys[i] - a.cy, xd[i] - a.cx, yd[i] - a.cy) <=
-                              a.tau2;
-                }
-                sc = vs::wave_sum_i(sc);
-                if (sc > best) {
-                    best = sc;
-                    best_h = h;
-                    for (int k = 0; k < 6; ++k) bm[k] = c[k];
-                }
-            }
-            if (lane == 0) {
-                w_score[wv] = best;
-                w_h[wv] = best_h;
-                for (int k = 0; k < 6; ++k) w_model[wv][k] = bm[k];
-            }
-            __syncthreads();
+            // the best of the hypothesis workgroups' bests: most inliers, then the smallest h
             if (t == 0) {
-                int bw = -1;
-                for (int w = 0; w < 4; ++w) {
-                    if (w_h[w] < 0) continue;
-                    if (bw < 0 || w_score[w] > w_score[bw] || (w_score[w] == w_score[bw] && w_h[w] < w_h[bw])) bw = w;
+                int bs = -1;
+                for (int q = 0; q < split; ++q) {
+                    const HypRec& r = hyp[q * N_SLOTS + slot_of_model(model)];
+                    if (r.h < 0) continue;
+                    if (bs < 0 || r.score > hyp[bs * N_SLOTS + slot_of_model(model)].score ||
+                        (r.score == hyp[bs * N_SLOTS + slot_of_model(model)].score &&
+                         r.h < hyp[bs * N_SLOTS + slot_of_model(model)].h))
+                        bs = q;
                 }
-                s_best_h = bw;
+                if (bs >= 0)
+                    for (int k = 0; k < 6; ++k) w_model[0][k] = hyp[bs * N_SLOTS + slot_of_model(model)].p[k];
+                s_best_h = bs < 0 ? -1 : 0;
             }
             __syncthreads();
             const int bw = s_best_h;
@@ -696,11 +787,19 @@ extern "C" int vs_fit_motion(const float* src, const float* dst, const uint8_t* 
     const size_t lds = pair_lds_bytes(capacity);
     if (lds > 65536) {
         // capacities above ~3400 points need more than the default 64 KiB of dynamic LDS
-        const hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(&fit_pair_kernel),
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(&fit_pair_kernel),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (he == hipSuccess)
+            he = hipFuncSetAttribute(reinterpret_cast<const void*>(&fit_hyp_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (he != hipSuccess) return vs::set_error(VS_ERR_HIP, "vs_fit_motion: %s", hipGetErrorString(he));
     }
-    fit_pair_kernel<<<n, NT, lds, s>>>(src, dst, valid, capacity, a, pair_index0, w8);
+    // few pairs: spread each pair's hypotheses over up to MAX_SPLIT workgroups
+    const int split = a.iters > 0 ? std::min(std::max((512 + n - 1) / n, 1), MAX_SPLIT) : 1;
+    fit_hyp_kernel<<<n * split, NT, lds, s>>>(src, dst, valid, capacity, a, pair_index0, split, w8);
+    int e0 = vs::check_launch("vs_fit_motion(hypotheses)");
+    if (e0) return e0;
+    fit_pair_kernel<<<n, NT, lds, s>>>(src, dst, valid, capacity, a, pair_index0, split, w8);
     int e = vs::check_launch("vs_fit_motion(pairs)");
     if (e) return e;
     fit_resolve_kernel<<<1, NT, 0, s>>>(n, capacity, a, pair_index0, state, w8);
