@@ -453,10 +453,10 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
     __shared__ int32_t acc_x[VS_MAX_CORNERS];
     __shared__ int32_t acc_y[VS_MAX_CORNERS];
     __shared__ uint32_t s_conf[64];
+    __shared__ __attribute__((aligned(16))) uint8_t s_mbits[64 * 16];
     __shared__ int32_t s_cx[64], s_cy[64];
     __shared__ int s_nacc, s_bcount, s_digit, s_done;
     __shared__ uint32_t s_need, s_above, s_sel_in_bin;
-    __shared__ uint32_t s_red[32];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     CandHeader* hd = hdr_of(ws, item_bytes, item);
@@ -472,44 +472,45 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
     if (tid == 0) { s_nacc = 0; s_done = !(lmax > 0.0) || K <= 0; }
     __syncthreads();
 
+    // keys requested per batch: the greedy typically consumes about 1.2 K candidates, so 1.5 K keeps
+    // one batch (and a 2048-element sort for K up to ~1300) in the common case
+    const uint32_t batch = (uint32_t)min(BATCH, max(512, K + K / 2));
     const uint64_t span = lmax_bits >= base ? lmax_bits - base : 0;
     const int nbits = (span ? 64 - __clzll((long long)span) : 0) + 32;
     bool unbounded = true;
     u128 U = 0;                    // exclusive upper bound on composite keys still to process
 
     while (!s_done) {
-        // ---- 1) count the eligible keys below U
-        uint32_t cnt = 0;
-        for_each_key(keys, idx, N, tid, [&](uint64_t kb, uint32_t ix) {
-            if (kb >= base && (unbounded || comp(kb, ix, base) < U)) ++cnt;
-        });
-        cnt = (uint32_t)vs::wave_sum_i((int)cnt);
-        if (lane == 0) s_red[wv] = cnt;
-        __syncthreads();
-        uint32_t n_elig = 0;
-        for (int i = 0; i < 16; ++i) n_elig += s_red[i];
-        __syncthreads();
-        if (n_elig == 0) break;
-
-        // ---- 2) radix select the cut T: all eligible keys in [T, U) form the batch
+        // ---- 1) radix select the cut T: all eligible keys in [T, U) form the batch. The first digit
+        // pass also counts the eligible keys: none left ends the selection, and when they all fit the
+        // batch is all of them (T = 0).
         u128 T = 0;
-        if (n_elig > CAP) {
+        bool none_left = false;
+        {
             int shift = nbits;
             u128 prefix = 0;
-            if (tid == 0) { s_need = BATCH; s_above = 0; }
+            if (tid == 0) { s_need = batch; s_above = 0; }
             __syncthreads();
-            while (true) {
+            for (int pass = 0;; ++pass) {
                 const int db = shift < DIGIT ? shift : DIGIT;
                 const int pshift = shift;             // prefix covers bits >= pshift
                 shift -= db;
                 for (int b = tid; b < NBIN; b += 1024) hist[b] = 0;
                 __syncthreads();
                 for_each_key(keys, idx, N, tid, [&](uint64_t kb, uint32_t ix) {
-                    if (kb < base) return;
-                    const u128 v = comp(kb, ix, base);
-                    if (!unbounded && v >= U) return;
-                    if (pshift < 128 && (v >> pshift) != prefix) return;
-                    atomicAdd(&hist[(uint32_t)(v >> shift) & ((1u << db) - 1u)], 1u);
+                    bool in = kb >= base;
+                    u128 v = 0;
+                    if (in) {
+                        v = comp(kb, ix, base);
+                        in = (unbounded || v < U) && !(pshift < 128 && (v >> pshift) != prefix);
+                    }
+                    // most keys fall into a few low bins: the lanes sharing the first active lane's bin
+                    // add in one atomic, the others one each
+                    const uint32_t b = in ? ((uint32_t)(v >> shift) & ((1u << db) - 1u)) : 0xFFFFFFFFu;
+                    const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b);
+                    const uint64_t same = __ballot(in && b == b0);
+                    if (same && lane == (int)__builtin_ctzll(same)) atomicAdd(&hist[b0], (uint32_t)__popcll(same));
+                    if (in && b != b0) atomicAdd(&hist[b], 1u);
                 });
                 __syncthreads();
                 // suffix sums from the top digit (Hillis-Steele in place over NBIN bins)
@@ -523,7 +524,11 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
                     for (int q = 0; q < 2; ++q) hist[tid + q * 1024] += add[q];
                     __syncthreads();
                 }
-                // hist[b] is now the count of keys with digit >= b
+                // hist[b] is now the count of keys with digit >= b; hist[0] counts every eligible key
+                if (pass == 0 && hist[0] <= CAP) {
+                    none_left = hist[0] == 0;
+                    break;
+                }
                 const uint32_t need = s_need;
                 if (tid == 0) { s_digit = 0; s_sel_in_bin = hist[0]; }
                 __syncthreads();
@@ -550,16 +555,25 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
                 __syncthreads();
             }
         }
+        if (none_left) break;
 
-        // ---- 3) gather [T, U) into LDS
+        // ---- 2) gather [T, U) into LDS
         if (tid == 0) s_bcount = 0;
         __syncthreads();
         for_each_key(keys, idx, N, tid, [&](uint64_t kb, uint32_t ix) {
-            if (kb < base) return;
-            const u128 v = comp(kb, ix, base);
-            if (v < T || (!unbounded && v >= U)) return;
-            const int slot = atomicAdd(&s_bcount, 1);
-            if (slot < CAP) {          // always true by construction of T; keeps LDS writes in range
+            bool take = kb >= base;
+            if (take) {
+                const u128 v = comp(kb, ix, base);
+                take = !(v < T || (!unbounded && v >= U));
+            }
+            // one atomic per wave for the wave's selected keys
+            const uint64_t m = __ballot(take);
+            if (!m) return;
+            int first = 0;
+            if (lane == (int)__builtin_ctzll(m)) first = atomicAdd(&s_bcount, __popcll(m));
+            first = __shfl(first, (int)__builtin_ctzll(m), 64);
+            const int slot = first + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            if (take && slot < CAP) {  // always true by construction of T; keeps LDS writes in range
                 bkey[slot] = kb;
                 bidx[slot] = ix;
             }
@@ -571,7 +585,7 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
         for (int i = bc + tid; i < p2; i += 1024) { bkey[i] = 0; bidx[i] = 0xFFFFFFFFu; }
         __syncthreads();
 
-        // ---- 4) bitonic sort, earliest first
+        // ---- 3) bitonic sort, earliest first
         for (int k = 2; k <= p2; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
                 for (int i = tid; i < p2; i += 1024) {
@@ -588,20 +602,24 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
             }
         }
 
-        // ---- 5) greedy acceptance, 64 candidates at a time
+        // ---- 4) greedy acceptance, 64 candidates at a time. Wave 0 stages a group's coordinates. All
+        // waves then test the group against the corners accepted so far and fill the group's 64 x 64
+        // matrix of too-close earlier members. Wave 0 accepts the members clear of both at once and
+        // walks only the contested ones in order; then it stages the next group. Two barriers a group.
+        if (tid < 64) {
+            s_conf[tid] = 0;
+            if (tid < bc) {
+                const uint32_t ix = bidx[tid];
+                s_cx[tid] = (int32_t)(ix % (uint32_t)W);
+                s_cy[tid] = (int32_t)(ix / (uint32_t)W);
+            }
+        }
+        __syncthreads();
         for (int g0 = 0; g0 < bc; g0 += 64) {
             const int na = s_nacc;
             if (na >= K) break;
-            if (tid < 64) {
-                s_conf[tid] = 0;
-                if (g0 + tid < bc) {
-                    const uint32_t ix = bidx[g0 + tid];
-                    s_cx[tid] = (int32_t)(ix % (uint32_t)W);
-                    s_cy[tid] = (int32_t)(ix / (uint32_t)W);
-                }
-            }
-            __syncthreads();
-            if (g0 + lane < bc) {
+            const int gn = min(64, bc - g0);                  // members in this group
+            if (lane < gn) {
                 const int cx = s_cx[lane], cy = s_cy[lane];
                 bool conf = false;
                 // wave wv checks accepted corners wv, wv + 16, ...; four independent reads per step
@@ -616,35 +634,46 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
                     }
                 }
                 if (conf) s_conf[lane] = 1;
+                // members 4 wv .. 4 wv + 3 of the group that come before this lane and are too close
+                uint32_t bits = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int j = 4 * wv + b;
+                    if (j < lane) {
+                        const int64_t dx = cx - s_cx[j], dy = cy - s_cy[j];
+                        if (dx * dx + dy * dy < d2) bits |= 1u << b;
+                    }
+                }
+                s_mbits[lane * 16 + wv] = (uint8_t)bits;
+            } else {
+                s_mbits[lane * 16 + wv] = 0;
             }
             __syncthreads();
             if (wv == 0) {
-                const bool valid = g0 + lane < bc;
+                const bool valid = lane < gn;
                 const int cx = valid ? s_cx[lane] : 0, cy = valid ? s_cy[lane] : 0;
-                uint64_t mask = 0;                      // earlier group members too close
-                for (int k = 0; k < 64; ++k) {
-                    if (k >= lane || g0 + k >= bc) break;
-                    const int64_t dx = cx - s_cx[k], dy = cy - s_cy[k];
-                    if (dx * dx + dy * dy < d2) mask |= 1ull << k;
-                }
-                const uint32_t pre = valid ? s_conf[lane] : 1u;
-                uint64_t acc_mask = 0;
-                int cnt_acc = na;
-                // in group order, over the members not already too close to an accepted corner
-                uint64_t todo = __ballot(pre == 0);
-                while (todo && cnt_acc < K) {
-                    const int k = __builtin_ctzll(todo);
-                    todo &= todo - 1;
+                const bool pre_ok = valid && s_conf[lane] == 0;
+                const uint64_t ok = __ballot(pre_ok);
+                const uint4 mb = *reinterpret_cast<const uint4*>(&s_mbits[lane * 16]);
+                const uint32_t w4[4] = {mb.x, mb.y, mb.z, mb.w};
+                uint64_t mask = 0;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) mask |= (uint64_t)((w4[q >> 2] >> (8 * (q & 3))) & 0xFu) << (4 * q);
+                mask &= ok;                                   // earlier members still eligible and too close
+                uint64_t acc = __ballot(pre_ok && mask == 0); // no earlier eligible member too close
+                uint64_t contested = ok & ~acc;
+                while (contested) {
+                    const int k = __builtin_ctzll(contested);
+                    contested &= contested - 1;
                     const uint32_t mlo = __builtin_amdgcn_readlane((uint32_t)mask, k);
                     const uint32_t mhi = __builtin_amdgcn_readlane((uint32_t)(mask >> 32), k);
-                    const uint64_t mk = ((uint64_t)mhi << 32) | mlo;
-                    if (!(mk & acc_mask)) {
-                        acc_mask |= 1ull << k;
-                        ++cnt_acc;
-                    }
+                    if (!((((uint64_t)mhi << 32) | mlo) & acc)) acc |= 1ull << k;
                 }
-                if ((acc_mask >> lane) & 1ull) {
-                    const int rank = na + __popcll(acc_mask & ((1ull << lane) - 1ull));
+                // the corner budget keeps the first K - na acceptances in group order
+                const int allowed = K - na;
+                const int rank_in = __popcll(acc & ((1ull << lane) - 1ull));
+                if (((acc >> lane) & 1ull) && rank_in < allowed) {
+                    const int rank = na + rank_in;
                     acc_x[rank] = cx;
                     acc_y[rank] = cy;
                     float* o = xy_out + (rec * capacity + rank) * 2;
@@ -653,7 +682,14 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
                     if (score_out)
                         score_out[rec * capacity + rank] = __longlong_as_double((long long)bkey[g0 + lane]);
                 }
-                if (lane == 0) s_nacc = cnt_acc;
+                if (lane == 0) s_nacc = na + min(__popcll(acc), allowed);
+                // stage the next group
+                s_conf[lane] = 0;
+                if (g0 + 64 + lane < bc) {
+                    const uint32_t ix = bidx[g0 + 64 + lane];
+                    s_cx[lane] = (int32_t)(ix % (uint32_t)W);
+                    s_cy[lane] = (int32_t)(ix / (uint32_t)W);
+                }
             }
             __syncthreads();
         }
