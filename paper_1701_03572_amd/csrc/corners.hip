@@ -31,7 +31,7 @@ typedef unsigned __int128 u128;
 
 struct CandHeader {
     uint32_t count;        // candidates (exact 3x3 maxima) in the key/index lists
-    uint32_t raw_count;    // survivors appended by the response kernel
+    uint32_t raw_count;    // survivor-list entries reserved by the response kernel (unused ones are marked)
     uint64_t lmax_bits;
 };
 
@@ -39,17 +39,28 @@ constexpr int64_t HDR = 256;
 constexpr int SW = 240;         // output columns per wave strip (lanes 1..62 of 64 x 4 columns)
 constexpr int SUP = 6;          // rows per unrolled super-step (period of the register rotation)
 constexpr int SR = 60;          // output rows per wave: the pipeline runs SR + 6 pixel rows
+constexpr int SR_FEW = 12;      // rows per wave for batches of at most 8 frames (more waves per frame)
 constexpr int CAP = 4096;       // LDS batch capacity of the selection
 constexpr int BATCH = 2048;     // keys requested per batch
 constexpr int DIGIT = 11;
 constexpr int NBIN = 1 << DIGIT;
+// Each response wave reserves its survivor-list entries RAW_CHUNK at a time (one atomic per chunk
+// rather than one per row on the frame's single counter, whose atomics serialise in L2); entries
+// of a chunk it does not fill are marked RAW_UNUSED.
+constexpr uint32_t RAW_CHUNK = 256;   // >= 4 columns x 64 lanes, so one row's survivors always fit
+constexpr uint32_t RAW_UNUSED = 0xFFFFFFFFu;
+
+// response waves of one item at most (the smaller segment height, strips over the whole width)
+__host__ __device__ inline int64_t max_waves(int w, int h) { return (int64_t)(w / SW + 2) * (h / SR_FEW + 2); }
 
 // per item: header | keys (8 B each) | indices (4 B) | survivors (16 B: A, B, C, index | flag << 31);
-// every list has room for one entry per pixel
+// the key and index lists have room for one entry per pixel, the survivor list also for one
+// partly filled chunk per response wave
+__host__ __device__ inline int64_t raw_entries(int w, int h) { return (int64_t)w * h + max_waves(w, h) * RAW_CHUNK; }
 __host__ __device__ inline int64_t per_item_bytes(int w, int h)
 {
     const int64_t c = (int64_t)w * h;
-    return (HDR + 8 * c + 4 * c + 16 * c + 255) & ~(int64_t)255;
+    return (HDR + 8 * c + 4 * c + 16 * raw_entries(w, h) + 255) & ~(int64_t)255;
 }
 
 __device__ __forceinline__ CandHeader* hdr_of(uint8_t* ws, int64_t item_bytes, int item)
@@ -154,7 +165,14 @@ struct RespState {
     int ha[3][4], hb[3][4], hc[3][4];
     int sa[2][4], sb[2][4], sc[2][4];
     float sv[2][4], hm[3][4], sd[2][4];
+    uint32_t cbase, cfill;   // the wave's current survivor chunk (wave-uniform) and its fill
 };
+
+// marks entries [from, to) of the survivor list unused (the whole wave writes them)
+__device__ __forceinline__ void mark_unused(uint4* raw, uint32_t from, uint32_t to, int lane)
+{
+    for (uint32_t i = from + lane; i < to; i += 64) raw[i] = make_uint4(0u, 0u, 0u, RAW_UNUSED);
+}
 
 struct RespCtx {
     int lane, xb, oy, oy_end;
@@ -254,9 +272,16 @@ __device__ __forceinline__ void resp_step(RespState& st, uint32_t P, int t, cons
             tot += (uint32_t)__popcll(bal[c]);
         }
         if (tot) {
-            uint32_t base = 0;
-            if (cx.lane == 0) base = atomicAdd(cx.raw_count, tot);
-            base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+            if (st.cfill + tot > RAW_CHUNK) {
+                // the current chunk is full: mark its rest unused and reserve the next one
+                if (st.cbase != RAW_UNUSED) mark_unused(cx.raw, st.cbase + st.cfill, st.cbase + RAW_CHUNK, cx.lane);
+                uint32_t b = 0;
+                if (cx.lane == 0) b = atomicAdd(cx.raw_count, RAW_CHUNK);
+                st.cbase = (uint32_t)__builtin_amdgcn_readfirstlane((int)b);
+                st.cfill = 0;
+            }
+            uint32_t base = st.cbase + st.cfill;
+            st.cfill += tot;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const uint32_t lo = (uint32_t)bal[c], hi = (uint32_t)(bal[c] >> 32);
@@ -273,8 +298,9 @@ __device__ __forceinline__ void resp_step(RespState& st, uint32_t P, int t, cons
 
 __global__ __launch_bounds__(256) void corner_response_kernel(const uint8_t* __restrict__ frames, int64_t frame_stride,
                                                               int W, int H, int pitch, int mx, int my, int n_items,
-                                                              int strips, int segs, int istride, const int32_t* gate,
-                                                              int gate_min, uint8_t* ws, int64_t item_bytes)
+                                                              int strips, int segs, int sr, int istride,
+                                                              const int32_t* gate, int gate_min, uint8_t* ws,
+                                                              int64_t item_bytes)
 {
     const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);   // one independent wave per (item, strip, segment)
     const int per_item = strips * segs;
@@ -291,10 +317,10 @@ __global__ __launch_bounds__(256) void corner_response_kernel(const uint8_t* __r
     cx.out_lo = mx + SW * strip;
     cx.out_hi = min(cx.out_lo + SW, cx.rx1);
     cx.xb = ((cx.out_lo - 4) & ~3) + 4 * cx.lane;   // lanes 1..62 cover [out_lo, out_lo + SW)
-    cx.oy = my + SR * seg;
-    cx.oy_end = min(cx.oy + SR, cx.ry1);
+    cx.oy = my + sr * seg;
+    cx.oy_end = min(cx.oy + sr, cx.ry1);
     cx.raw_count = &hdr_of(ws, item_bytes, item)->raw_count;
-    cx.raw = raw_of(ws, item_bytes, item, W, H);
+    cx.raw = raw_of(ws, item_bytes, item, W, H);   // room for raw_entries(W, H) entries
 
     // pixel rows are read through a buffer descriptor: rows or columns past the image read as 0 and
     // only feed estimates outside the ROI, which the NMS ignores
@@ -305,6 +331,8 @@ __global__ __launch_bounds__(256) void corner_response_kernel(const uint8_t* __r
     };
 
     RespState st;
+    st.cbase = RAW_UNUSED;
+    st.cfill = RAW_CHUNK;                       // no chunk yet: the first survivors reserve one
     const int nsteps = (cx.oy_end - cx.oy) + 6;
     const int nsup = (nsteps + SUP - 1) / SUP;
     uint32_t P[SUP];
@@ -335,6 +363,7 @@ __global__ __launch_bounds__(256) void corner_response_kernel(const uint8_t* __r
         resp_step<4, true, true, true>(st, P[4], t0 + 4, cx);
         resp_step<5, true, true, true>(st, P[5], t0 + 5, cx);
     }
+    if (st.cbase != RAW_UNUSED) mark_unused(cx.raw, st.cbase + st.cfill, st.cbase + RAW_CHUNK, cx.lane);
 }
 
 // Exact scores of the survivors; flagged ones get the exact NMS against their in-ROI neighbours.
@@ -351,15 +380,18 @@ __global__ __launch_bounds__(256) void corner_keys_kernel(const uint8_t* __restr
     uint64_t* keys = keys_of(ws, item_bytes, item);
     uint32_t* idx = idx_of(ws, item_bytes, item, W, H);
     const uint8_t* img = frames + item * frame_stride;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int rx0 = mx, rx1 = W - mx, ry0 = my, ry1 = H - my;
+    __shared__ uint32_t s_wcnt[4], s_base;
+    __shared__ uint64_t s_wmax[4];
+    uint64_t mx_bits = 0;
     for (uint32_t b0 = blockIdx.x * 256u; b0 < nraw; b0 += gridDim.x * 256u) {
         const uint32_t i = b0 + threadIdx.x;
         bool keep = false;
         uint64_t kb = 0;
         uint32_t ix = 0;
-        if (i < nraw) {
-            const uint4 r = raw[i];
+        const uint4 r = i < nraw ? raw[i] : make_uint4(0u, 0u, 0u, RAW_UNUSED);
+        if (r.w != RAW_UNUSED) {
             ix = r.w & 0x7FFFFFFFu;
             const double key = exact_key((int32_t)r.x, (int32_t)r.y, (int32_t)r.z);
             keep = key > 0.0;
@@ -376,24 +408,37 @@ __global__ __launch_bounds__(256) void corner_keys_kernel(const uint8_t* __restr
             }
             kb = (uint64_t)__double_as_longlong(key);
         }
+        // one atomic per workgroup and iteration places the workgroup's kept candidates
         const uint64_t bal = __ballot(keep);
-        if (bal) {
-            uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(&hd->count, (uint32_t)__popcll(bal));
-            base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
-            const uint32_t pos = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            if (keep) {
-                keys[pos] = kb;
-                idx[pos] = ix;
-            }
-            uint64_t m = keep ? kb : 0;
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-                const uint64_t t = __shfl_xor(m, o, 64);
-                m = t > m ? t : m;
-            }
-            if (lane == 0) atomicMax((unsigned long long*)&hd->lmax_bits, (unsigned long long)m);
+        if (lane == 0) s_wcnt[wv] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t tot = (s_wcnt[0] + s_wcnt[1]) + (s_wcnt[2] + s_wcnt[3]);
+            s_base = tot ? atomicAdd(&hd->count, tot) : 0u;
         }
+        __syncthreads();
+        uint32_t pos = s_base;
+        for (int w = 0; w < wv; ++w) pos += s_wcnt[w];
+        pos += __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        if (keep) {
+            keys[pos] = kb;
+            idx[pos] = ix;
+            if (kb > mx_bits) mx_bits = kb;
+        }
+        __syncthreads();
+    }
+    // the largest kept key: one atomic per workgroup
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const uint64_t t = __shfl_xor(mx_bits, o, 64);
+        mx_bits = t > mx_bits ? t : mx_bits;
+    }
+    if (lane == 0) s_wmax[wv] = mx_bits;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t m = s_wmax[0];
+        for (int w = 1; w < 4; ++w) m = s_wmax[w] > m ? s_wmax[w] : m;
+        if (m) atomicMax((unsigned long long*)&hd->lmax_bits, (unsigned long long)m);
     }
 }
 
@@ -747,15 +792,19 @@ extern "C" int vs_detect_corners(const uint8_t* frames, int64_t frame_stride, in
     int e = vs::check_launch("vs_detect_corners(init)");
     if (e) return e;
     const int rw = width - 2 * p->roi_mx, rh = height - 2 * p->roi_my;
-    const int strips = (rw + SW - 1) / SW, segs = (rh + SR - 1) / SR;
+    // each output row belongs to one wave's segment and the survivors are sorted afterwards, so the
+    // segment height only trades per-wave warm-up rows against waves per frame
+    const int sr = n <= 8 ? SR_FEW : SR;
+    const int strips = (rw + SW - 1) / SW, segs = (rh + sr - 1) / sr;
     const int64_t nwaves = (int64_t)n * strips * segs;
     corner_response_kernel<<<(unsigned)((nwaves + 3) / 4), 256, 0, s>>>(frames, frame_stride, width, height, pitch,
-                                                                      p->roi_mx, p->roi_my, n, strips, segs, istride,
-                                                                      gate, gate_min, w8, ib);
+                                                                      p->roi_mx, p->roi_my, n, strips, segs, sr,
+                                                                      istride, gate, gate_min, w8, ib);
     e = vs::check_launch("vs_detect_corners(response)");
     if (e) return e;
-    // survivors are a small fraction of the ROI: 32 blocks per item stride over them
-    corner_keys_kernel<<<dim3(32, n), 256, 0, s>>>(frames, frame_stride, width, height, pitch, p->roi_mx, p->roi_my,
+    // survivors are a small fraction of the ROI: 32 blocks per item stride over them (256 for
+    // batches of at most 8 frames)
+    corner_keys_kernel<<<dim3(n <= 8 ? 256 : 32, n), 256, 0, s>>>(frames, frame_stride, width, height, pitch, p->roi_mx, p->roi_my,
                                                    istride, gate, gate_min, w8, ib);
     e = vs::check_launch("vs_detect_corners(keys)");
     if (e) return e;
