@@ -228,6 +228,7 @@ def main() -> int:
     ap.add_argument("--batched-streams", type=int, default=64)
     ap.add_argument("--batched-frames", type=int, default=120)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-hbm", action="store_true", help="skip the extra pyramid/warp launches of the HBM figures")
     ap.add_argument("--serving-seconds", type=float, default=4.0)
     ap.add_argument("--tuning", choices=["auto", "default", "cached"], default="auto",
                     help="launch tuning: autotune on the workload before timing (default), the library defaults, "
@@ -327,10 +328,12 @@ def main() -> int:
                 "share_of_step": round(lk_share, 4),
                 "iterations_per_setup": float(w[..., 1].sum() / max(w[..., 0].sum(), 1))}
 
-    hbm = hbm_figures(V, ss, frames, P, n, W, H, ms_per_step)
-    log("hbm: pyramid %.0f GB/s, warp %.0f GB/s; whole step %.2f MB/frame algorithmic, %.0f GB/s (%.3f of 8 TB/s)" %
-        (hbm["pyramid"]["achieved_gb_s"], hbm["warp"]["achieved_gb_s"], hbm["step"]["bytes_per_frame"] / 1e6,
-         hbm["step"]["achieved_gb_s"], hbm["step"]["frac"]))
+    hbm = None
+    if not args.no_hbm:
+        hbm = hbm_figures(V, ss, frames, P, n, W, H, ms_per_step)
+        log("hbm: pyramid %.0f GB/s, warp %.0f GB/s; whole step %.2f MB/frame algorithmic, %.0f GB/s (%.3f of 8 TB/s)" %
+            (hbm["pyramid"]["achieved_gb_s"], hbm["warp"]["achieved_gb_s"], hbm["step"]["bytes_per_frame"] / 1e6,
+             hbm["step"]["achieved_gb_s"], hbm["step"]["frac"]))
 
     if args.calibrate_copy:
         a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
