@@ -2,8 +2,10 @@
 // in the same launch.
 //
 // Each 256-thread workgroup produces a 128 x 32 tile of level l+1 from the (2*128+3) x (2*32+3) input
-// window of level l, staged in LDS with 16-byte loads from reflect-101 rows (16-byte chunks that cross
-// the left or right frame edge: byte by byte with reflect-101 columns). Each thread then produces a 4 x 4 block: for each of its 11 input rows
+// window of level l, staged in LDS with 16-byte loads from reflect-101 rows. Columns outside the frame
+// are never loaded: a chunk crossing an edge loads its in-frame bytes one by one, and after staging
+// the (at most two) reflect-101 columns on each side are copied inside LDS from the columns they
+// mirror. Each thread then produces a 4 x 4 block: for each of its 11 input rows
 // it forms the 4 horizontal 5-tap sums with byte dot products on aligned LDS words, and it filters
 // those sums vertically in registers. All sums are exact integers (<= 65280); one rounding at the end
 // makes the result bit-identical to the direct 5 x 5 integer sum.
@@ -60,9 +62,8 @@ __global__ __launch_bounds__(256) void pyr_down_kernel(const uint8_t* __restrict
                 const int gx = a0 + 16 * c;
                 if (vec_ok && gx >= 0 && gx + 16 <= sw) {
                     v[j] = __builtin_bit_cast(V4, __builtin_amdgcn_raw_buffer_load_b128(rs, gy * src_pitch + gx, 0, 0));
-                } else {
-                    // chunk crossing the left or right frame edge (or an unaligned source): 16 independent
-                    // byte loads from reflect-101 columns, issued together
+                } else if (!vec_ok) {
+                    // unaligned source rows: 16 byte loads from reflect-101 columns, issued together
                     uint32_t wd[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
                     for (int e = 0; e < 16; ++e) {
@@ -71,7 +72,20 @@ __global__ __launch_bounds__(256) void pyr_down_kernel(const uint8_t* __restrict
                         wd[e >> 2] |= byte << (8 * (e & 3));
                     }
                     v[j] = V4{wd[0], wd[1], wd[2], wd[3]};
+                } else {
+                    // chunk crossing an edge: its in-frame bytes (the reflected columns are filled in LDS)
+                    uint32_t wd[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int x = gx + e;
+                        if (x >= 0 && x < sw)
+                            wd[e >> 2] |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, gy * src_pitch + x, 0, 0)
+                                          << (8 * (e & 3));
+                    }
+                    v[j] = V4{wd[0], wd[1], wd[2], wd[3]};
                 }
+            } else if (k < NCH * IH) {
+                v[j] = V4{0u, 0u, 0u, 0u};
             }
         }
 #pragma unroll
@@ -80,6 +94,23 @@ __global__ __launch_bounds__(256) void pyr_down_kernel(const uint8_t* __restrict
             const int r = k / NCH, c = k - r * NCH;
             if (k < NCH * IH && r < need_r && 16 * c - OFF < need_c)
                 *reinterpret_cast<V4*>(&tin[16 * k]) = v[j];   // row r, chunk c at r * LP + 16 c
+        }
+        // reflect-101 columns: global column g sits at LDS byte OFF + g - ix0 of its row; left of the
+        // frame -1, -2 mirror 1, 2; right of it sw, sw + 1 mirror sw - 2, sw - 3
+        const bool left = ix0 < 0, right = ix0 + need_c > sw;
+        if (vec_ok && (left || right)) {
+            __syncthreads();
+            if (tid < need_r) {
+                uint8_t* row = &tin[tid * LP + OFF - ix0];
+                if (left) {
+                    row[-1] = row[1];
+                    row[-2] = row[2];
+                }
+                if (right) {
+                    row[sw] = row[sw - 2];
+                    if (ix0 + need_c > sw + 1) row[sw + 1] = row[sw - 3];
+                }
+            }
         }
     }
     __syncthreads();
