@@ -1,7 +1,8 @@
 // warp_frame: inverse-mapped bilinear warp of 8-bit frames, all items of a batch in one launch.
 //
-// A 256-thread workgroup covers a 256 x 32 output tile; each thread produces 4 consecutive pixels in
-// each of 8 rows, stored as one 32-bit word per row when the row allows it. The 2x3 matrix is
+// A 256-thread workgroup covers a 256 x 64 output tile; each thread produces 4 consecutive pixels in
+// each of 16 rows (tall tiles spread the per-tile matrix inversion, source box and staging over more
+// pixels), stored as one 32-bit word per row when the row allows it. The 2x3 matrix is
 // inverted in binary64; per-pixel source coordinates are FP32, relative to the tile's source box.
 //
 // Source box: the map is affine and is evaluated in a form that is monotone in x and in y, so the
@@ -17,11 +18,11 @@
 namespace {
 
 constexpr int TW = 256;                 // tile width: 64 lanes x 4 pixels
-constexpr int RPT = 8;                  // rows per thread
+constexpr int RPT = 16;                 // rows per thread
 constexpr int TH = 4 * RPT;             // 4 waves stacked vertically
 constexpr int LW = 288;                 // LDS row pitch: 18 chunks of 16 bytes
 constexpr int NCH = LW / 16;
-constexpr int MAXR = 64;                // staged rows at most
+constexpr int MAXR = 96;                // staged rows at most
 constexpr int NLD = (NCH * MAXR + 255) / 256;
 constexpr float BIG = 1048576.0f;       // boxes beyond +-2^20 take the direct path
 constexpr uint32_t RSRC_WORD3 = 0x00020000;   // raw (untyped) buffer access on gfx9-family parts
