@@ -3,12 +3,16 @@
 //
 // Lane layout for a (2h+1)^2 window: the window's 2h+1 columns are spread over the lanes and the
 // rows over G = 64 / (2h+1) lane groups, each group owning R = ceil((2h+1) / G) consecutive rows
-// (h = 10: 21 columns x 3 groups of 7 rows = 63 lanes). Samples outside the window get zero
-// gradient weight, so every lane runs the same branch-free loops. All samples of a window share
-// one fractional offset, so per level a lane reads its (R+3) x 4 previous-frame block once (one
-// unaligned 32-bit load per row when the whole window is inside the level, edge-clamped byte loads
-// otherwise), interpolates each row horizontally first and derives I, dI/dx, dI/dy of its R samples
-// into registers.
+// (h = 10: 21 columns x 3 groups of 7 rows = 63 lanes). Lanes outside every group read out of their
+// buffer's range, which returns zeros, so all their terms vanish; when the window's rows do not
+// fill every group's R rows, the samples past the window get zero gradient weight. Every lane runs
+// the same branch-free loops. All samples of a window share one fractional offset, so per level a
+// lane reads its (R+3) x 4 previous-frame block once (one unaligned 32-bit load per row when the
+// whole window is inside the level, edge-clamped byte loads otherwise; row offsets go in the scalar
+// offset of the buffer load), interpolates each row horizontally first and derives I and the two
+// central differences of its R samples into registers. The differences are kept without their
+// factor 1/2 (D = 2 grad I): the tensor then carries a factor 4 and the residual sums a factor 2,
+// both exact powers of two, which the minimum-eigenvalue test and the step solve absorb.
 //
 // Gauss-Newton iterations: all samples also share the iterate's fractional offset (ja, jb), so the
 // residual sum over the window, sum (I - J) grad I, is E0 - ja E1 - jb E2 - ja jb E3 with four sums
@@ -18,15 +22,18 @@
 // pixel costs a few wave-uniform operations. The lanes accumulate plain sums of products of raw
 // next-frame pixels with the gradients (no per-sample differences), and the E sums are formed from
 // the reduced totals. The first block of each level is read with the set-up, and its eight sums
-// share the set-up's reduction with the three tensor sums and the two sums of I times the gradient. Reductions are
-// transposing DPP row sums, so several sums cost little more than one; every lane ends with the
-// same totals, and the iteration control is wave-uniform. One wave per workgroup lets every point
-// retire independently.
+// share the set-up's reduction with the three tensor sums and the two sums of I times the gradient.
+// Reductions are transposing (lane-swap and DPP steps), so several sums cost little more than one;
+// the totals are read as uniforms, and the iteration control is wave-uniform. One wave per
+// workgroup lets every point retire independently.
 #include "vs_common.hpp"
 
 namespace {
 
 constexpr uint32_t RSRC_WORD3 = 0x00020000;   // raw (untyped) buffer access on gfx9-family parts
+// vector offset of lanes outside the window: at or past 2^31, beyond every level's byte count (the
+// host limits a level to fewer than 2^31 bytes), so their buffer loads return 0
+constexpr int OOB = -2147483647 - 1;
 
 struct Img {
     __amdgpu_buffer_rsrc_t rs;
@@ -64,29 +71,129 @@ __device__ __forceinline__ float det2(float g11, float g22, float g12)
 struct LKConst {
     int hw, cols, groups, rows, nwin;
     int max_iter;
-    float eps2, min_eig;
+    int full;          // the window's rows fill every lane group's `rows` rows exactly
+    float eps2, eig_thr;   // eig_thr = 4 N min_eig
 };
 
 __device__ __forceinline__ bool wave_all(bool c) { return __ballot(!c) == 0; }
+// for a condition every lane evaluates identically: a scalar branch condition
+__device__ __forceinline__ bool uniform(bool c) { return __ballot(c) != 0; }
 
-// Next-frame 2-pixel rows x0, x0 + 1 of rows y0 .. y0 + RMAX: qa = P(x0), qb = P(x0 + 1). When every
-// active lane's block is inside the level, one (unaligned) 16-bit load per row; otherwise
-// edge-clamped byte loads.
+// Per-wave LDS scratch of the window sums: the lanes' values stored transposed (value j of lane l at
+// j * RED_STRIDE + l; the odd stride puts the lanes of every later read on distinct banks), then 64
+// chunk sums and 16 totals.
+constexpr int RED_STRIDE = 65;
+constexpr int RED_FLOATS = 16 * RED_STRIDE + 64 + 16;
+// The same per-wave area first holds staged image blocks: STAGE_ROWS rows of 32 bytes (the window's
+// rows, 4-byte aligned at the left), written by one 16-byte load per lane pair. A zeroed area after
+// it serves the lanes outside the window, whose reads must return 0.
+constexpr int STAGE_ROWS = 24;
+constexpr int ZERO_FLOATS = 80;   // 10 rows of 32 bytes
+constexpr int WAVE_LDS_FLOATS = RED_FLOATS + ZERO_FLOATS;
+static_assert(STAGE_ROWS * 8 <= RED_FLOATS && WAVE_LDS_FLOATS % 4 == 0, "staging fits the reduction area");
+
+// orders one wave's LDS accesses across lanes (LDS operations of a wave complete in issue order)
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Wave totals of the first M of N (8 or 16) values per lane, returned in every lane. Lane l adds value
+// l % N over the N lanes of its chunk l / N, lane j < M then adds the 64 / N chunk sums of value j, and
+// every lane reads the M totals back (a broadcast read). The order of the additions is fixed, so the
+// totals are the same in every lane and on every run. The cross-lane traffic goes through LDS, which
+// costs no vector ALU cycles beyond the additions.
+template <int N, int M>
+__device__ __forceinline__ void wave_sums(const float (&v)[N], float (&tot)[M], float* red)
+{
+    static_assert(N == 8 || N == 16, "8 or 16 values per lane");
+    constexpr int C = 64 / N;   // chunks
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < M; ++j) red[j * RED_STRIDE + lane] = v[j];
+    wave_lds_sync();
+    const int vj = lane % N, ch = lane / N;
+    const float* col = red + vj * RED_STRIDE + ch * N;
+    float s = col[0];
+#pragma unroll
+    for (int i = 1; i < N; ++i) s += col[i];
+    float* part = red + 16 * RED_STRIDE;
+    part[vj * C + ch] = s;
+    wave_lds_sync();
+    float* T = part + 64;
+    if (lane < M) {
+        float t = part[lane * C];
+#pragma unroll
+        for (int k = 1; k < C; ++k) t += part[lane * C + k];
+        T[lane] = t;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < M; ++j) tot[j] = T[j];
+    wave_lds_sync();   // the next call's stores come after these reads
+}
+
+// Stages rows r0 .. r0 + nr - 1, bytes c0 .. c0 + 31 (c0 a multiple of 4) of the level into the wave's
+// LDS rows (32 bytes each): lane 2r + h loads row r's 16-byte half h with one load. Bytes past the
+// level's range read as 0 (buffer range check); the caller uses only bytes inside the level.
+__device__ __forceinline__ void stage_rows(const Img& A, int r0, int nr, int c0, uint32_t* rows)
+{
+    const int lane = threadIdx.x & 63;
+    const int r = lane >> 1, h = lane & 1;
+    if (r < nr) {
+        const int off = (int)__umul24((unsigned)(r0 + r), (unsigned)A.pitch) + c0 + 16 * h;
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(A.rs, off, 0, 0);
+        *reinterpret_cast<u32x4*>(rows + 8 * r + 4 * h) = v;
+    }
+    wave_lds_sync();
+}
+
+// the 4 bytes at byte offset 4 * word + shift of an LDS area (shift 0..3), read as two aligned words
+__device__ __forceinline__ uint32_t lds_word(const uint32_t* p, unsigned shift)
+{
+    return __builtin_amdgcn_alignbyte(p[1], p[0], shift);
+}
+
+// Next-frame 2-pixel rows x0, x0 + 1 of rows y0 .. y0 + RMAX: qa = P(x0), qb = P(x0 + 1). The lane's
+// block sits at column gcol and row lrow of the window's block, whose origin is (bx, by). When every
+// active lane's block is inside the level: for windows of at most 7 rows per lane the window's
+// 22-row block is staged in LDS with one load and each lane reads its rows there; larger windows
+// load one (unaligned) 16-bit word per row, the row offset in the load's scalar offset. Otherwise
+// edge-clamped byte loads. Inactive lanes read zeros.
 template <int RMAX>
-__device__ __forceinline__ void load_next_block(const Img& B, int x0, int y0, bool active, float (&qa)[RMAX + 1],
-                                                float (&qb)[RMAX + 1])
+__device__ __forceinline__ void load_next_block(const Img& B, int x0, int y0, int bx, int by, int lane_off, bool active,
+                                                uint32_t* stage, float (&qa)[RMAX + 1], float (&qb)[RMAX + 1])
 {
     const bool b_in = wave_all(!active || (x0 >= 0 && x0 + 1 <= B.w - 1 && y0 >= 0 && y0 + RMAX <= B.h - 1));
     if (b_in) {
+        if constexpr (RMAX <= 7) {
+            const int c0 = bx & ~3;
+            stage_rows(B, by, STAGE_ROWS - 2, c0, stage);
+            const int o = active ? lane_off + (bx - c0) : 4 * RED_FLOATS;
+            const uint32_t* p = stage + (o >> 2);
+            const unsigned sh = (unsigned)(o & 3);
 #pragma unroll
-        for (int k = 0; k <= RMAX; ++k) {
-            const uint32_t w = __builtin_amdgcn_raw_buffer_load_b16(
-                B.rs, (int)__umul24((unsigned)(y0 + k), (unsigned)B.pitch) + x0, 0, 0);
-            qa[k] = (float)(w & 0xff);
-            qb[k] = (float)((w >> 8) & 0xff);
+            for (int k = 0; k <= RMAX; ++k) {
+                const uint32_t w = lds_word(p + 8 * k, sh);
+                qa[k] = (float)(w & 0xff);
+                qb[k] = (float)((w >> 8) & 0xff);
+            }
+            wave_lds_sync();   // the area is written again by the next staging or reduction
+        } else {
+            const int v0 = active ? (int)__umul24((unsigned)y0, (unsigned)B.pitch) + x0 : OOB;
+#pragma unroll
+            for (int k = 0; k <= RMAX; ++k) {
+                const uint32_t w = __builtin_amdgcn_raw_buffer_load_b16(B.rs, v0, k * B.pitch, 0);
+                qa[k] = (float)(w & 0xff);
+                qb[k] = (float)((w >> 8) & 0xff);
+            }
         }
     } else {
-        const int c0 = vs::clampi(x0, 0, B.w - 1), c1 = vs::clampi(x0 + 1, 0, B.w - 1);
+        const int c0 = active ? vs::clampi(x0, 0, B.w - 1) : OOB;
+        const int c1 = active ? vs::clampi(x0 + 1, 0, B.w - 1) : OOB;
 #pragma unroll
         for (int k = 0; k <= RMAX; ++k) {
             const int base = (int)__umul24((unsigned)vs::clampi(y0 + k, 0, B.h - 1), (unsigned)B.pitch);
@@ -134,51 +241,110 @@ __device__ __forceinline__ void e_from_sums(float S, float A0, float A1, float B
     E[3] = (B1 - A1) - (B0 - A0);
 }
 
-// Previous-frame samples of one lane: I, and the gradient terms 0.5 * central differences (zero
-// outside the window), at rows iy .. iy + RMAX - 1 and column ix, offset by the shared fraction (a, b).
-// Rows iy-1 .. iy+RMAX+1 and columns ix-1 .. ix+2 are read: with FAST (every lane's block inside the
-// level) one unaligned 32-bit load per row, otherwise four edge-clamped byte loads. Rows are
-// interpolated horizontally first.
-template <int RMAX, bool FAST>
-__device__ __forceinline__ void window_samples(const Img& A, int ix, int iy, float a, float b, int nrows, float (&I)[RMAX],
+// The compiler would turn differences of converted bytes back into integer differences followed by
+// conversions; an empty asm statement hides the conversion's origin.
+__device__ __forceinline__ float byte_f(uint32_t p)
+{
+    float f = (float)p;
+    asm("" : "+v"(f));
+    return f;
+}
+
+// Horizontal terms of one previous-frame row from its pixels p0..p3 at columns ix-1 .. ix+2:
+// H = P(ix + a) and, with DIFF, D = P(ix + 1 + a) - P(ix - 1 + a) = (p2 - p0) + a ((p3 - p1) - (p2 - p0)).
+// The pixel differences are exact in binary32, so each term rounds once. Bytes are converted first
+// and differenced as floats: a float subtraction issues at twice the rate of an integer difference
+// followed by a conversion.
+
+template <bool DIFF>
+__device__ __forceinline__ void row_terms(uint32_t p0, uint32_t p1, uint32_t p2, uint32_t p3, float a, float& H, float& D)
+{
+    const float f1 = byte_f(p1), f2 = byte_f(p2);
+    H = fmaf(a, f2 - f1, f1);
+    if constexpr (DIFF) {
+        const float d20 = f2 - byte_f(p0);
+        D = fmaf(a, (byte_f(p3) - f1) - d20, d20);
+    }
+}
+
+// Previous-frame samples of one lane at rows iy .. iy + RMAX - 1 and column ix, offset by the shared
+// fraction (a, b): I, Dx = I(x + 1) - I(x - 1) and Dy = I(y + 1) - I(y - 1). Rows iy-1 .. iy+RMAX+1
+// and columns ix-1 .. ix+2 are read. With FAST (every lane's block inside the level) and at most 7
+// rows per lane, the window's 24-row block (origin (bx, by), 4-byte aligned left edge) is staged in
+// LDS with one load and the lane's rows start at byte lane_off of it; with FAST and larger windows,
+// one unaligned 32-bit load per row; otherwise four edge-clamped byte loads. Rows are interpolated horizontally
+// first; V(r) = lerp(H(r), H(r+1), b) gives I = V(k+1) and Dy = V(k+2) - V(k), and Dx interpolates
+// the rows' D vertically. With WEIGHTED, rows k >= nrows get Dx = Dy = 0.
+template <int RMAX, bool FAST, bool WEIGHTED>
+__device__ __forceinline__ void window_samples(const Img& A, int ix, int iy, int bx, int by, int lane_off, float a,
+                                               float b, int nrows, bool active, uint32_t* stage, float (&I)[RMAX],
                                                float (&Ix)[RMAX], float (&Iy)[RMAX])
 {
-    float H1[RMAX + 3], Dd[RMAX + 3];   // per row: horizontal lerp at the sample column, and the
-                                        // horizontal central difference lerped the same way
+    constexpr bool STAGED = FAST && RMAX <= 7;   // the window's 24-row block staged in LDS
+    float H[RMAX + 3], D[RMAX + 3];   // D is used for rows 1 .. RMAX + 1 only
+    int v0 = 0;
+    const uint32_t* sp = stage;
+    unsigned sh = 0;
+    if constexpr (STAGED) {
+        const int c0 = bx & ~3;
+        stage_rows(A, by, STAGE_ROWS, c0, stage);
+        const int o = active ? lane_off + (bx - c0) : 4 * RED_FLOATS;
+        sp = stage + (o >> 2);
+        sh = (unsigned)(o & 3);
+    } else {
+        v0 = active ? (int)__umul24((unsigned)(iy - 1), (unsigned)A.pitch) + ix - 1 : OOB;
+    }
+    int c[4];
+    if constexpr (!FAST) {
 #pragma unroll
-    for (int r = 0; r < RMAX + 3; ++r) {
-        float p0, p1, p2, p3;
-        if constexpr (FAST) {
-            const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(
-                A.rs, (int)__umul24((unsigned)(iy - 1 + r), (unsigned)A.pitch) + ix - 1, 0, 0);
-            p0 = (float)(w & 0xff);
-            p1 = (float)((w >> 8) & 0xff);
-            p2 = (float)((w >> 16) & 0xff);
-            p3 = (float)(w >> 24);
-        } else {
-            const int base = (int)__umul24((unsigned)vs::clampi(iy - 1 + r, 0, A.h - 1), (unsigned)A.pitch);
-            p0 = ld(A, base + vs::clampi(ix - 1, 0, A.w - 1));
-            p1 = ld(A, base + vs::clampi(ix, 0, A.w - 1));
-            p2 = ld(A, base + vs::clampi(ix + 1, 0, A.w - 1));
-            p3 = ld(A, base + vs::clampi(ix + 2, 0, A.w - 1));
-        }
-        H1[r] = lerp(p1, p2, a);
-        Dd[r] = lerp(p2, p3, a) - lerp(p0, p1, a);
+        for (int j = 0; j < 4; ++j) c[j] = active ? vs::clampi(ix - 1 + j, 0, A.w - 1) : OOB;
     }
 #pragma unroll
+    for (int r = 0; r < RMAX + 3; ++r) {
+        uint32_t p0, p1, p2, p3;
+        if constexpr (FAST) {
+            uint32_t w;
+            if constexpr (STAGED)
+                w = lds_word(sp + 8 * r, sh);
+            else
+                w = __builtin_amdgcn_raw_buffer_load_b32(A.rs, v0, r * A.pitch, 0);
+            p0 = w & 0xff;
+            p1 = (w >> 8) & 0xff;
+            p2 = (w >> 16) & 0xff;
+            p3 = w >> 24;
+        } else {
+            const int base = (int)__umul24((unsigned)vs::clampi(iy - 1 + r, 0, A.h - 1), (unsigned)A.pitch);
+            p0 = __builtin_amdgcn_raw_buffer_load_b8(A.rs, base + c[0], 0, 0);
+            p1 = __builtin_amdgcn_raw_buffer_load_b8(A.rs, base + c[1], 0, 0);
+            p2 = __builtin_amdgcn_raw_buffer_load_b8(A.rs, base + c[2], 0, 0);
+            p3 = __builtin_amdgcn_raw_buffer_load_b8(A.rs, base + c[3], 0, 0);
+        }
+        if (r == 0 || r == RMAX + 2)
+            row_terms<false>(p0, p1, p2, p3, a, H[r], D[r]);
+        else
+            row_terms<true>(p0, p1, p2, p3, a, H[r], D[r]);
+    }
+    float V[RMAX + 2];
+#pragma unroll
+    for (int r = 0; r < RMAX + 2; ++r) V[r] = lerp(H[r], H[r + 1], b);
+    if constexpr (STAGED) wave_lds_sync();   // the area is written again by the next staging
+#pragma unroll
     for (int k = 0; k < RMAX; ++k) {
-        // sample row k sits between rows k + 1 and k + 2
-        const float wgt = k < nrows ? 0.5f : 0.0f;   // zero weight outside the window
-        I[k] = lerp(H1[k + 1], H1[k + 2], b);
-        Ix[k] = wgt * lerp(Dd[k + 1], Dd[k + 2], b);
-        Iy[k] = wgt * lerp(H1[k + 2] - H1[k], H1[k + 3] - H1[k + 1], b);
+        I[k] = V[k + 1];
+        Ix[k] = lerp(D[k + 1], D[k + 2], b);
+        Iy[k] = V[k + 2] - V[k];
+        if constexpr (WEIGHTED) {
+            const float wgt = k < nrows ? 1.0f : 0.0f;
+            Ix[k] *= wgt;
+            Iy[k] *= wgt;
+        }
     }
 }
 
 template <int RMAX>
 __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* fb, const uint8_t* pb,
                           const vs::LevelDesc& d, const LKConst& c, float ux, float uy, float& vx, float& vy,
-                          uint32_t& n_setup, uint32_t& n_iter)
+                          uint32_t& n_setup, uint32_t& n_iter, float* red)
 {
     const int lane = threadIdx.x & 63;
     const int gcol = lane % c.cols, grp = lane / c.cols;
@@ -188,6 +354,8 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
     int nrows = c.hw - qy0 + 1;                          // rows of this lane inside the window
     nrows = active ? (nrows < c.rows ? nrows : c.rows) : 0;
     nrows = nrows < 0 ? 0 : nrows;
+    const int lane_off = grp * c.rows * 32 + gcol;       // the lane's first byte in a staged block
+    uint32_t* stage = reinterpret_cast<uint32_t*>(red);
 
     float gx = 0.f, gy = 0.f;
     bool ok = true;
@@ -200,21 +368,29 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
         const float a = cx - fx, b = cy - fy;
         const int ix = (int)fx + qx, iy = (int)fy + qy0;
 
-        // ---- window set-up: rows iy-1 .. iy+RMAX+1, columns ix-1 .. ix+2 of the previous frame. When
-        // every lane's block is inside the level, a row is one (unaligned) 32-bit load; otherwise four
-        // edge-clamped byte loads.
+        // ---- window set-up: rows iy-1 .. iy+RMAX+1, columns ix-1 .. ix+2 of the previous frame, the
+        // window's block starting at (fx - h - 1, fy - h - 1)
         const bool a_in = wave_all(!active || (ix - 1 >= 0 && ix + 2 <= A.w - 1 && iy - 1 >= 0 && iy + RMAX + 1 <= A.h - 1));
+        const int bx = (int)fx - c.hw - 1, by = (int)fy - c.hw - 1;
         float I[RMAX], Ix[RMAX], Iy[RMAX];
-        if (a_in)
-            window_samples<RMAX, true>(A, ix, iy, a, b, nrows, I, Ix, Iy);
-        else
-            window_samples<RMAX, false>(A, ix, iy, a, b, nrows, I, Ix, Iy);
+        if (c.full) {
+            if (a_in)
+                window_samples<RMAX, true, false>(A, ix, iy, bx, by, lane_off, a, b, nrows, active, stage, I, Ix, Iy);
+            else
+                window_samples<RMAX, false, false>(A, ix, iy, bx, by, lane_off, a, b, nrows, active, stage, I, Ix, Iy);
+        } else {
+            if (a_in)
+                window_samples<RMAX, true, true>(A, ix, iy, bx, by, lane_off, a, b, nrows, active, stage, I, Ix, Iy);
+            else
+                window_samples<RMAX, false, true>(A, ix, iy, bx, by, lane_off, a, b, nrows, active, stage, I, Ix, Iy);
+        }
         // the first iterate's next-frame block is read here, so its residual sums share the set-up's
-        // reduction: 3 tensor sums + 2 sums of I times the gradient + 8 residual sums in one
-        // transposing reduction
-        int cjx = (int)floorf(cx + gx), cjy = (int)floorf(cy + gy);
+        // reduction: 3 tensor sums + 2 sums of I times the gradient + 8 residual sums in one reduction
         float qa[RMAX + 1], qb[RMAX + 1];
-        load_next_block<RMAX>(B, cjx + qx, cjy + qy0, active, qa, qb);
+        {
+            const int jx0 = (int)floorf(cx + gx), jy0 = (int)floorf(cy + gy);
+            load_next_block<RMAX>(B, jx0 + qx, jy0 + qy0, jx0 - c.hw, jy0 - c.hw, lane_off, active, stage, qa, qb);
+        }
         float v[16];
         residual_partials<RMAX>(Ix, Iy, qa, qb, v + 5);
         v[0] = v[1] = v[2] = v[3] = v[4] = 0.f;
@@ -228,52 +404,56 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
         }
 #pragma unroll
         for (int j = 13; j < 16; ++j) v[j] = 0.f;
-        const float tot = vs::wave_transpose_sum<16>(v);
-        const float g11 = vs::transposed_total<16>(tot, 0), g12 = vs::transposed_total<16>(tot, 1);
-        const float g22 = vs::transposed_total<16>(tot, 2);
-        const float Sx = vs::transposed_total<16>(tot, 3), Sy = vs::transposed_total<16>(tot, 4);
+        float tot[13];
+        wave_sums<16, 13>(v, tot, red);
+        const float g11 = tot[0], g12 = tot[1], g22 = tot[2], Sx = tot[3], Sy = tot[4];
         float E[8];
-        e_from_sums(Sx, vs::transposed_total<16>(tot, 5), vs::transposed_total<16>(tot, 6),
-                    vs::transposed_total<16>(tot, 7), vs::transposed_total<16>(tot, 8), E);
-        e_from_sums(Sy, vs::transposed_total<16>(tot, 9), vs::transposed_total<16>(tot, 10),
-                    vs::transposed_total<16>(tot, 11), vs::transposed_total<16>(tot, 12), E + 4);
+        e_from_sums(Sx, tot[5], tot[6], tot[7], tot[8], E);
+        e_from_sums(Sy, tot[9], tot[10], tot[11], tot[12], E + 4);
         ++n_setup;
         const float tr = g11 + g22;
-        const float sq = sqrtf((g11 - g22) * (g11 - g22) + 4.0f * g12 * g12);
+        // hardware square root (about 1 ulp): the value only enters the eigenvalue test
+        const float sq = __builtin_amdgcn_sqrtf((g11 - g22) * (g11 - g22) + 4.0f * g12 * g12);
         const float lmax = 0.5f * (tr + sq);
         const float det = det2(g11, g22, g12);
-        const float lmin = lmax > 0.f ? det / lmax : 0.f;
         float nux = 0.f, nuy = 0.f;
-        if (!(lmin / (float)c.nwin >= c.min_eig)) {
+        // lambda_min = det / lambda_max, so lambda_min / N >= min_eig is det >= (N min_eig) lambda_max
+        // (no division). The tensor is 4 G and the residual sums 2 b (D = 2 grad I): the threshold
+        // carries the factor 4, and G^-1 b = 2 (4 G)^-1 (2 b).
+        const bool strong = uniform(lmax > 0.f ? det >= c.eig_thr * lmax : c.eig_thr <= 0.f);
+        if (!strong) {
             if (l == 0) ok = false;
         } else {
-            const float inv = __builtin_amdgcn_rcpf(det);
+            // step = (4 G)^-1 (2 b) * 2 = H b with H = 2 adj(4 G) / det(4 G), formed once per level
+            const float inv = 2.0f * __builtin_amdgcn_rcpf(det);
+            const float h11 = g11 * inv, h12 = g12 * inv, h22 = g22 * inv;
+            const float px0 = cx + gx, py0 = cy + gy;
+            float cfx = floorf(px0), cfy = floorf(py0);   // the integer position of the current sums
             for (int it = 0; it < c.max_iter; ++it) {
-                const float pxx = cx + gx + nux, pyy = cy + gy + nuy;
+                const float pxx = px0 + nux, pyy = py0 + nuy;
                 const float jfx = floorf(pxx), jfy = floorf(pyy);
-                const float ja = pxx - jfx, jb = pyy - jfy;
-                const int jx = (int)jfx, jy = (int)jfy;
-                if (jx != cjx || jy != cjy) {
+                if (uniform(jfx != cfx || jfy != cfy)) {
                     // the integer position moved: new block, new residual sums
-                    cjx = jx;
-                    cjy = jy;
-                    load_next_block<RMAX>(B, jx + qx, jy + qy0, active, qa, qb);
-                    float e[8];
+                    cfx = jfx;
+                    cfy = jfy;
+                    const int jx = (int)jfx, jy = (int)jfy;
+                    load_next_block<RMAX>(B, jx + qx, jy + qy0, jx - c.hw, jy - c.hw, lane_off, active, stage, qa, qb);
+                    float e[8], t8[8];
                     residual_partials<RMAX>(Ix, Iy, qa, qb, e);
-                    const float t8 = vs::wave_transpose_sum<8>(e);
-                    e_from_sums(Sx, vs::transposed_total<8>(t8, 0), vs::transposed_total<8>(t8, 1),
-                                vs::transposed_total<8>(t8, 2), vs::transposed_total<8>(t8, 3), E);
-                    e_from_sums(Sy, vs::transposed_total<8>(t8, 4), vs::transposed_total<8>(t8, 5),
-                                vs::transposed_total<8>(t8, 6), vs::transposed_total<8>(t8, 7), E + 4);
+                    wave_sums<8, 8>(e, t8, red);
+                    e_from_sums(Sx, t8[0], t8[1], t8[2], t8[3], E);
+                    e_from_sums(Sy, t8[4], t8[5], t8[6], t8[7], E + 4);
                 }
-                const float b1 = E[0] - fmaf(ja, fmaf(jb, E[3], E[1]), jb * E[2]);
-                const float b2 = E[4] - fmaf(ja, fmaf(jb, E[7], E[5]), jb * E[6]);
-                const float ex = (g22 * b1 - g12 * b2) * inv;
-                const float ey = (g11 * b2 - g12 * b1) * inv;
+                const float ja = pxx - jfx, jb = pyy - jfy;
+                // b = E0 - ja E1 - jb E2 - ja jb E3 = (E0 - jb E2) - ja (E1 + jb E3)
+                const float b1 = fmaf(-ja, fmaf(jb, E[3], E[1]), fmaf(-jb, E[2], E[0]));
+                const float b2 = fmaf(-ja, fmaf(jb, E[7], E[5]), fmaf(-jb, E[6], E[4]));
+                const float ex = fmaf(h22, b1, -(h12 * b2));
+                const float ey = fmaf(h11, b2, -(h12 * b1));
                 nux += ex;
                 nuy += ey;
                 ++n_iter;
-                if (ex * ex + ey * ey < c.eps2) break;
+                if (uniform(ex * ex + ey * ey < c.eps2)) break;
             }
         }
         if (l > 0) {
@@ -306,9 +486,16 @@ __global__ __launch_bounds__(256) void lk_kernel(const uint8_t* __restrict__ pre
     const int groups = (capacity + ppg - 1) / ppg;
     int item, group;
     if (!vs::xcd_map(blockIdx.x, n_items, groups, by_xcd != 0, item, group)) return;
-    const int slot = group * ppg + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
+    const int slot = group * ppg + wave;
     if (slot >= capacity) return;
     const int lane = threadIdx.x & 63;
+    extern __shared__ float lk_lds[];
+    float* red = lk_lds + wave * WAVE_LDS_FLOATS;
+    // the zero area read by lanes outside the window
+    red[RED_FLOATS + lane] = 0.f;
+    if (lane < ZERO_FLOATS - 64) red[RED_FLOATS + 64 + lane] = 0.f;
+    wave_lds_sync();
     const int64_t rec = (int64_t)item * istride;
     const int64_t k = rec * capacity + slot;
     const float ux = xy_prev[2 * k], uy = xy_prev[2 * k + 1];
@@ -321,10 +508,10 @@ __global__ __launch_bounds__(256) void lk_kernel(const uint8_t* __restrict__ pre
         const uint8_t* pa = prev_pyrs + item * pyr_stride;
         const uint8_t* fb_ = next_frames + item * frame_stride;
         const uint8_t* pb = next_pyrs + item * pyr_stride;
-        ok = track_one<RMAX>(fa, pa, fb_, pb, d, c, ux, uy, vx, vy, n_setup, n_iter);
+        ok = track_one<RMAX>(fa, pa, fb_, pb, d, c, ux, uy, vx, vy, n_setup, n_iter, red);
         if (ok && fb) {
             float bx = vx, by = vy;
-            const bool okb = track_one<RMAX>(fb_, pb, fa, pa, d, c, vx, vy, bx, by, n_setup, n_iter);
+            const bool okb = track_one<RMAX>(fb_, pb, fa, pa, d, c, vx, vy, bx, by, n_setup, n_iter, red);
             err = sqrtf((bx - ux) * (bx - ux) + (by - uy) * (by - uy));
             ok = okb && err <= fb_thresh;
         }
@@ -389,7 +576,8 @@ extern "C" int vs_track_lk(const uint8_t* prev_frames, const uint8_t* prev_pyrs,
     c.nwin = c.cols * c.cols;
     c.max_iter = p->max_iter;
     c.eps2 = p->eps * p->eps;
-    c.min_eig = p->min_eig;
+    c.full = c.groups * c.rows == c.cols && c.rows == (c.rows <= 7 ? 7 : 16);
+    c.eig_thr = (float)(4.0 * (double)p->min_eig * (double)c.nwin);
     hipStream_t s = vs::as_stream(stream);
     unsigned long long* wk = reinterpret_cast<unsigned long long*>(work);
     if (n_valid || wk) {
@@ -404,12 +592,13 @@ extern "C" int vs_track_lk(const uint8_t* prev_frames, const uint8_t* prev_pyrs,
     if (nblk > 0x7fffffff) return vs::set_error(VS_ERR_INVALID, "vs_track_lk: grid too large");
     const unsigned grid = (unsigned)nblk;
     const unsigned threads = 64u * (unsigned)ppg;
+    const size_t lds = sizeof(float) * WAVE_LDS_FLOATS * (size_t)ppg;
     if (c.rows <= 7)
-        lk_kernel<7><<<grid, threads, 0, s>>>(prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride,
+        lk_kernel<7><<<grid, threads, lds, s>>>(prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride,
                                          istride, d, xy_prev, alive_prev, capacity, c, p->fb, p->fb_thresh, xy_next,
                                          status, fb_err, n_valid, xy_chain, alive_chain, wk, n, by_xcd);
     else
-        lk_kernel<16><<<grid, threads, 0, s>>>(prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride,
+        lk_kernel<16><<<grid, threads, lds, s>>>(prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride,
                                           istride, d, xy_prev, alive_prev, capacity, c, p->fb, p->fb_thresh, xy_next,
                                           status, fb_err, n_valid, xy_chain, alive_chain, wk, n, by_xcd);
     return vs::check_launch("vs_track_lk");

@@ -100,53 +100,6 @@ __device__ __forceinline__ float wave_total(float v)
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
-// Transposing row sum of N = 8 or 16 values per lane. Each step pairs every lane with a partner that
-// differs in one lane bit (row_mirror: bit 3, row_half_mirror: bit 2, quad_perm [2,3,0,1]: bit 1,
-// quad_perm [1,0,3,2]: bit 0; each partner lies in the same half of the previous pairing); the lane
-// keeps one half of its values, adds the partner's copy of that half and hands over the other half.
-// On return lane L holds the sum over its 16-lane row of value (L & 15) for N = 16, or of value
-// ((L >> 1) & 7) for N = 8. wave_transpose_sum then adds the four rows, so every lane holds the
-// wave total of its value; value j is read as a uniform with transposed_total().
-template <int CTRL, int BIT, int M, int N>
-__device__ __forceinline__ void transpose_step(float (&v)[N], int lane)
-{
-    const bool up = (lane >> BIT) & 1;
-#pragma unroll
-    for (int j = 0; j < M / 2; ++j) {
-        const float lo = v[j], hi = v[j + M / 2];
-        const float send = up ? lo : hi, keep = up ? hi : lo;
-        v[j] = keep + dpp_mov<CTRL>(send);
-    }
-}
-
-template <int N>
-__device__ __forceinline__ float wave_transpose_sum(float (&v)[N])
-{
-    static_assert(N == 8 || N == 16, "8 or 16 values");
-    const int lane = threadIdx.x & 63;
-    transpose_step<0x140, 3, N>(v, lane);        // row_mirror
-    transpose_step<0x141, 2, N / 2>(v, lane);    // row_half_mirror
-    transpose_step<0x4E, 1, N / 4>(v, lane);     // quad_perm [2,3,0,1]
-    float t;
-    if constexpr (N == 16) {
-        transpose_step<0xB1, 0, 2>(v, lane);     // quad_perm [1,0,3,2]
-        t = v[0];
-    } else {
-        t = v[0] + dpp_mov<0xB1>(v[0]);
-    }
-    t += __shfl_xor(t, 16, 64);
-    t += __shfl_xor(t, 32, 64);
-    return t;
-}
-
-// uniform read of value j of a wave_transpose_sum<N> result
-template <int N>
-__device__ __forceinline__ float transposed_total(float t, int j)
-{
-    const int src = (N == 16) ? j : 2 * j;
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, t), src));
-}
-
 // Workgroup -> (item, tile) mapping of a one-dimensional grid. With `by_xcd`, the tiles of item i
 // all run on the same XCD (workgroups are dealt to the 8 XCDs round-robin, so workgroup b runs on
 // XCD b % 8): item i takes XCD i % 8 and its tiles are consecutive there, so neighbouring tiles
