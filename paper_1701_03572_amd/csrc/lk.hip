@@ -431,11 +431,16 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
             float cfx = floorf(px0), cfy = floorf(py0);   // the integer position of the current sums
             for (int it = 0; it < c.max_iter; ++it) {
                 const float pxx = px0 + nux, pyy = py0 + nuy;
-                const float jfx = floorf(pxx), jfy = floorf(pyy);
-                if (uniform(jfx != cfx || jfy != cfy)) {
+                float ja = pxx - cfx, jb = pyy - cfy;
+                // the iterate left its pixel unless both fractions lie in [0, 1): as unsigned integers
+                // the bit patterns of [0, 1) are exactly those below 1.0's (negatives carry the sign bit)
+                if (uniform(__float_as_uint(ja) >= 0x3f800000u || __float_as_uint(jb) >= 0x3f800000u)) {
                     // the integer position moved: new block, new residual sums
+                    const float jfx = floorf(pxx), jfy = floorf(pyy);
                     cfx = jfx;
                     cfy = jfy;
+                    ja = pxx - jfx;
+                    jb = pyy - jfy;
                     const int jx = (int)jfx, jy = (int)jfy;
                     load_next_block<RMAX>(B, jx + qx, jy + qy0, jx - c.hw, jy - c.hw, lane_off, active, stage, qa, qb);
                     float e[8], t8[8];
@@ -444,7 +449,6 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
                     e_from_sums(Sx, t8[0], t8[1], t8[2], t8[3], E);
                     e_from_sums(Sy, t8[4], t8[5], t8[6], t8[7], E + 4);
                 }
-                const float ja = pxx - jfx, jb = pyy - jfy;
                 // b = E0 - ja E1 - jb E2 - ja jb E3 = (E0 - jb E2) - ja (E1 + jb E3)
                 const float b1 = fmaf(-ja, fmaf(jb, E[3], E[1]), fmaf(-jb, E[2], E[0]));
                 const float b2 = fmaf(-ja, fmaf(jb, E[7], E[5]), fmaf(-jb, E[6], E[4]));
