@@ -57,7 +57,7 @@ struct HypRec {
     double pad;
 };
 static_assert(sizeof(HypRec) == 64, "hypothesis record");
-constexpr int MAX_SPLIT = 8;    // hypothesis workgroups per pair at most
+constexpr int MAX_SPLIT = 32;   // hypothesis workgroups per pair at most (one hypothesis per wave for 128)
 
 __host__ __device__ inline int64_t cap_aligned(int cap) { return ((int64_t)cap + 255) & ~(int64_t)255; }
 __host__ __device__ inline int64_t hyp_offset(int cap) { return 256 + N_SLOTS * cap_aligned(cap); }
@@ -514,20 +514,26 @@ __global__ __launch_bounds__(NT, 3) void fit_pair_kernel(const float* __restrict
         const bool affine = model == VS_AFFINE;
         bool have = false;
         if (a.iters > 0 && (!affine || n >= 3)) {
-            // the best of the hypothesis workgroups' bests: most inliers, then the smallest h
-            if (t == 0) {
-                int bs = -1;
-                for (int q = 0; q < split; ++q) {
-                    const HypRec& r = hyp[q * N_SLOTS + slot_of_model(model)];
-                    if (r.h < 0) continue;
-                    if (bs < 0 || r.score > hyp[bs * N_SLOTS + slot_of_model(model)].score ||
-                        (r.score == hyp[bs * N_SLOTS + slot_of_model(model)].score &&
-                         r.h < hyp[bs * N_SLOTS + slot_of_model(model)].h))
-                        bs = q;
+            // the best of the hypothesis workgroups' bests: most inliers, then the smallest h. Wave 0
+            // reads one record per lane and takes the maximum of the key (score + 1, ~h); records
+            // without a hypothesis (h < 0) have key 0. Hypothesis indices are distinct, so the
+            // maximum is unique.
+            if (t < 64) {
+                uint64_t key = 0;
+                if (t < split) {
+                    const HypRec& r = hyp[t * N_SLOTS + slot_of_model(model)];
+                    if (r.h >= 0)
+                        key = ((uint64_t)(uint32_t)(r.score + 1) << 32) | (uint64_t)(0xffffffffu - (uint32_t)r.h);
                 }
-                if (bs >= 0)
-                    for (int k = 0; k < 6; ++k) w_model[0][k] = hyp[bs * N_SLOTS + slot_of_model(model)].p[k];
-                s_best_h = bs < 0 ? -1 : 0;
+                uint64_t m = key;
+#pragma unroll
+                for (int d = 32; d >= 1; d >>= 1) {
+                    const uint64_t o = __shfl_xor(m, d, 64);
+                    m = o > m ? o : m;
+                }
+                if (m != 0 && key == m)
+                    for (int k = 0; k < 6; ++k) w_model[0][k] = hyp[t * N_SLOTS + slot_of_model(model)].p[k];
+                if (t == 0) s_best_h = m == 0 ? -1 : 0;
             }
             __syncthreads();
             const int bw = s_best_h;
