@@ -420,7 +420,7 @@ __device__ __forceinline__ int model_of(int mode, int mi)
     return !hybrid ? mode : mi == 0 ? VS_RIGID : mi == 1 ? VS_SIMILARITY : VS_AFFINE;
 }
 
-__device__ __forceinline__ int models_in(int mode) { return mode == VS_HYBRID3 ? 3 : mode == VS_HYBRID ? 2 : 1; }
+__host__ __device__ __forceinline__ int models_in(int mode) { return mode == VS_HYBRID3 ? 3 : mode == VS_HYBRID ? 2 : 1; }
 
 // Kernel 1a (fit_hyp): workgroup (pair, s) of `split` per pair scores the hypotheses h = s, s + split,
 // ... of every requested model (wave w takes h = s + split (w + 4k)) and records its best in the
@@ -491,26 +491,26 @@ __global__ __launch_bounds__(NT, 3) void fit_pair_kernel(const float* __restrict
     __shared__ double s_out[6], s_tmp[4];
     __shared__ int s_best_h, s_ninl, s_flag;
 
-    const int item = blockIdx.x, t = threadIdx.x;
+    // one workgroup per (pair, model): the hybrid's candidates are fitted side by side
+    const int n_models = models_in(a.model);
+    const int item = blockIdx.x / n_models, mi = blockIdx.x - item * n_models, t = threadIdx.x;
     PairRec* rec = reinterpret_cast<PairRec*>(ws + item * rec_bytes(capacity));
     uint8_t* masks = ws + item * rec_bytes(capacity) + 256;
     const int64_t base = (int64_t)item * capacity;
+    const int model = model_of(a.model, mi);
 
     const int n = compact_valid(src, dst, valid, base, capacity, xs, ys, xd, yd, slot_of, red4);
     const HypRec* hyp = reinterpret_cast<const HypRec*>(ws + item * rec_bytes(capacity) + hyp_offset(capacity));
-    for (int k = t; k < N_SLOTS * cap_aligned(capacity); k += NT) masks[k] = 0;
+    uint8_t* mk = masks + slot_of_model(model) * cap_aligned(capacity);
+    for (int k = t; k < cap_aligned(capacity); k += NT) mk[k] = 0;
     __syncthreads();
-    if (t == 0) {
+    if (t == 0 && mi == 0) {
         rec->n_valid = n;
         rec->skipped = (n < a.min_valid || n < 2) ? 1 : 0;
     }
     if (n < a.min_valid || n < 2) return;
 
-    // models to fit: one, or the hybrid's two or three candidates
-    const bool hybrid = a.model == VS_HYBRID || a.model == VS_HYBRID3;
-    const int n_models = a.model == VS_HYBRID3 ? 3 : a.model == VS_HYBRID ? 2 : 1;
-    for (int mi = 0; mi < n_models; ++mi) {
-        const int model = !hybrid ? a.model : mi == 0 ? VS_RIGID : mi == 1 ? VS_SIMILARITY : VS_AFFINE;
+    {
         const bool affine = model == VS_AFFINE;
         bool have = false;
         if (a.iters > 0 && (!affine || n >= 3)) {
@@ -578,9 +578,7 @@ __global__ __launch_bounds__(NT, 3) void fit_pair_kernel(const float* __restrict
             mf.err = sqrt(e[0] / n);
             mf.n_inl = s_ninl;
         }
-        uint8_t* mk = masks + slot * cap_aligned(capacity);
         for (int i = t; i < n; i += NT) mk[slot_of[i]] = inl[i];
-        __syncthreads();
     }
 }
 
@@ -805,7 +803,7 @@ extern "C" int vs_fit_motion(const float* src, const float* dst, const uint8_t* 
     fit_hyp_kernel<<<n * split, NT, lds, s>>>(src, dst, valid, capacity, a, pair_index0, split, w8);
     int e0 = vs::check_launch("vs_fit_motion(hypotheses)");
     if (e0) return e0;
-    fit_pair_kernel<<<n, NT, lds, s>>>(src, dst, valid, capacity, a, pair_index0, split, w8);
+    fit_pair_kernel<<<n * models_in(a.model), NT, lds, s>>>(src, dst, valid, capacity, a, pair_index0, split, w8);
     int e = vs::check_launch("vs_fit_motion(pairs)");
     if (e) return e;
     fit_resolve_kernel<<<1, NT, 0, s>>>(n, capacity, a, pair_index0, state, w8);
