@@ -360,15 +360,16 @@ def main() -> int:
         torch.cuda.synchronize()
         plain_ms = e0.elapsed_time(e1)
         plain_fps = n / (plain_ms / 1e3)
-        # per-frame compute latency: each frame processed on arrival with an idle GPU
+        # per-frame compute latency: each frame processed on arrival with an idle GPU, until the
+        # outputs of its push are written (the push's ready event; the corner detection for the
+        # next pair follows it)
         st.reset()
         lat = []
         for j in range(n):
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record()
-            st.push(frames[j])
-            b.record()
+            st.push(frames[j], ready=b)
             torch.cuda.synchronize()
             lat.append(a.elapsed_time(b))
         st.flush()

@@ -316,7 +316,9 @@ int vs_photometric_refine(const uint8_t* prev, const uint8_t* next, int64_t fram
  * the skip rule (Section 4), the optional photometric refinement, the re-detection (every
  * redetect_every frames, and on the device after a pair with fewer than min_valid points), the
  * smoother's step with the sliding parameter store (Sections 5.1, 6) and the warps of the frames
- * it emits (Section 5). The result equals the whole-sequence path's, frame for frame.
+ * it emits (Section 5). The result equals the whole-sequence path's, frame for frame. The corners
+ * detected on a frame serve only the next pair, so a push enqueues that detection last, after the
+ * warps of the frames it emits (and after recording ready_event).
  * The caller sets the geometry, parameters and device buffers below, keeps the struct (host
  * memory) and every buffer alive while the stream runs, and keeps each pushed frame (device,
  * width x height, pitch = width) unchanged until it has been emitted. vs_stream_reset starts a new
@@ -370,6 +372,9 @@ typedef struct {
     void* photo_ws;            /* vs_photometric_workspace(1) bytes, when photo_steps > 0 */
     size_t photo_ws_bytes;
     uint8_t* out;              /* [out_slots][height][width] */
+    void* ready_event;         /* optional hipEvent_t (NULL: none), recorded on `stream` by every
+                                  push once the frames it emits are written, before the re-detection
+                                  that only serves the next pair */
     /* progress, maintained by the library */
     int64_t next_frame;        /* index of the next pushed frame */
     int64_t emitted;           /* frames emitted so far */

@@ -2,10 +2,11 @@
 // launch of one frame through the library's own entry points, with the frame's indices and ring
 // positions computed on the host, so a frame costs one call into the library instead of one per
 // stage. The sequence of operations is the streaming pipeline's:
-//   pyramid(j); j = 0: detect(j), smoother start; j > 0: track(j - 1 -> j) with the backward
-//   check and chaining, fit(pair j - 1), optional photometric refinement, detect(j) (every
-//   redetect_every frames, else gated on the device by the pair's valid count), smoother step;
-//   then the warps of the frames the smoother emits.
+//   pyramid(j); j = 0: smoother start; j > 0: track(j - 1 -> j) with the backward check and
+//   chaining, fit(pair j - 1), optional photometric refinement, smoother step; then the warps of
+//   the frames the smoother emits, the caller's ready event, and last detect(j) (every
+//   redetect_every frames and for j = 0, else gated on the device by the pair's valid count):
+//   its corners serve only the pair (j, j + 1), so the frame's outputs need not wait for it.
 #include <cstddef>
 
 #include "vs_common.hpp"
@@ -81,7 +82,6 @@ extern "C" int vs_stream_push(vs_stream* s, const uint8_t* frame, int64_t* first
     if ((rc = vs_build_pyramid(frame, 0, pyr_cur, 0, 1, &s->layout, st))) return rc;
     s->frames[j % ring] = frame;
     if (j == 0) {
-        if ((rc = detect(s, frame, cur, false, st))) return rc;
         if ((rc = vs_smooth_trajectory(nullptr, 0, 0, &s->smooth, s->traj_state, s->mats, ring, s->n_emitted,
                                        s->first_frame, st)))
             return rc;
@@ -106,7 +106,6 @@ extern "C" int vs_stream_push(vs_stream* s, const uint8_t* frame, int64_t* first
                                             s->photo_ws_bytes, st)))
                 return rc;
         }
-        if ((rc = detect(s, frame, cur, j % s->redetect_every != 0, st))) return rc;
         if ((rc = vs_smooth_trajectory(s->pair_params, 1, 0, &s->smooth, s->traj_state, s->mats, ring, s->n_emitted,
                                        s->first_frame, st)))
             return rc;
@@ -115,7 +114,10 @@ extern "C" int vs_stream_push(vs_stream* s, const uint8_t* frame, int64_t* first
     const int lag = lag_of(s);
     int64_t end = lag ? s->next_frame - lag : s->next_frame;
     if (end < s->emitted) end = s->emitted;
-    return emit(s, end, first_emitted, n_emitted, st);
+    if ((rc = emit(s, end, first_emitted, n_emitted, st))) return rc;
+    if (s->ready_event && hipEventRecord(static_cast<hipEvent_t>(s->ready_event), st) != hipSuccess)
+        return vs::set_error(VS_ERR_HIP, "vs_stream_push: hipEventRecord failed");
+    return detect(s, frame, cur, j != 0 && j % s->redetect_every != 0, st);
 }
 
 extern "C" int vs_stream_flush(vs_stream* s, int64_t* first_emitted, int32_t* n_emitted, void* stream)

@@ -193,7 +193,9 @@ class Stabilizer:
     """Plain per-frame streaming path. ``push`` enqueues all work for one frame on the current
     stream through one native call (``vs_stream_push``) and returns the indices and output views of
     the frames it emits (the outputs are complete once the stream reaches this point). Pushed
-    frames must stay unchanged until they are emitted; no frame is copied."""
+    frames must stay unchanged until they are emitted; no frame is copied. The corner detection
+    that serves the next pair is enqueued after the emitted frames' warps; a ``ready`` event given
+    to ``push`` is recorded between the two, when the call's outputs are written."""
 
     def __init__(self, width: int, height: int, P: StabParams, device="cuda", out_slots: int | None = None):
         self.W, self.H, self.P = width, height, P
@@ -257,10 +259,16 @@ class Stabilizer:
             del self.frames[e]
         return out
 
-    def push(self, frame: torch.Tensor) -> list:
+    def push(self, frame: torch.Tensor, ready: torch.cuda.Event | None = None) -> list:
         assert frame.is_cuda and frame.dtype == torch.uint8 and frame.shape == (self.H, self.W)
         assert frame.is_contiguous()
         self.frames[self.j] = frame
+        handle = 0
+        if ready is not None:
+            if not ready.cuda_event:
+                ready.record()          # creates the event; the push records it again
+            handle = ready.cuda_event
+        self._s.ready_event = handle
         first, n = V.vs_stream_push(self._s, frame)
         self.j += 1
         return self._collect(first, n)

@@ -72,15 +72,16 @@ class StreamServer:
         self.streams[sid] = st
         return True
 
-    def submit(self, sid, frame_host: torch.Tensor) -> list:
+    def submit(self, sid, frame_host: torch.Tensor, ready: torch.cuda.Event | None = None) -> list:
         """Copy one arriving frame (host, uint8 [H, W]) to the device and enqueue its processing.
-        Returns (frame index, output view) for the frames this push emits."""
+        Returns (frame index, output view) for the frames this push emits; ``ready`` (optional) is
+        recorded on the stream's queue once they are written."""
         st = self.streams[sid]
         with torch.cuda.stream(st.queue):
             slot = st.ring[st.pushed % st.ring.shape[0]]
             slot.copy_(frame_host, non_blocking=True)
             st.pushed += 1
-            return st.stab.push(slot)
+            return st.stab.push(slot, ready=ready)
 
     def close(self, sid) -> list:
         """End a stream: emit what is left, release its memory and admit queued streams that now fit."""
@@ -168,12 +169,13 @@ def simulate(server: StreamServer, workload: list, pools: list, paced: bool) -> 
         pool = pools[s.clip]
         frame = pool[(s.offset + j) % pool.shape[0]]
         queue = server.streams[s.sid].queue
-        emitted = server.submit(s.sid, frame)
+        ev = torch.cuda.Event(enable_timing=True)
+        emitted = server.submit(s.sid, frame, ready=ev)   # recorded on the queue after the push's warps
         if kind == 1:
             emitted += server.close(s.sid)
-        if emitted:
             ev = torch.cuda.Event(enable_timing=True)
-            ev.record(queue)                          # on the stream's own queue, after its warps
+            ev.record(queue)                          # after the flush's warps too
+        if emitted:
             done.append((t, ev, len(emitted)))
             n_out += len(emitted)
     for q in server.queues:

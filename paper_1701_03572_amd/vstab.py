@@ -89,7 +89,7 @@ class vs_stream(C.Structure):
                 ("affine6", C.c_void_p), ("info", C.c_void_p), ("inliers", C.c_void_p), ("traj_state", C.c_void_p),
                 ("mats", C.c_void_p), ("n_emitted", C.c_void_p), ("first_frame", C.c_void_p),
                 ("photo_loss", C.c_void_p), ("photo_accepted", C.c_void_p), ("photo_ws", C.c_void_p),
-                ("photo_ws_bytes", C.c_size_t), ("out", C.c_void_p), ("next_frame", C.c_int64),
+                ("photo_ws_bytes", C.c_size_t), ("out", C.c_void_p), ("ready_event", C.c_void_p), ("next_frame", C.c_int64),
                 ("emitted", C.c_int64), ("frames", C.c_void_p * VS_STREAM_MAX_FRAMES)]
 
 
