@@ -798,8 +798,9 @@ extern "C" int vs_fit_motion(const float* src, const float* dst, const uint8_t* 
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (he != hipSuccess) return vs::set_error(VS_ERR_HIP, "vs_fit_motion: %s", hipGetErrorString(he));
     }
-    // few pairs: spread each pair's hypotheses over up to MAX_SPLIT workgroups
-    const int split = a.iters > 0 ? std::min(std::max((512 + n - 1) / n, 1), MAX_SPLIT) : 1;
+    // spread each pair's hypotheses over workgroups until about 2048 are in flight (up to MAX_SPLIT
+    // per pair): the scoring loops are chains of dependent FP64 operations, hidden only by other waves
+    const int split = a.iters > 0 ? std::min(std::max((2048 + n - 1) / n, 1), MAX_SPLIT) : 1;
     fit_hyp_kernel<<<n * split, NT, lds, s>>>(src, dst, valid, capacity, a, pair_index0, split, w8);
     int e0 = vs::check_launch("vs_fit_motion(hypotheses)");
     if (e0) return e0;
