@@ -1,31 +1,34 @@
-// track_lk: pyramidal Lucas-Kanade with the forward-backward check, one wave64 (one workgroup)
-// per point slot.
+// track_lk: pyramidal Lucas-Kanade with the forward-backward check, one wave64 per point slot.
 //
 // Lane layout for a (2h+1)^2 window: the window's 2h+1 columns are spread over the lanes and the
 // rows over G = 64 / (2h+1) lane groups, each group owning R = ceil((2h+1) / G) consecutive rows
-// (h = 10: 21 columns x 3 groups of 7 rows = 63 lanes). Lanes outside every group read out of their
-// buffer's range, which returns zeros, so all their terms vanish; when the window's rows do not
-// fill every group's R rows, the samples past the window get zero gradient weight. Every lane runs
-// the same branch-free loops. All samples of a window share one fractional offset, so per level a
-// lane reads its (R+3) x 4 previous-frame block once (one unaligned 32-bit load per row when the
-// whole window is inside the level, edge-clamped byte loads otherwise; row offsets go in the scalar
-// offset of the buffer load), interpolates each row horizontally first and derives I and the two
-// central differences of its R samples into registers. The differences are kept without their
-// factor 1/2 (D = 2 grad I): the tensor then carries a factor 4 and the residual sums a factor 2,
-// both exact powers of two, which the minimum-eigenvalue test and the step solve absorb.
+// (h = 10: 21 columns x 3 groups of 7 rows = 63 lanes). Lanes outside every group read zeros (an
+// out-of-range buffer offset, or a zeroed LDS area), so all their terms vanish; when the window's
+// rows do not fill every group's R rows, the samples past the window get zero gradient weight.
+// Every lane runs the same branch-free loops. All samples of a window share one fractional offset,
+// so per level a lane reads its (R+3) x 4 previous-frame block once, interpolates each row
+// horizontally first and derives I and the two central differences of its R samples into
+// registers. When the whole window is inside the level and R <= 7, the window's block (24 rows of
+// 32 bytes) is staged in the wave's LDS by one 16-byte load per lane pair and each lane reads its
+// rows there as two aligned words; a wave64 buffer load occupies the texture address unit for
+// about the same time whatever its width, so this replaces 10 row loads per set-up. Larger windows
+// load one unaligned 32-bit word per row; windows at the level's edge take edge-clamped byte loads.
+// The differences are kept without their factor 1/2 (D = 2 grad I): the tensor then carries a
+// factor 4 and the residual sums a factor 2, both exact powers of two, which the minimum-eigenvalue
+// test and the step solve absorb.
 //
 // Gauss-Newton iterations: all samples also share the iterate's fractional offset (ja, jb), so the
 // residual sum over the window, sum (I - J) grad I, is E0 - ja E1 - jb E2 - ja jb E3 with four sums
 // per gradient component that depend only on the iterate's integer position (the bilinear form of
 // the next-frame 2 x 2 blocks; see residual_partials). They are recomputed, from the lane's (R+1) x 2
-// next-frame block, only when the integer position moves; an iteration that stays on the same
-// pixel costs a few wave-uniform operations. The lanes accumulate plain sums of products of raw
-// next-frame pixels with the gradients (no per-sample differences), and the E sums are formed from
-// the reduced totals. The first block of each level is read with the set-up, and its eight sums
-// share the set-up's reduction with the three tensor sums and the two sums of I times the gradient.
-// Reductions are transposing (lane-swap and DPP steps), so several sums cost little more than one;
-// the totals are read as uniforms, and the iteration control is wave-uniform. One wave per
-// workgroup lets every point retire independently.
+// next-frame block (staged like the previous-frame block), only when the integer position moves;
+// an iteration that stays on the same pixel costs a few wave-uniform operations. The lanes
+// accumulate plain sums of products of raw next-frame pixels with the gradients (no per-sample
+// differences), and the E sums are formed from the totals. The first block of each level is read
+// with the set-up, and its eight sums share the set-up's reduction with the three tensor sums and
+// the two sums of I times the gradient. The sums are reduced through LDS (a transposed store,
+// chunk sums, totals read back by every lane), which costs only additions on the vector ALU; the
+// iteration control is wave-uniform. One wave per point lets every point retire independently.
 #include "vs_common.hpp"
 
 namespace {
@@ -272,9 +275,9 @@ __device__ __forceinline__ void row_terms(uint32_t p0, uint32_t p1, uint32_t p2,
 // and columns ix-1 .. ix+2 are read. With FAST (every lane's block inside the level) and at most 7
 // rows per lane, the window's 24-row block (origin (bx, by), 4-byte aligned left edge) is staged in
 // LDS with one load and the lane's rows start at byte lane_off of it; with FAST and larger windows,
-// one unaligned 32-bit load per row; otherwise four edge-clamped byte loads. Rows are interpolated horizontally
-// first; V(r) = lerp(H(r), H(r+1), b) gives I = V(k+1) and Dy = V(k+2) - V(k), and Dx interpolates
-// the rows' D vertically. With WEIGHTED, rows k >= nrows get Dx = Dy = 0.
+// one unaligned 32-bit load per row; otherwise four edge-clamped byte loads. Rows are interpolated
+// horizontally first; V(r) = lerp(H(r), H(r+1), b) gives I = V(k+1) and Dy = V(k+2) - V(k), and Dx
+// interpolates the rows' D vertically. With WEIGHTED, rows k >= nrows get Dx = Dy = 0.
 template <int RMAX, bool FAST, bool WEIGHTED>
 __device__ __forceinline__ void window_samples(const Img& A, int ix, int iy, int bx, int by, int lane_off, float a,
                                                float b, int nrows, bool active, uint32_t* stage, float (&I)[RMAX],
