@@ -111,7 +111,7 @@ def test_hd_pair_full_size():
     assert r["excluded"] <= 0.05 * len(pts)
 
 
-@pytest.mark.parametrize("hw", [3, 7, 15])
+@pytest.mark.parametrize("hw", [1, 3, 5, 7, 11, 15])
 def test_other_window_sizes(hw):
     say("lk window", hw)
     seq = synth.make_sequence("tiny", n_frames=2)
