@@ -110,17 +110,23 @@ __device__ __forceinline__ double exact_key(int32_t A, int32_t B, int32_t C)
     return __ddiv_rn(2.0 * det, __dadd_rn(tr, __dsqrt_rn(disc)));
 }
 
-// FP32 estimate of the same score, relative error below 5e-7 (each of the roughly ten rounded
-// steps contributes at most one or two units of 2^-24); 0 exactly when det == 0.
+// FP32 estimate of the same score. A, B and C are integers below 2^24 in magnitude, so they are
+// exact floats. det comes from Kahan's compensated 2x2 determinant (relative error at most 2u,
+// u = 2^-24, hence the exact sign, and 0 exactly when det == 0); disc = (A - C)^2 + 4 fl(B^2) is one
+// fused rounding over non-negative terms (A - C is exact); with the sum A + C, the square root and
+// the reciprocal (each within one ulp) and the final product the relative error stays below 10u
+// (6e-7).
 __device__ __forceinline__ float approx_key(int32_t A, int32_t B, int32_t C)
 {
-    const double a = (double)A, b = (double)B, c = (double)C;
-    const double det = a * c - b * b;
-    if (!(det > 0.0)) return 0.0f;
-    const double dm = a - c;
-    const double disc = dm * dm + 4.0 * (b * b);
-    const float sf = __builtin_amdgcn_sqrtf((float)disc);
-    return 2.0f * (float)det * __builtin_amdgcn_rcpf((float)(a + c) + sf);
+    const float a = (float)A, b = (float)B, c = (float)C;
+    const float w = b * b;
+    const float e = fmaf(-b, b, w);        // w - b^2, exactly
+    const float det = fmaf(a, c, -w) + e;
+    if (!(det > 0.0f)) return 0.0f;
+    const float dm = a - c;
+    const float disc = fmaf(dm, dm, 4.0f * w);
+    const float sf = __builtin_amdgcn_sqrtf(disc);
+    return 2.0f * det * __builtin_amdgcn_rcpf((a + c) + sf);
 }
 
 // half-width of the band inside which two FP32 estimates are compared exactly
