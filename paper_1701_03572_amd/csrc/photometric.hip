@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void photo_sums_kernel(const uint8_t* __restri
         }
     }
     __syncthreads();
-    if (threadIdx.x < nk) {
+    if ((int)threadIdx.x < nk) {
         const int k = threadIdx.x;
         const double t = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
         atomicAdd(&out[k], t);

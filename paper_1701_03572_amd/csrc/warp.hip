@@ -56,7 +56,8 @@ __device__ __forceinline__ Box corner_box(float f00, float f01, float c0, float 
     return b;
 }
 
-__global__ __launch_bounds__(256, 8) void warp_kernel(const uint8_t* __restrict__ src, int64_t src_stride, int W, int H,
+// 5 workgroups per CU: the LDS tile (96 rows of 288 bytes) allows no more
+__global__ __launch_bounds__(256, 5) void warp_kernel(const uint8_t* __restrict__ src, int64_t src_stride, int W, int H,
                                                       int src_pitch, const double* __restrict__ mats, int64_t mat_stride,
                                                       uint8_t* __restrict__ dst, int64_t dst_stride, int dst_pitch,
                                                       int border, int tiles_x, int tiles_y, int vec_ok, int n_items,
