@@ -2,7 +2,6 @@
 (each frame is the previous one moved by a known similarity), following the paper's
 motion-estimation workflow (Section 4.1) and motion compensation (Section 5.1)."""
 import numpy as np
-import pytest
 
 from oracle import oracle as O
 from paper_1701_03572_amd import params, synth
