@@ -73,7 +73,7 @@ def lib():
         _lib.vso_detect.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int,
                                     P, P, P]
         _lib.vso_detect.restype = C.c_int
-        _lib.vso_track_lk.argtypes = [P, P, P, P, P, C.c_int, P, C.c_int, P, C.POINTER(LKParams), P, P, P, P]
+        _lib.vso_track_lk.argtypes = [P, P, P, P, P, C.c_int, P, C.c_int, P, C.POINTER(LKParams), P, P, P, P, P]
         _lib.vso_draw.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int, C.c_int]
         _lib.vso_draw.restype = C.c_uint64
         _lib.vso_draw3.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int, C.c_int]
@@ -170,8 +170,10 @@ def detect(img: np.ndarray, K: int, quality: float = 0.01, min_dist: int = 10, r
 # ---------------------------------------------------------------------------------------------
 
 def track_lk(prev_pyr: list, next_pyr: list, pts: np.ndarray, alive=None, win_half=10, max_iter=30, eps=1e-3,
-             min_eig=1e-2, fb=True, fb_thresh=1.0):
-    """Returns (xy_next [n,2], status [n] uint8, fb_err [n], iters [n,2])."""
+             min_eig=1e-2, fb=True, fb_thresh=1.0, with_margin: bool = False):
+    """Returns (xy_next [n,2], status [n] uint8, fb_err [n], iters [n,2]), plus eig_margin [n] when
+    ``with_margin``: the smallest |lambda_min / window size - min_eig| / min_eig over every level of
+    both passes (how close the point came to the eigenvalue test's threshold)."""
     L = len(prev_pyr)
     pv = [_u8(a) for a in prev_pyr]
     nx = [_u8(a) for a in next_pyr]
@@ -187,8 +189,11 @@ def track_lk(prev_pyr: list, next_pyr: list, pts: np.ndarray, alive=None, win_ha
     st = np.empty(n, np.uint8)
     fe = np.empty(n, np.float64)
     it = np.empty((n, 2), np.int32)
+    mg = np.empty(n, np.float64)
     lib().vso_track_lk(pp, npp, _p(lw), _p(lh), _p(lw), L, _p(pts), n, None if al is None else _p(al),
-                       C.byref(prm), _p(out), _p(st), _p(fe), _p(it))
+                       C.byref(prm), _p(out), _p(st), _p(fe), _p(it), _p(mg))
+    if with_margin:
+        return out, st, fe, it, mg
     return out, st, fe, it
 
 
@@ -343,9 +348,44 @@ def photo_refine(f0: np.ndarray, f1: np.ndarray, theta0, omega, max_steps: int =
 # whole sequence
 # ---------------------------------------------------------------------------------------------
 
-def stabilize(frames: np.ndarray, P, warp_frames: bool = True, max_pairs: int | None = None) -> dict:
+def _segment_tracks(frames: np.ndarray, P, roi, first: int, last: int) -> list:
+    """Detection and tracking of frames first..last (first a re-detection frame, last the next one or
+    the final frame): detect on ``first``, track pair by pair, chain the tracked points, and re-detect
+    after a pair with fewer than min_valid valid points (the fit skips such a pair). Returns one
+    record per pair plus the detections made, exactly as the whole-sequence loop makes them."""
+    recs = []
+    pyr_prev = pyramid(frames[first], P.levels)
+    pts, _, _ = detect(frames[first], P.max_corners, P.quality, P.min_dist, roi)
+    alive = np.ones(len(pts), np.uint8)
+    dets = {first: pts.copy()}
+    for j in range(first + 1, last + 1):
+        pyr_next = pyramid(frames[j], P.levels)
+        nxt, status, fb_err, iters = track_lk(pyr_prev, pyr_next, pts, alive, P.win_half, P.max_iter, P.eps,
+                                              P.min_eig, P.fb, P.fb_thresh)
+        recs.append({"src": pts.copy(), "dst": nxt, "status": status, "fb_err": fb_err, "iters": iters})
+        if j == last:
+            break
+        if j % P.redetect_every == 0 or int(status.sum()) < P.min_valid:
+            pts, _, _ = detect(frames[j], P.max_corners, P.quality, P.min_dist, roi)
+            alive = np.ones(len(pts), np.uint8)
+            dets[j] = pts.copy()
+        else:
+            pts, alive = nxt, status
+        pyr_prev = pyr_next
+    return recs, dets
+
+
+def stabilize(frames: np.ndarray, P, warp_frames: bool = True, max_pairs: int | None = None, workers: int = 1) -> dict:
     """Run the whole path on uint8 frames [n, H, W] with parameters ``P`` (attributes as in the
-    package's StabParams; read by name only). Returns every intermediate the tests compare."""
+    package's StabParams; read by name only). Returns every intermediate the tests compare.
+
+    workers > 1 runs the detection and tracking of the re-detection segments in that many threads
+    (the C calls release the interpreter lock) and the warps likewise; the fits, the refinement and the
+    smoothing stay in pair order. Segments are independent: every segment starts from a fresh
+    detection, and a skipped pair (fewer than min_valid valid points) forces a re-detection inside its
+    own segment, decided by the tracking alone. The results are identical to workers = 1 (tested)."""
+    if workers > 1:
+        return _stabilize_threaded(frames, P, warp_frames, max_pairs, workers)
     n, H, W = frames.shape
     n_pairs = n - 1 if max_pairs is None else min(n - 1, max_pairs)
     n_used = n_pairs + 1
@@ -363,13 +403,7 @@ def stabilize(frames: np.ndarray, P, warp_frames: bool = True, max_pairs: int | 
         nxt, status, fb_err, iters = track_lk(pyr_prev, pyr_next, pts, alive, P.win_half, P.max_iter, P.eps,
                                               P.min_eig, P.fb, P.fb_thresh)
         prm, info, inl = fit_pair(pts, nxt, status, fp, j - 1, st)
-        steps = getattr(P, "photometric_steps", 0)
-        if steps > 0 and not info["skipped"]:
-            # optional photometric refinement of the fitted similarity (O-7), in its (a, b, tx, ty) form
-            m = P.photometric_margin if getattr(P, "photometric_margin", None) is not None else max(16, min(W, H) // 10)
-            th, _, _ = photo_refine(frames[j - 1], frames[j], theta_from_fit(prm, W, H), (m, m, W - m, H - m), steps)
-            rho = photo_frame(W, H)[2]
-            prm = np.array([1.0 + th[0] / rho, th[1] / rho, th[2], th[3]])
+        prm = _refined(frames, P, j, prm, info, W, H)
         out["pair_params"][j - 1] = prm
         out["info"].append(info)
         out["tracks"].append({"src": pts.copy(), "dst": nxt, "status": status, "fb_err": fb_err, "iters": iters,
@@ -386,4 +420,52 @@ def stabilize(frames: np.ndarray, P, warp_frames: bool = True, max_pairs: int | 
     out.update(traj=traj, smoothed=sm, mats=mats, detect_frames=detect_frames)
     if warp_frames:
         out["warped"] = np.stack([warp(frames[j], mats[j], P.border) for j in range(n_used)])
+    return out
+
+
+def _refined(frames, P, j, prm, info, W, H):
+    """Optional photometric refinement of the fitted similarity of pair j-1 -> j (O-7), in its
+    (a, b, tx, ty) form; skipped pairs stay as they are."""
+    steps = getattr(P, "photometric_steps", 0)
+    if steps <= 0 or info["skipped"]:
+        return prm
+    m = P.photometric_margin if getattr(P, "photometric_margin", None) is not None else max(16, min(W, H) // 10)
+    th, _, _ = photo_refine(frames[j - 1], frames[j], theta_from_fit(prm, W, H), (m, m, W - m, H - m), steps)
+    rho = photo_frame(W, H)[2]
+    return np.array([1.0 + th[0] / rho, th[1] / rho, th[2], th[3]])
+
+
+def _stabilize_threaded(frames, P, warp_frames, max_pairs, workers):
+    import concurrent.futures as cf
+    n, H, W = frames.shape
+    n_pairs = n - 1 if max_pairs is None else min(n - 1, max_pairs)
+    n_used = n_pairs + 1
+    roi = (P.roi_mx if P.roi_mx is not None else max(16, W // 20),
+           P.roi_my if P.roi_my is not None else max(16, H // 20))
+    e = P.redetect_every
+    segs = [(s, min(s + e, n_used - 1)) for s in range(0, n_used - 1, e)]
+    lib()
+    with cf.ThreadPoolExecutor(workers) as ex:
+        parts = list(ex.map(lambda fl: _segment_tracks(frames, P, roi, fl[0], fl[1]), segs))
+    fp = fit_params(P.model, P.ransac_iters, P.inlier_thresh, P.seed, P.stream_id, P.min_valid, P.dwell, W, H)
+    st = new_hybrid_state()
+    out = {"pair_params": np.zeros((n_pairs, 4)), "info": [], "tracks": [], "detections": {}}
+    if n_pairs == 0:
+        pts, _, _ = detect(frames[0], P.max_corners, P.quality, P.min_dist, roi)
+        out["detections"][0] = pts
+    detect_frames = []
+    for recs, dets in parts:
+        out["detections"].update(dets)
+        detect_frames += sorted(dets)
+        out["tracks"] += recs
+    for k, t in enumerate(out["tracks"]):
+        prm, info, inl = fit_pair(t["src"], t["dst"], t["status"], fp, k, st)
+        out["pair_params"][k] = _refined(frames, P, k + 1, prm, info, W, H)
+        out["info"].append(info)
+        t["inliers"] = inl
+    traj, sm, mats = smooth(out["pair_params"], n_used, P.smooth_mode, P.radius, P.kalman_ratio, P.crop, W, H)
+    out.update(traj=traj, smoothed=sm, mats=mats, detect_frames=detect_frames if n_pairs else [0])
+    if warp_frames:
+        with cf.ThreadPoolExecutor(workers) as ex:
+            out["warped"] = np.stack(list(ex.map(lambda j: warp(frames[j], mats[j], P.border), range(n_used))))
     return out

@@ -258,7 +258,7 @@ typedef struct {
 
 /* One coarse-to-fine track of point u from pyramid A to pyramid B. Returns 1 if valid. */
 static int lk_one(const img_t* A, const img_t* B, int levels, const vso_lk_params* p, double ux, double uy,
-                  double* vx, double* vy, int* iters_l0)
+                  double* vx, double* vy, int* iters_l0, double* eig_margin)
 {
     const int hw = p->win_half;
     const double nwin = (double)((2 * hw + 1) * (2 * hw + 1));
@@ -278,6 +278,10 @@ static int lk_one(const img_t* A, const img_t* B, int levels, const vso_lk_param
                 g22 += iy * iy;
             }
         const double lmin = 0.5 * ((g11 + g22) - sqrt((g11 - g22) * (g11 - g22) + 4.0 * g12 * g12));
+        /* distance of this level's test statistic from its threshold, relative to the threshold
+         * (reported only: lets a caller tell decisions taken on the threshold's edge) */
+        const double margin = fabs(lmin / nwin - p->min_eig) / p->min_eig;
+        if (margin < *eig_margin) *eig_margin = margin;
         double nux = 0.0, nuy = 0.0;
         if (lmin / nwin < p->min_eig) {
             if (l == 0) ok = 0;
@@ -315,11 +319,12 @@ static int lk_one(const img_t* A, const img_t* B, int levels, const vso_lk_param
 
 /* prev_lv / next_lv: level base pointers; lw/lh/lpitch per level. alive may be NULL (all alive).
  * Outputs (n each): out_xy[2n], status[n], fb_err[n] (NaN where not computed), iters[2n]
- * (level-0 iterations of the forward and backward passes). */
+ * (level-0 iterations of the forward and backward passes), eig_margin[n] (may be NULL: the smallest
+ * |lambda_min / window size - min_eig| / min_eig over every level of both passes; +inf if none ran). */
 VSO_EXPORT void vso_track_lk(const uint8_t* const* prev_lv, const uint8_t* const* next_lv, const int* lw,
                              const int* lh, const int* lpitch, int levels, const double* pts, int n,
                              const uint8_t* alive, const vso_lk_params* p, double* out_xy, uint8_t* status,
-                             double* fb_err, int* iters)
+                             double* fb_err, int* iters, double* eig_margin)
 {
     img_t A[16], B[16];
     for (int l = 0; l < levels; ++l) {
@@ -333,22 +338,25 @@ VSO_EXPORT void vso_track_lk(const uint8_t* const* prev_lv, const uint8_t* const
         status[i] = 0;
         fb_err[i] = NAN;
         iters[2 * i] = iters[2 * i + 1] = 0;
+        double margin = INFINITY;
+        if (eig_margin) eig_margin[i] = INFINITY;
         if (alive && !alive[i]) continue;
         double vx = ux, vy = uy;
         int it0 = 0, it1 = 0;
-        int ok = lk_one(A, B, levels, p, ux, uy, &vx, &vy, &it0);
+        int ok = lk_one(A, B, levels, p, ux, uy, &vx, &vy, &it0, &margin);
         out_xy[2 * i] = vx;
         out_xy[2 * i + 1] = vy;
         iters[2 * i] = it0;
         if (ok && p->fb) {
             double bx = vx, by = vy;
-            const int okb = lk_one(B, A, levels, p, vx, vy, &bx, &by, &it1);
+            const int okb = lk_one(B, A, levels, p, vx, vy, &bx, &by, &it1, &margin);
             iters[2 * i + 1] = it1;
             const double e = sqrt((bx - ux) * (bx - ux) + (by - uy) * (by - uy));
             fb_err[i] = e;
             ok = okb && (e <= p->fb_thresh);
         }
         status[i] = (uint8_t)ok;
+        if (eig_margin) eig_margin[i] = margin;
     }
 }
 

@@ -311,6 +311,27 @@ def make_sequence(name_or_recipe, n_frames: int | None = None, device: str | tor
     return seq
 
 
+def integer_translation_sequence(width: int, height: int, n_frames: int, max_step: int = 5,
+                                 seed: int = 1709) -> Sequence:
+    """Frames cut from one uint8 blob texture at integer offsets: frame j is the canvas window at
+    offset o_j, o_0 = 0 and o_{j+1} - o_j drawn uniformly from [-max_step, max_step]^2. Every frame is
+    an exact integer shift of the previous one (no resampling, no rounding), so the pair transform
+    S_j is the translation by o_j - o_{j+1}, exactly."""
+    rng = np.random.default_rng(seed)
+    steps = rng.integers(-max_step, max_step + 1, size=(max(n_frames - 1, 0), 2))
+    off = np.concatenate([np.zeros((1, 2), np.int64), np.cumsum(steps, axis=0)], axis=0)
+    lo, hi = off.min(0), off.max(0)
+    cw, ch = width + int(hi[0] - lo[0]), height + int(hi[1] - lo[1])
+    canvas = np.clip(np.floor(_blob_canvas(cw, ch, rng) + 0.5), 0, 255).astype(np.uint8)
+    frames = np.stack([canvas[int(o[1] - lo[1]):int(o[1] - lo[1]) + height, int(o[0] - lo[0]):int(o[0] - lo[0]) + width]
+                       for o in off])
+    A = np.stack([np.array([[1.0, 0.0, -float(o[0])], [0.0, 1.0, -float(o[1])], [0.0, 0.0, 1.0]]) for o in off])
+    r = SeqRecipe("translate", width, height, n_frames, "blobs", "translate", seed=seed)
+    seq = Sequence(r, np.ascontiguousarray(frames), A)
+    seq._movers = []
+    return seq
+
+
 def _reflect(v: float, lo: float, hi: float) -> float:
     span = hi - lo
     if span <= 0:

@@ -115,3 +115,43 @@ def test_backward_error_is_a_separate_backward_track():
         d = np.hypot(*(bwd - pts).T)
         np.testing.assert_allclose(fe[ok], d[ok], rtol=0, atol=1e-12)
         np.testing.assert_array_equal(st.astype(bool), ok & st_b.astype(bool) & (d <= thr))
+
+
+def test_eigen_margin_is_the_window_tensor_minimum_eigenvalue():
+    """The reported margin of a single-level zero-motion track is |lambda_min(G) / 441 - tau| / tau
+    with G the gradient tensor of the 21x21 window, here from numpy.gradient and numpy.linalg.eigvalsh
+    (both passes see the same window at an integer point)."""
+    img = synth.smooth_random_image(96, 80, 13, sigma=2.0)
+    pts = np.array([[47.0, 38.0], [30.0, 25.0], [60.0, 50.0]])
+    tau = 0.5
+    _, st, _, _, mg = O.track_lk([img], [img], pts, min_eig=tau, with_margin=True)
+    gy, gx = np.gradient(img.astype(np.float64))
+    for i, (x, y) in enumerate(pts.astype(int)):
+        sl = (slice(y - 10, y + 11), slice(x - 10, x + 11))
+        G = np.array([[np.sum(gx[sl] ** 2), np.sum(gx[sl] * gy[sl])], [np.sum(gx[sl] * gy[sl]), np.sum(gy[sl] ** 2)]])
+        lam = np.linalg.eigvalsh(G)[0] / 441.0
+        assert abs(mg[i] - abs(lam - tau) / tau) <= 1e-9 * max(1.0, abs(lam - tau) / tau)
+        assert st[i] == (lam >= tau)
+
+
+def test_eigen_margin_is_the_smallest_over_levels_and_passes():
+    """Moving the threshold onto one level's statistic drives the margin to zero; a dead slot, which
+    runs no test, reports +inf."""
+    a = synth.smooth_random_image(200, 160, 21, sigma=1.5)
+    b = smooth_texture(200, 160, 1.7, -2.2, seed=3)
+    pa, pb = O.pyramid(a, 3), O.pyramid(b, 3)
+    pts = synth.random_points(20, 200, 160, 30, 6)
+    _, _, _, _, m1 = O.track_lk(pa, pb, pts, min_eig=1.0, with_margin=True)
+    # with tau' = tau (1 - m) or tau (1 + m) one of the statistics seen equals the new threshold
+    for i in range(3):
+        for tau in (1.0 * (1.0 - m1[i]), 1.0 * (1.0 + m1[i])):
+            if tau <= 0:
+                continue
+            _, _, _, _, m2 = O.track_lk(pa, pb, pts[i:i + 1], min_eig=tau, with_margin=True)
+            # either the statistic sits exactly on the new threshold, or the other sign was the hit
+            if m2[0] < 1e-9:
+                break
+        else:
+            raise AssertionError("no level statistic at distance %g" % m1[i])
+    _, _, _, _, m3 = O.track_lk(pa, pb, pts[:2], alive=np.array([0, 1], np.uint8), with_margin=True)
+    assert np.isinf(m3[0]) and np.isfinite(m3[1])

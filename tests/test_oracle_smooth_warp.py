@@ -1,7 +1,8 @@
 """Pins of the oracle's trajectory smoothing (Section 5.1, Section 6) and warp (Section 5).
 
 Smoothing pins: constant and linear trajectories, closed-form window means of j^2 with truncated
-ends, the global mean when the radius covers the sequence, the Kalman steady-state gain of a
+ends (centred and causal windows), the causal correction -r v of a constant pan, causality (later
+pairs never change earlier outputs), the global mean when the radius covers the sequence, the Kalman steady-state gain of a
 random walk (Riccati fixed point), and the correction matrix of a pure translation.
 Warp pins: identity, integer shifts with zero fill, the 180 degree rotation as a flip, half-pixel
 shifts, and scipy's map_coordinates (order 1, grid-constant) on general similarities.
@@ -52,6 +53,54 @@ def test_window_means_of_squares_with_truncated_ends():
         lo, hi = max(0, j - r), min(n - 1, j + r)
         mean = (s2(hi) - (s2(lo - 1) if lo > 0 else 0.0)) / (hi - lo + 1)
         assert abs(sm[j, 0] - mean) <= 1e-12 * max(1.0, mean)
+
+
+@pytest.mark.parametrize("r", [1, 4, 7])
+def test_causal_window_of_a_constant_pan(r):
+    """Causal mode (the sliding store of the real-time version, Section 6) averages P over
+    [max(0, j - 2r), j]. With a constant pan v, P_j = j v: the mean is (j - r) v once j >= 2r, so the
+    correction is exactly -r v there, and j v / 2 over the truncated window before it."""
+    n = 40
+    v = np.array([1.5, -0.25])
+    _, sm, mats = O.smooth(pairs_const(n, tx=v[0], ty=v[1]), n, 1, r, 0.0, 0.0, W, H)
+    for j in range(n):
+        want = (j - r) * v if j >= 2 * r else j * v / 2.0
+        np.testing.assert_allclose(sm[j, :2], want, rtol=0, atol=1e-12 * max(1.0, j))
+        np.testing.assert_allclose(mats[j], [1, 0, want[0] - j * v[0], 0, 1, want[1] - j * v[1]], rtol=0,
+                                   atol=1e-12 * max(1.0, j))
+
+
+@pytest.mark.parametrize("r", [2, 5])
+def test_causal_window_means_of_squares(r):
+    """P_j = j^2: the causal mean over [lo, j], lo = max(0, j - 2r), is (S(j) - S(lo - 1)) / (j - lo + 1)
+    with S(m) = m (m + 1) (2m + 1) / 6."""
+    n = 30
+    pp = np.array([[1.0, 0.0, 2.0 * k + 1.0, 0.0] for k in range(n - 1)])
+    _, sm, _ = O.smooth(pp, n, 1, r, 0.0, 0.0, W, H)
+
+    def s2(m):
+        return m * (m + 1) * (2 * m + 1) / 6.0
+
+    for j in range(n):
+        lo = max(0, j - 2 * r)
+        mean = (s2(j) - (s2(lo - 1) if lo > 0 else 0.0)) / (j - lo + 1)
+        assert abs(sm[j, 0] - mean) <= 1e-12 * max(1.0, mean)
+
+
+def test_causal_output_ignores_later_pairs():
+    """Frame j's causal output depends on pairs before j only: changing pair k leaves frames <= k
+    unchanged (a centred or off-by-one window would not)."""
+    n, r = 24, 3
+    rng = np.random.default_rng(4)
+    pp = np.stack([np.ones(n - 1), np.zeros(n - 1), rng.normal(0, 3, n - 1), rng.normal(0, 3, n - 1)], 1)
+    _, sm, mats = O.smooth(pp, n, 1, r, 0.0, 0.0, W, H)
+    for k in (0, 7, 15):
+        q = pp.copy()
+        q[k, 2] += 5.0
+        _, sm2, mats2 = O.smooth(q, n, 1, r, 0.0, 0.0, W, H)
+        np.testing.assert_array_equal(sm2[:k + 1], sm[:k + 1])
+        np.testing.assert_array_equal(mats2[:k + 1], mats[:k + 1])
+        assert np.all(sm2[k + 1:k + 2 * r + 2, 0] != sm[k + 1:k + 2 * r + 2, 0])
 
 
 def test_radius_beyond_sequence_is_global_mean():
