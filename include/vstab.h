@@ -215,6 +215,24 @@ int vs_fit_motion(const float* src, const float* dst, const uint8_t* valid, int3
                   const vs_fit_params* p, int64_t pair_index0, vs_fit_state* state, double* params, double* affine6,
                   vs_fit_info* info, uint8_t* inliers, void* workspace, size_t ws_bytes, void* stream);
 
+/* fit_motion_noalloc -- for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. Same arguments, outputs and errors
+ * as vs_fit_motion, without the workspace: the fit kernels use instead a scratch array of
+ * VS_FIT_NOALLOC_SCRATCH_BYTES that the library holds in static device memory, one copy per GPU,
+ * until the process ends. The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine). At most vs_fit_noalloc_max_pairs(capacity) pairs per call (the workspace the same call
+ * would take from vs_fit_workspace must fit the scratch); a larger n returns VS_ERR_WORKSPACE with
+ * nothing enqueued. `stream` must belong to the current device (else VS_ERR_INVALID). Every call on
+ * one GPU uses that GPU's one scratch array: calls that may overlap on the device (different streams
+ * without ordering between them) race and must be serialised by the caller; calls on one stream are
+ * ordered. The scratch needs no clearing: each call writes every byte of it that it reads. The first
+ * call on a device looks up that device's scratch address (hipGetSymbolAddress) and keeps it. */
+#define VS_FIT_NOALLOC_SCRATCH_BYTES (8 * 1024 * 1024)
+int32_t vs_fit_noalloc_max_pairs(int32_t capacity);
+int vs_fit_motion_noalloc(const float* src, const float* dst, const uint8_t* valid, int32_t capacity, int32_t n,
+                          const vs_fit_params* p, int64_t pair_index0, vs_fit_state* state, double* params,
+                          double* affine6, vs_fit_info* info, uint8_t* inliers, void* stream);
+
 /* ---------------------------------------------------------------------------------------------
  * smooth_trajectory -- Section 5.1 (accumulate the per-pair parameters into a trajectory, smooth
  * it with an averaging window of twice the smoothing radius, correct each frame by smoothed minus

@@ -24,6 +24,7 @@
 // info and inlier flags.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "vs_common.hpp"
 
@@ -756,38 +757,43 @@ extern "C" int vs_fit_state_init(vs_fit_state* state, void* stream)
     return vs::check_launch("vs_fit_state_init");
 }
 
-extern "C" int vs_fit_motion(const float* src, const float* dst, const uint8_t* valid, int32_t capacity, int32_t n,
-                             const vs_fit_params* p, int64_t pair_index0, vs_fit_state* state, double* params,
-                             double* affine6, vs_fit_info* info, uint8_t* inliers, void* workspace, size_t ws_bytes,
-                             void* stream)
+namespace {
+
+// Validates the arguments shared by both fit entry points; on success fills *a.
+int check_fit_args(const char* who, const float* src, const float* dst, const uint8_t* valid, int32_t capacity,
+                   int32_t n, const vs_fit_params* p, int64_t pair_index0, const vs_fit_state* state,
+                   const double* params, const vs_fit_info* info, FitArgs* a)
 {
-    if (!p) return vs::set_error(VS_ERR_INVALID, "vs_fit_motion: null params");
-    if (n < 0 || capacity <= 0) return vs::set_error(VS_ERR_INVALID, "vs_fit_motion: bad count or capacity");
+    if (!p) return vs::set_error(VS_ERR_INVALID, "%s: null params", who);
+    if (n < 0 || capacity <= 0) return vs::set_error(VS_ERR_INVALID, "%s: bad count or capacity", who);
     if (n == 0) return VS_OK;
-    if (!src || !dst || !valid || !state || !params || !info || !workspace)
-        return vs::set_error(VS_ERR_INVALID, "vs_fit_motion: null argument");
-    if (capacity > VS_MAX_CORNERS) return vs::set_error(VS_ERR_UNSUPPORTED, "vs_fit_motion: capacity > %d", VS_MAX_CORNERS);
+    if (!src || !dst || !valid || !state || !params || !info)
+        return vs::set_error(VS_ERR_INVALID, "%s: null argument", who);
+    if (capacity > VS_MAX_CORNERS) return vs::set_error(VS_ERR_UNSUPPORTED, "%s: capacity > %d", who, VS_MAX_CORNERS);
     const bool with_affine = p->model == VS_AFFINE || p->model == VS_HYBRID3;
     if (p->model < VS_RIGID || p->model > VS_HYBRID3 || p->ransac_iters < 0 ||
         p->ransac_iters > (with_affine ? 8191 : 32767) || !(p->inlier_thresh >= 0.0) || p->dwell < 1 || pair_index0 < 0)
-        return vs::set_error(VS_ERR_INVALID, "vs_fit_motion: bad parameters");
-    if (n > 65535) return vs::set_error(VS_ERR_INVALID, "vs_fit_motion: more than 65535 pairs");
-    const size_t need = vs_fit_workspace(n, capacity);
-    if (ws_bytes < need) return vs::set_error(VS_ERR_WORKSPACE, "vs_fit_motion: workspace %zu < %zu", ws_bytes, need);
-    if (reinterpret_cast<uintptr_t>(workspace) & 255)
-        return vs::set_error(VS_ERR_INVALID, "vs_fit_motion: workspace must be 256-byte aligned");
-    FitArgs a;
-    a.model = p->model;
-    a.iters = p->ransac_iters;
-    a.tau2 = p->inlier_thresh * p->inlier_thresh;
-    a.seed = p->seed;
-    a.stream_id = p->stream_id;
-    a.min_valid = p->min_valid;
-    a.dwell = p->dwell;
-    a.cx = p->cx;
-    a.cy = p->cy;
-    hipStream_t s = vs::as_stream(stream);
-    uint8_t* w8 = static_cast<uint8_t*>(workspace);
+        return vs::set_error(VS_ERR_INVALID, "%s: bad parameters", who);
+    if (n > 65535) return vs::set_error(VS_ERR_INVALID, "%s: more than 65535 pairs", who);
+    a->model = p->model;
+    a->iters = p->ransac_iters;
+    a->tau2 = p->inlier_thresh * p->inlier_thresh;
+    a->seed = p->seed;
+    a->stream_id = p->stream_id;
+    a->min_valid = p->min_valid;
+    a->dwell = p->dwell;
+    a->cx = p->cx;
+    a->cy = p->cy;
+    return VS_OK;
+}
+
+// Enqueues the four fit kernels over a workspace of at least vs_fit_workspace(n, capacity) bytes
+// (a device address, 256-byte aligned; its contents on entry do not matter: every byte the kernels
+// read is written earlier in the same call).
+int launch_fit(const char* who, const float* src, const float* dst, const uint8_t* valid, int32_t capacity, int32_t n,
+               const FitArgs& a, int64_t pair_index0, vs_fit_state* state, double* params, double* affine6,
+               vs_fit_info* info, uint8_t* inliers, uint8_t* w8, hipStream_t s)
+{
     const size_t lds = pair_lds_bytes(capacity);
     if (lds > 65536) {
         // capacities above ~3400 points need more than the default 64 KiB of dynamic LDS
@@ -796,22 +802,100 @@ extern "C" int vs_fit_motion(const float* src, const float* dst, const uint8_t* 
         if (he == hipSuccess)
             he = hipFuncSetAttribute(reinterpret_cast<const void*>(&fit_hyp_kernel),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (he != hipSuccess) return vs::set_error(VS_ERR_HIP, "vs_fit_motion: %s", hipGetErrorString(he));
+        if (he != hipSuccess) return vs::set_error(VS_ERR_HIP, "%s: %s", who, hipGetErrorString(he));
     }
     // spread each pair's hypotheses over workgroups until about 2048 are in flight (up to MAX_SPLIT
     // per pair): the scoring loops are chains of dependent FP64 operations, hidden only by other waves
     const int split = a.iters > 0 ? std::min(std::max((2048 + n - 1) / n, 1), MAX_SPLIT) : 1;
     fit_hyp_kernel<<<n * split, NT, lds, s>>>(src, dst, valid, capacity, a, pair_index0, split, w8);
-    int e0 = vs::check_launch("vs_fit_motion(hypotheses)");
-    if (e0) return e0;
+    int e = vs::check_launch(who);
+    if (e) return e;
     fit_pair_kernel<<<n * models_in(a.model), NT, lds, s>>>(src, dst, valid, capacity, a, pair_index0, split, w8);
-    int e = vs::check_launch("vs_fit_motion(pairs)");
-    if (e) return e;
+    if ((e = vs::check_launch(who))) return e;
     fit_resolve_kernel<<<1, NT, 0, s>>>(n, capacity, a, pair_index0, state, w8);
-    e = vs::check_launch("vs_fit_motion(resolve)");
-    if (e) return e;
+    if ((e = vs::check_launch(who))) return e;
     fit_emit_kernel<<<n, NT, 0, s>>>(capacity, a.model, w8, params, affine6, info, inliers);
-    return vs::check_launch("vs_fit_motion(emit)");
+    return vs::check_launch(who);
+}
+
+// Scratch of vs_fit_motion_noalloc: a file-scope device array, one copy per GPU, held until the
+// process ends. Host code never passes `scratch` itself to a kernel (on the host the name is only a
+// stand-in for the symbol): it looks up each device's address once, with that device current, and
+// passes that address.
+static __device__ __align__(256) uint8_t scratch[VS_FIT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+int scratch_address(const char* who, hipStream_t s, uint8_t** out)
+{
+    int dev = -1;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) return vs::set_error(VS_ERR_HIP, "%s: hipGetDevice: %s", who, hipGetErrorString(he));
+    if (dev < 0 || dev >= MAX_DEVICES) return vs::set_error(VS_ERR_UNSUPPORTED, "%s: device %d", who, dev);
+    if (s) {
+        // the scratch must live on the device the work runs on
+        hipDevice_t sd = -1;
+        he = hipStreamGetDevice(s, &sd);
+        if (he != hipSuccess)
+            return vs::set_error(VS_ERR_HIP, "%s: hipStreamGetDevice: %s", who, hipGetErrorString(he));
+        if (sd != dev) return vs::set_error(VS_ERR_INVALID, "%s: stream of device %d, device %d current", who, sd, dev);
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        he = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (he != hipSuccess || !p)
+            return vs::set_error(VS_ERR_HIP, "%s: hipGetSymbolAddress: %s", who, hipGetErrorString(he));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<uint8_t*>(g_scratch_ptr[dev]);
+    return VS_OK;
+}
+
+}  // namespace
+
+extern "C" int vs_fit_motion(const float* src, const float* dst, const uint8_t* valid, int32_t capacity, int32_t n,
+                             const vs_fit_params* p, int64_t pair_index0, vs_fit_state* state, double* params,
+                             double* affine6, vs_fit_info* info, uint8_t* inliers, void* workspace, size_t ws_bytes,
+                             void* stream)
+{
+    FitArgs a;
+    int e = check_fit_args("vs_fit_motion", src, dst, valid, capacity, n, p, pair_index0, state, params, info, &a);
+    if (e || n == 0) return e;
+    if (!workspace) return vs::set_error(VS_ERR_INVALID, "vs_fit_motion: null argument");
+    const size_t need = vs_fit_workspace(n, capacity);
+    if (ws_bytes < need) return vs::set_error(VS_ERR_WORKSPACE, "vs_fit_motion: workspace %zu < %zu", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(workspace) & 255)
+        return vs::set_error(VS_ERR_INVALID, "vs_fit_motion: workspace must be 256-byte aligned");
+    return launch_fit("vs_fit_motion", src, dst, valid, capacity, n, a, pair_index0, state, params, affine6, info,
+                      inliers, static_cast<uint8_t*>(workspace), vs::as_stream(stream));
+}
+
+extern "C" int32_t vs_fit_noalloc_max_pairs(int32_t capacity)
+{
+    if (capacity <= 0 || capacity > VS_MAX_CORNERS) return 0;
+    return (int32_t)std::min<int64_t>(65535, (int64_t)VS_FIT_NOALLOC_SCRATCH_BYTES / rec_bytes(capacity));
+}
+
+extern "C" int vs_fit_motion_noalloc(const float* src, const float* dst, const uint8_t* valid, int32_t capacity,
+                                     int32_t n, const vs_fit_params* p, int64_t pair_index0, vs_fit_state* state,
+                                     double* params, double* affine6, vs_fit_info* info, uint8_t* inliers, void* stream)
+{
+    const char* who = "vs_fit_motion_noalloc";
+    FitArgs a;
+    int e = check_fit_args(who, src, dst, valid, capacity, n, p, pair_index0, state, params, info, &a);
+    if (e || n == 0) return e;
+    const int32_t max_n = vs_fit_noalloc_max_pairs(capacity);
+    if (n > max_n)
+        return vs::set_error(VS_ERR_WORKSPACE, "%s: %d pairs of capacity %d need %zu bytes of scratch; at most %d pairs "
+                             "fit its %d bytes", who, n, capacity, vs_fit_workspace(n, capacity), max_n,
+                             (int)VS_FIT_NOALLOC_SCRATCH_BYTES);
+    hipStream_t s = vs::as_stream(stream);
+    uint8_t* w8 = nullptr;
+    if ((e = scratch_address(who, s, &w8))) return e;
+    return launch_fit(who, src, dst, valid, capacity, n, a, pair_index0, state, params, affine6, info, inliers, w8, s);
 }
 
 extern "C" int vs_fit_similarity(const float* src, const float* dst, const uint8_t* valid, int32_t capacity, int32_t n,

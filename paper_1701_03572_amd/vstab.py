@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libvstab.so")
 VS_MAX_LEVELS = 8
 VS_MAX_CORNERS = 4096
 VS_TRAJ_RING = 256
+VS_FIT_NOALLOC_SCRATCH_BYTES = 8 * 1024 * 1024
 VS_RIGID, VS_SIMILARITY, VS_HYBRID, VS_AFFINE, VS_HYBRID3 = 0, 1, 2, 3, 4
 VS_SMOOTH_CENTERED, VS_SMOOTH_CAUSAL, VS_SMOOTH_KALMAN = 0, 1, 2
 
@@ -115,6 +116,9 @@ _SIGS = {
                                     _P, _P, _P, C.c_size_t, _P]),
     "vs_fit_motion": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.POINTER(vs_fit_params), C.c_int64, _P, _P, _P,
                                 _P, _P, _P, C.c_size_t, _P]),
+    "vs_fit_noalloc_max_pairs": (C.c_int32, [C.c_int32]),
+    "vs_fit_motion_noalloc": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.POINTER(vs_fit_params), C.c_int64, _P,
+                                        _P, _P, _P, _P, _P]),
     "vs_traj_state_bytes": (C.c_size_t, []),
     "vs_traj_state_init": (C.c_int, [_P, _P]),
     "vs_smooth_trajectory": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(vs_smooth_params), _P, _P, C.c_int32,
@@ -275,6 +279,17 @@ def vs_fit_motion(src, dst, valid, capacity: int, n: int, params: vs_fit_params,
     _check(load().vs_fit_motion(_ptr(src), _ptr(dst), _ptr(valid), capacity, n, C.byref(params), pair_index0,
                                 _ptr(state), _ptr(out_params), _ptr(affine6), _ptr(info), _ptr(inliers),
                                 _ptr(workspace), ws_bytes, _stream(stream)), "vs_fit_motion")
+
+
+def vs_fit_noalloc_max_pairs(capacity: int) -> int:
+    return int(load().vs_fit_noalloc_max_pairs(capacity))
+
+
+def vs_fit_motion_noalloc(src, dst, valid, capacity: int, n: int, params: vs_fit_params, pair_index0: int, state,
+                          out_params, affine6, info, inliers, stream=None):
+    _check(load().vs_fit_motion_noalloc(_ptr(src), _ptr(dst), _ptr(valid), capacity, n, C.byref(params), pair_index0,
+                                        _ptr(state), _ptr(out_params), _ptr(affine6), _ptr(info), _ptr(inliers),
+                                        _stream(stream)), "vs_fit_motion_noalloc")
 
 
 def vs_traj_state_bytes() -> int:
