@@ -51,7 +51,7 @@ def test_uhd_pyramid_corners_tracks_and_warp():
     pts = xy[0][:cnt[0]][:: cnt[0] // 300][:300].astype(np.float32)
     res = compare(f0, f1, pts, L)
     say(res)
-    assert res["valid"] > 250
+    assert res["compared"] > 250
 
     say("uhd warp")
     a, b = 1.004 * np.cos(0.01), 1.004 * np.sin(0.01)

@@ -2,8 +2,15 @@
 
 GPU arithmetic is FP32, the oracle binary64. Bar: positions of points valid on both sides within
 0.01 px; statuses equal except for points whose outcome sits on a decision boundary, which are
-counted and must stay rare: the oracle's round-trip error within 5 % of the threshold, a final
-position within 1 px of the image edge, or an oracle track that ran out of iterations at level 0.
+exempted:
+* the oracle's round-trip error within 1e-3 relative of the backward-check threshold;
+* the oracle's lambda_min / window size within 1e-3 relative of the eigenvalue threshold, at any
+  level of either pass;
+* a final position within 1 px of the image edge (the bilinear sampler's clamping starts there);
+* an oracle pass that ran out of iterations at level 0: its position is wherever the 30th update
+  left a non-converging iteration, not a fixed point, so the two precisions need not agree there
+  (such a track is compared too, and exempted only if it differs by more than 0.01 px).
+The exempted points are counted, reported and must stay at most 1 % of the tracked points.
 """
 import numpy as np
 import pytest
@@ -48,24 +55,44 @@ def gpu_track(prev, nxt, pts, L, alive=None, cap=None, **kw):
     return out, st, fe
 
 
-def compare(prev, nxt, pts, L, alive=None, tol=0.01, **kw):
+def compare(prev, nxt, pts, L, alive=None, tol=0.01, max_excluded=0.01, **kw):
+    """Statuses must agree except on a decision boundary (the classes above); positions of points
+    valid on both sides must agree within tol, except for oracle tracks that ran out of iterations.
+    The points exempted (status mismatches on a boundary, capped tracks beyond tol) are the excluded
+    ones: counted, reported and at most max_excluded of the tracked points (at least one allowed)."""
     prm = dict(LKP, **kw)
     g_xy, g_st, g_fe = gpu_track(prev, nxt, pts, L, alive, **kw)
-    ro, rs, rf, it = O.track_lk(O.pyramid(prev, L), O.pyramid(nxt, L), pts.astype(np.float32).astype(np.float64),
-                                alive, **prm)
+    ro, rs, rf, it, mg = O.track_lk(O.pyramid(prev, L), O.pyramid(nxt, L), pts.astype(np.float32).astype(np.float64),
+                                    alive, with_margin=True, **prm)
     h, w = prev.shape
-    near_edge = (ro[:, 0] < 1) | (ro[:, 1] < 1) | (ro[:, 0] > w - 2) | (ro[:, 1] > h - 2)
-    boundary = (np.abs(rf - prm["fb_thresh"]) < 0.05 * prm["fb_thresh"]) | near_edge | (it[:, 0] >= prm["max_iter"]) \
-        | (it[:, 1] >= prm["max_iter"])
+    n_alive = len(pts) if alive is None else int(np.sum(alive))
+    capped = (it[:, 0] >= prm["max_iter"]) | (it[:, 1] >= prm["max_iter"])
+    classes = {
+        "fb_band": np.abs(rf - prm["fb_thresh"]) <= 1e-3 * prm["fb_thresh"],
+        "eig_band": mg <= 1e-3,
+        "edge": (ro[:, 0] < 1) | (ro[:, 1] < 1) | (ro[:, 0] > w - 2) | (ro[:, 1] > h - 2),
+        "iter_cap": capped,
+    }
+    boundary = np.zeros(len(pts), bool)
+    for v in classes.values():
+        boundary |= v
     mism = (g_st != rs)
     unexplained = mism & ~boundary
     assert unexplained.sum() == 0, np.nonzero(unexplained)[0][:10]
-    both = (g_st == 1) & (rs == 1) & ~boundary
-    err = np.abs(g_xy[both].astype(np.float64) - ro[both])
-    assert both.sum() > 0
-    assert err.max() <= tol, (err.max(), np.argmax(err.max(1)))
-    return dict(n=len(pts), valid=int(both.sum()), excluded=int(boundary.sum()), mismatched=int(mism.sum()),
-                max_err=float(err.max()))
+    both = (g_st == 1) & (rs == 1)
+    err = np.full(len(pts), 0.0)
+    err[both] = np.abs(g_xy[both].astype(np.float64) - ro[both]).max(1)
+    off = both & (err > tol)
+    assert not (off & ~capped).any(), (err.max(), np.nonzero(off & ~capped)[0][:10])
+    excluded = mism | off
+    assert (both & ~excluded).sum() > 0
+    r = dict(n=n_alive, compared=int((both & ~excluded).sum()), excluded=int(excluded.sum()),
+             status_mismatch=int(mism.sum()), capped_beyond_tol=int(off.sum()),
+             max_err=float(err[both & ~excluded].max()),
+             **{"in_" + k: int(v.sum()) for k, v in classes.items()})
+    say("lk parity", r)
+    assert r["excluded"] <= max(1, max_excluded * n_alive), r
+    return r
 
 
 def test_zero_motion_exact():
@@ -96,9 +123,7 @@ def test_sequence_pairs(name, K, L, pair):
     seq = synth.make_sequence(name, n_frames=pair + 2)
     a, b = seq.frames[pair], seq.frames[pair + 1]
     pts, _, _ = O.detect(a, K)
-    r = compare(a, b, pts.astype(np.float32), L)
-    say(r)
-    assert r["valid"] >= 0.5 * len(pts)
+    compare(a, b, pts.astype(np.float32), L)
 
 
 def test_hd_pair_full_size():
@@ -106,9 +131,7 @@ def test_hd_pair_full_size():
     seq = synth.make_sequence("hd", n_frames=2)
     a, b = seq.frames[0], seq.frames[1]
     pts, _, _ = O.detect(a, 1000)
-    r = compare(a, b, pts.astype(np.float32), 5)
-    say(r)
-    assert r["excluded"] <= 0.05 * len(pts)
+    compare(a, b, pts.astype(np.float32), 5)
 
 
 @pytest.mark.parametrize("hw", [1, 3, 5, 7, 11, 15])
