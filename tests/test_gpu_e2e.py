@@ -4,34 +4,24 @@
   pair parameters, fit records, matrices and stabilized frames (same kernels, independent
   5-frame segments, order-independent smoothing).
 * Against the oracle (binary64 tracking): identical first-frame corners, identical skip flags and
-  model choices, pair transforms within 0.02 px over the frame, stabilized pixels within 1 level
-  almost everywhere.
+  model choices (ties within 1e-12 relative excepted), pair transforms within 0.01 px over the
+  frame, stabilized pixels within 1 level almost everywhere (the stage-by-stage parity of the warp,
+  under the same matrices, is in test_gpu_configs).
 * At the full 1920x1080 / 600-frame workload in the launch configuration the benchmark times:
   corners of sampled segment-start frames are identical to the oracle's, sampled first tracking
-  steps match the oracle's tracker, and every pair transform recovers the generator's known
-  transform.
+  steps match the oracle's tracker at its bar, and every pair transform recovers the generator's
+  known transform (a sanity check of the method, not a parity bar: the frames are quantised).
 """
 import numpy as np
 import pytest
 import torch
 
-from helpers import dev, say
+from helpers import dev, lk_parity, say, transform_err
 from oracle import oracle as O
 from paper_1701_03572_amd import params, synth
 from paper_1701_03572_amd.pipeline import SequenceStabilizer, Stabilizer
 
 pytestmark = pytest.mark.gpu
-
-
-def transform_err(p, q, w, h):
-    cx, cy = (w - 1) / 2, (h - 1) / 2
-    pts = np.array([[-cx, -cy], [cx, -cy], [-cx, cy], [cx, cy], [0, 0]])
-
-    def ap(t):
-        a, b, tx, ty = t
-        return np.stack([a * pts[:, 0] - b * pts[:, 1] + tx, b * pts[:, 0] + a * pts[:, 1] + ty], 1)
-
-    return float(np.max(np.hypot(*(ap(p) - ap(q)).T)))
 
 
 def run_both_paths(frames_np, P):
@@ -68,12 +58,12 @@ def test_paths_agree_and_match_oracle(name, n):
     for p in range(n - 1):
         gi, ri = seq["info"][p], ref["info"][p]
         assert gi["skipped"] == ri["skipped"], p
-        tie = ri["decided_here"] and abs(ri["err_rigid"] - ri["err_sim"]) < 1e-6 * ri["err_sim"]
+        tie = ri["decided_here"] and abs(ri["err_rigid"] - ri["err_sim"]) < 1e-12 * ri["err_sim"]
         if not tie:
             assert gi["model"] == ri["model"], p
         errs.append(transform_err(seq["pair_params"][p], ref["pair_params"][p], w, h))
     say("max pair transform difference (px)", max(errs), "median", float(np.median(errs)))
-    assert max(errs) < 0.02 and np.median(errs) < 0.005
+    assert max(errs) < 0.01 and np.median(errs) < 0.005
     # first-frame corners are the oracle's
     cnt0 = int(seq["alive_src"][0].sum())
     np.testing.assert_array_equal(seq["src"][0][:cnt0], ref["detections"][0].astype(np.float32))
@@ -124,13 +114,11 @@ def test_full_size_workload_sampled():
         cnt = int(res["alive_src"][f].sum())
         np.testing.assert_array_equal(res["src"][f][:cnt], rxy.astype(np.float32))
         nxt = frames[f + 1].cpu().numpy()
-        ro, rs, rf, it = O.track_lk(O.pyramid(img, P.levels), O.pyramid(nxt, P.levels), rxy, None, P.win_half,
-                                    P.max_iter, P.eps, P.min_eig, P.fb, P.fb_thresh)
-        ok = (rs == 1) & (res["status"][f][:cnt] == 1) & (it[:, 0] < P.max_iter) & (it[:, 1] < P.max_iter) \
-            & (np.abs(rf - P.fb_thresh) > 0.05)
-        err = np.abs(res["dst"][f][:cnt][ok].astype(np.float64) - ro[ok])
-        say("segment", m, "valid", int(ok.sum()), "of", cnt, "max err", float(err.max()))
-        assert ok.sum() > 0.5 * cnt and err.max() <= 0.01
+        lkp = dict(win_half=P.win_half, max_iter=P.max_iter, eps=P.eps, min_eig=P.min_eig, fb=P.fb,
+                   fb_thresh=P.fb_thresh)
+        ref = O.track_lk(O.pyramid(img, P.levels), O.pyramid(nxt, P.levels), rxy, None, with_margin=True, **lkp)
+        r = lk_parity(res["dst"][f][:cnt], res["status"][f][:cnt], ref, rec.width, rec.height, **lkp)
+        say("segment", m, r)
     # streaming path over the same frames gives the same matrices
     st = Stabilizer(rec.width, rec.height, P, out_slots=P.radius + 2)
     for j in range(n):
@@ -163,7 +151,7 @@ def test_photometric_refinement_in_both_paths():
             assert acc[p] == 0
             continue
         assert loss[p, 1] <= loss[p, 0]
-        assert transform_err(seq["pair_params"][p], ref["pair_params"][p], w, h) < 0.02
+        assert transform_err(seq["pair_params"][p], ref["pair_params"][p], w, h) < 0.01
     say("accepted steps", acc.tolist())
     assert acc.sum() > 0
     d = np.abs(stream_out.astype(int) - seq_out.astype(int))
@@ -172,7 +160,7 @@ def test_photometric_refinement_in_both_paths():
 
 def test_three_way_hybrid_with_the_affine_candidate():
     """The hybrid extended by the 6-DOF affine of Eq. 7-8 (a variant): both paths agree bit for bit,
-    decisions and skips equal the oracle's, the smoothed similarity parts within 0.02 px."""
+    decisions and skips equal the oracle's, the pair similarities within 0.01 px."""
     sq = synth.make_sequence("tiny", n_frames=26)
     P = params.PRESETS["tiny"].replace(model=params.HYBRID3)
     seq, seq_out, stream_out, ss, st = run_both_paths(sq.frames, P)
@@ -184,11 +172,11 @@ def test_three_way_hybrid_with_the_affine_candidate():
         gi, ri = seq["info"][p], ref["info"][p]
         assert gi["skipped"] == ri["skipped"] and gi["decided_here"] == ri["decided_here"], p
         errs = [ri["err_rigid"], ri["err_sim"], ri["err_affine"]]
-        tie = ri["decided_here"] and any(abs(x - y) < 1e-6 * max(x, y) for i, x in enumerate(errs) for y in errs[i + 1:])
+        tie = ri["decided_here"] and any(abs(x - y) < 1e-12 * max(x, y) for i, x in enumerate(errs) for y in errs[i + 1:])
         if not tie:
             assert gi["model"] == ri["model"], p
         models.append(gi["model"])
-        assert transform_err(seq["pair_params"][p], ref["pair_params"][p], w, h) < 0.02
+        assert transform_err(seq["pair_params"][p], ref["pair_params"][p], w, h) < 0.01
         if gi["model"] == params.AFFINE:
             m = seq["affine6"][p]
             np.testing.assert_allclose(seq["pair_params"][p], [(m[0] + m[4]) / 2, (m[3] - m[1]) / 2, m[2], m[5]],

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import dev, say
+from helpers import dev, lk_parity, say
 from oracle import oracle as O
 from paper_1701_03572_amd import synth
 from paper_1701_03572_amd import vstab as V
@@ -55,43 +55,14 @@ def gpu_track(prev, nxt, pts, L, alive=None, cap=None, **kw):
     return out, st, fe
 
 
-def compare(prev, nxt, pts, L, alive=None, tol=0.01, max_excluded=0.01, **kw):
-    """Statuses must agree except on a decision boundary (the classes above); positions of points
-    valid on both sides must agree within tol, except for oracle tracks that ran out of iterations.
-    The points exempted (status mismatches on a boundary, capped tracks beyond tol) are the excluded
-    ones: counted, reported and at most max_excluded of the tracked points (at least one allowed)."""
+def compare(prev, nxt, pts, L, alive=None, tol=0.01, **kw):
     prm = dict(LKP, **kw)
     g_xy, g_st, g_fe = gpu_track(prev, nxt, pts, L, alive, **kw)
-    ro, rs, rf, it, mg = O.track_lk(O.pyramid(prev, L), O.pyramid(nxt, L), pts.astype(np.float32).astype(np.float64),
-                                    alive, with_margin=True, **prm)
+    ref = O.track_lk(O.pyramid(prev, L), O.pyramid(nxt, L), pts.astype(np.float32).astype(np.float64), alive,
+                     with_margin=True, **prm)
     h, w = prev.shape
-    n_alive = len(pts) if alive is None else int(np.sum(alive))
-    capped = (it[:, 0] >= prm["max_iter"]) | (it[:, 1] >= prm["max_iter"])
-    classes = {
-        "fb_band": np.abs(rf - prm["fb_thresh"]) <= 1e-3 * prm["fb_thresh"],
-        "eig_band": mg <= 1e-3,
-        "edge": (ro[:, 0] < 1) | (ro[:, 1] < 1) | (ro[:, 0] > w - 2) | (ro[:, 1] > h - 2),
-        "iter_cap": capped,
-    }
-    boundary = np.zeros(len(pts), bool)
-    for v in classes.values():
-        boundary |= v
-    mism = (g_st != rs)
-    unexplained = mism & ~boundary
-    assert unexplained.sum() == 0, np.nonzero(unexplained)[0][:10]
-    both = (g_st == 1) & (rs == 1)
-    err = np.full(len(pts), 0.0)
-    err[both] = np.abs(g_xy[both].astype(np.float64) - ro[both]).max(1)
-    off = both & (err > tol)
-    assert not (off & ~capped).any(), (err.max(), np.nonzero(off & ~capped)[0][:10])
-    excluded = mism | off
-    assert (both & ~excluded).sum() > 0
-    r = dict(n=n_alive, compared=int((both & ~excluded).sum()), excluded=int(excluded.sum()),
-             status_mismatch=int(mism.sum()), capped_beyond_tol=int(off.sum()),
-             max_err=float(err[both & ~excluded].max()),
-             **{"in_" + k: int(v.sum()) for k, v in classes.items()})
+    r = lk_parity(g_xy, g_st, ref, w, h, alive, tol, **prm)
     say("lk parity", r)
-    assert r["excluded"] <= max(1, max_excluded * n_alive), r
     return r
 
 
