@@ -288,25 +288,33 @@ int vs_warp_frame(const uint8_t* src, int64_t src_stride, int32_t width, int32_t
  * sums[i * VS_PHOTO_SUMS + k] (device), fully written by the call:
  *   k = 0 the loss; 1..4 dL/dtheta; 5..14 the upper triangle of J^T J row by row
  *   (00 01 02 03 11 12 13 22 23 33); 15..18 J^T r. vs_photometric_fwd fills only k = 0 (the rest 0).
+ * Every sum is formed in a fixed order (per-tile partial sums in the workspace, then a per-pair
+ * reduction over the tiles in tile order), so repeated calls give bit-identical results.
+ * workspace (device, 256-byte aligned): at least vs_photometric_workspace(n, width, height) bytes;
+ * no state survives the call.
  */
 #define VS_PHOTO_SUMS 19
 typedef struct {
     int32_t x0, y0, x1, y1;
 } vs_rect;
 
+size_t vs_photometric_workspace(int32_t n, int32_t width, int32_t height);
 int vs_photometric_fwd(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width, int32_t height,
                        int32_t pitch, int32_t n, const double* theta, int64_t theta_stride, double cx, double cy,
-                       double rho, const vs_rect* omega, double* sums, void* stream);
+                       double rho, const vs_rect* omega, double* sums, void* workspace, size_t ws_bytes, void* stream);
 int vs_photometric_bwd(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width, int32_t height,
                        int32_t pitch, int32_t n, const double* theta, int64_t theta_stride, double cx, double cy,
-                       double rho, const vs_rect* omega, double* sums, void* stream);
+                       double rho, const vs_rect* omega, double* sums, void* workspace, size_t ws_bytes, void* stream);
 
-/* Per-feature window loss (same sampler): for point i with u[i][2] and displacement d[i][2] (float,
- * device), loss[i] = sum over q in [-win_half, win_half]^2 of (S(next, u + d + q) - S(prev, u + q))^2
- * and grad[i][2] = dloss/dd (may be NULL). One frame pair; 0 <= win_half <= 31. */
-int vs_photometric_features(const uint8_t* prev, const uint8_t* next, int32_t width, int32_t height, int32_t pitch,
-                            const float* u, const float* d, int32_t m, int32_t win_half, double* loss, double* grad,
-                            void* stream);
+/* Per-feature window loss (same sampler), the displacement part of the photometric residual of
+ * Eq. 3: for point k of pair i (pair i reads prev + i * frame_stride and next + i * frame_stride;
+ * its points are u[i * m + k][2] and displacements d[i * m + k][2], float, device),
+ * loss[i * m + k] = sum over q in [-win_half, win_half]^2 of (S(next, u + d + q) - S(prev, u + q))^2
+ * and grad[i * m + k][2] = dloss/dd (may be NULL). 0 <= win_half <= 31. Each point's sums are
+ * reduced in a fixed order (deterministic). */
+int vs_photometric_features(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width,
+                            int32_t height, int32_t pitch, int32_t n, const float* u, const float* d, int32_t m,
+                            int32_t win_half, double* loss, double* grad, void* stream);
 
 /* Gauss-Newton refinement of n pairs from theta0: each step solves (J^T J) delta = -J^T r at the
  * current parameters and accepts theta + delta only if the loss decreases; a pair stops at its first
@@ -317,10 +325,10 @@ int vs_photometric_features(const uint8_t* prev, const uint8_t* next, int32_t wi
  * `skipped` field of vs_fit_info records (skip = &info[0].skipped, skip_stride = sizeof(vs_fit_info) / 4).
  * Outputs (device): theta_out[i * theta_stride + 0..3] (may alias theta0), loss_out[i][2] = (initial,
  * final) (may be NULL), accepted[i] = accepted steps (may be NULL). workspace: at least
- * vs_photometric_workspace(n) bytes, 8-byte aligned; no state survives the call. */
+ * vs_photometric_workspace(n, width, height) bytes, 256-byte aligned; no state survives the call.
+ * The sums are those of vs_photometric_bwd, so every decision is reproducible. */
 #define VS_PHOTO_THETA 0
 #define VS_PHOTO_FIT 1
-size_t vs_photometric_workspace(int32_t n);
 int vs_photometric_refine(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width, int32_t height,
                           int32_t pitch, int32_t n, const double* theta0, double* theta_out, int64_t theta_stride,
                           int32_t param_kind, const int32_t* skip, int64_t skip_stride, double cx, double cy, double rho,
@@ -387,7 +395,7 @@ typedef struct {
     int64_t* first_frame;      /* [1] */
     double* photo_loss;        /* [1][2], when photo_steps > 0 */
     int32_t* photo_accepted;   /* [1], when photo_steps > 0 */
-    void* photo_ws;            /* vs_photometric_workspace(1) bytes, when photo_steps > 0 */
+    void* photo_ws;            /* vs_photometric_workspace(1, width, height) bytes, when photo_steps > 0 */
     size_t photo_ws_bytes;
     uint8_t* out;              /* [out_slots][height][width] */
     void* ready_event;         /* optional hipEvent_t (NULL: none), recorded on `stream` by every

@@ -11,7 +11,10 @@
 //
 // photo_sums_kernel: a 256-thread workgroup covers a 256 x 32 tile of Omega (4 x 8 pixels per thread)
 // and accumulates the loss, the gradient, J^T J (upper triangle) and J^T r; the per-thread sums are
-// reduced over the workgroup and added to the pair's 19 accumulators with one atomic each.
+// reduced over the workgroup in a fixed order and stored as the tile's 19 partial sums in the
+// workspace. photo_reduce_kernel: one workgroup per pair adds its tiles' partials, again in a fixed
+// order (tile t goes to thread t mod 256, the threads' totals through a wave butterfly and the four
+// wave totals in sequence), so every sum is reproducible bit for bit from run to run.
 // photo_feature_kernel: one wave per point; the window's samples are spread over the lanes.
 // Refinement: per step, one sums pass at the candidate parameters and one small kernel per pair that
 // accepts the candidate if its loss is lower, solves (J^T J) delta = -J^T r by Cholesky at the
@@ -69,26 +72,25 @@ __device__ __forceinline__ double sample(const Frame& f, double x, double y)
 }
 
 // Which parameters: theta_src[item * tstride] when state == nullptr, else the state's candidate
-// (pairs already stopped are skipped). Sums go to acc[item * astride] (zeroed beforehand).
+// (pairs already stopped are skipped). The tile's sums go to part[(item * tiles + tile) * NACC + k]
+// for k < 1 (loss only) or k < NACC.
 __global__ __launch_bounds__(256) void photo_sums_kernel(const uint8_t* __restrict__ prev, const uint8_t* __restrict__ next,
                                                          int64_t fstride, int W, int H, int pitch, const double* theta_src,
-                                                         int64_t tstride, PhotoState* state, double cx, double cy,
+                                                         int64_t tstride, const PhotoState* state, double cx, double cy,
                                                          double rho, int ox0, int oy0, int ox1, int oy1, int need_grad,
-                                                         double* acc, int64_t astride, int tiles_x, int tiles_y)
+                                                         double* __restrict__ part, int tiles_x, int tiles_y)
 {
     __shared__ double red[4][NACC];
     const int tiles = tiles_x * tiles_y;
     const int item = blockIdx.x / tiles, tile = blockIdx.x - item * tiles;
     const double* th;
-    double* out;
     if (state) {
         if (state[item].stopped) return;
         th = state[item].cand;
-        out = state[item].nxt;
     } else {
         th = theta_src + item * tstride;
-        out = acc + item * astride;
     }
+    double* out = part + ((int64_t)item * tiles + tile) * NACC;
     const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
     const Frame F0{prev + item * fstride, W, H, pitch}, F1{next + item * fstride, W, H, pitch};
     const double t0 = th[0], t1 = th[1], t2 = th[2], t3 = th[3];
@@ -139,8 +141,40 @@ __global__ __launch_bounds__(256) void photo_sums_kernel(const uint8_t* __restri
     __syncthreads();
     if ((int)threadIdx.x < nk) {
         const int k = threadIdx.x;
-        const double t = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
-        atomicAdd(&out[k], t);
+        out[k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+    }
+}
+
+// One workgroup per pair: the sum of its tiles' partials, in a fixed order, to the state's nxt
+// (refinement; stopped pairs are skipped) or to out[item * astride + k] (k >= nk written as 0).
+__global__ __launch_bounds__(256) void photo_reduce_kernel(const double* __restrict__ part, int tiles, int nk,
+                                                           PhotoState* state, double* out, int64_t astride)
+{
+    __shared__ double red[4][NACC];
+    const int item = blockIdx.x;
+    if (state && state[item].stopped) return;
+    double* dst = state ? state[item].nxt : out + item * astride;
+    const double* src = part + (int64_t)item * tiles * NACC;
+    double s[NACC];
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) s[k] = 0.0;
+    for (int t = threadIdx.x; t < tiles; t += 256) {
+#pragma unroll
+        for (int k = 0; k < NACC; ++k)
+            if (k < nk) s[k] += src[(int64_t)t * NACC + k];
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) {
+        if (k < nk) {
+            const double t = vs::wave_sum_d(s[k]);
+            if (lane == 0) red[wv][k] = t;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NACC) {
+        const int k = threadIdx.x;
+        dst[k] = k < nk ? (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]) : 0.0;
     }
 }
 
@@ -274,13 +308,16 @@ __global__ void refine_out_kernel(const PhotoState* st, int n, double* theta_out
     if (accepted) accepted[i] = s.accepted;
 }
 
+// one wave per point; point i of the call belongs to pair i / m
 __global__ __launch_bounds__(64) void photo_feature_kernel(const uint8_t* __restrict__ prev, const uint8_t* __restrict__ next,
-                                                           int W, int H, int pitch, const float* __restrict__ u,
-                                                           const float* __restrict__ d, int hw, double* loss, double* grad)
+                                                           int64_t fstride, int W, int H, int pitch, int m,
+                                                           const float* __restrict__ u, const float* __restrict__ d, int hw,
+                                                           double* loss, double* grad)
 {
-    const int i = blockIdx.x;
+    const int64_t i = blockIdx.x;
     const int lane = threadIdx.x;
-    const Frame F0{prev, W, H, pitch}, F1{next, W, H, pitch};
+    const int64_t pair = i / m;
+    const Frame F0{prev + pair * fstride, W, H, pitch}, F1{next + pair * fstride, W, H, pitch};
     const double ux = u[2 * i], uy = u[2 * i + 1];
     const double vx = ux + (double)d[2 * i], vy = uy + (double)d[2 * i + 1];
     const int side = 2 * hw + 1, nwin = side * side;
@@ -326,67 +363,95 @@ void sums_grid(const vs_rect* om, int& tiles_x, int& tiles_y)
     tiles_y = (oh + TH - 1) / TH;
 }
 
+// Workspace: the tiles' partial sums of every pair (room for tiles covering the whole frame), then
+// the refinement states.
+size_t part_bytes(int32_t n, int32_t w, int32_t h)
+{
+    const size_t tiles = (size_t)((w + TW - 1) / TW) * (size_t)((h + TH - 1) / TH);
+    return ((size_t)n * tiles * NACC * sizeof(double) + 255) & ~(size_t)255;
+}
+
+int check_workspace(const void* ws, size_t ws_bytes, int32_t n, int32_t w, int32_t h, const char* who)
+{
+    const size_t need = vs_photometric_workspace(n, w, h);
+    if (!ws) return vs::set_error(VS_ERR_INVALID, "%s: null workspace", who);
+    if (ws_bytes < need) return vs::set_error(VS_ERR_WORKSPACE, "%s: workspace %zu < %zu", who, ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return vs::set_error(VS_ERR_INVALID, "%s: workspace must be 256-byte aligned", who);
+    return VS_OK;
+}
+
 }  // namespace
 
 namespace {
 
 int photometric_sums(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width, int32_t height,
                      int32_t pitch, int32_t n, const double* theta, int64_t theta_stride, double cx, double cy, double rho,
-                     const vs_rect* omega, int need_grad, double* out, void* stream)
+                     const vs_rect* omega, int need_grad, double* out, void* workspace, size_t ws_bytes, void* stream)
 {
-    int e = check_common(prev, next, width, height, pitch, n, frame_stride, omega, "vs_photometric_sums");
+    const char* who = need_grad ? "vs_photometric_bwd" : "vs_photometric_fwd";
+    int e = check_common(prev, next, width, height, pitch, n, frame_stride, omega, who);
     if (e) return e;
     if (n == 0) return VS_OK;
-    if (!theta || !out) return vs::set_error(VS_ERR_INVALID, "vs_photometric_sums: null argument");
-    if (n > 1 && theta_stride < 4) return vs::set_error(VS_ERR_INVALID, "vs_photometric_sums: theta stride < 4");
-    if (!(rho > 0.0)) return vs::set_error(VS_ERR_INVALID, "vs_photometric_sums: rho must be positive");
+    if (!theta || !out) return vs::set_error(VS_ERR_INVALID, "%s: null argument", who);
+    if (n > 1 && theta_stride < 4) return vs::set_error(VS_ERR_INVALID, "%s: theta stride < 4", who);
+    if (!(rho > 0.0)) return vs::set_error(VS_ERR_INVALID, "%s: rho must be positive", who);
+    if ((e = check_workspace(workspace, ws_bytes, n, width, height, who))) return e;
     hipStream_t s = vs::as_stream(stream);
-    zero_kernel<<<(n * VS_PHOTO_SUMS + 255) / 256, 256, 0, s>>>(out, VS_PHOTO_SUMS, VS_PHOTO_SUMS, n);
-    e = vs::check_launch("vs_photometric_sums(zero)");
-    if (e) return e;
     int tiles_x, tiles_y;
     sums_grid(omega, tiles_x, tiles_y);
-    if (tiles_x * tiles_y == 0) return VS_OK;
+    if (tiles_x * tiles_y == 0) {
+        zero_kernel<<<(n * VS_PHOTO_SUMS + 255) / 256, 256, 0, s>>>(out, VS_PHOTO_SUMS, VS_PHOTO_SUMS, n);
+        return vs::check_launch(who);
+    }
+    double* part = static_cast<double*>(workspace);
     photo_sums_kernel<<<(unsigned)(n * tiles_x * tiles_y), 256, 0, s>>>(
         prev, next, frame_stride, width, height, pitch, theta, theta_stride, nullptr, cx, cy, rho, omega->x0, omega->y0,
-        omega->x1, omega->y1, need_grad != 0, out, VS_PHOTO_SUMS, tiles_x, tiles_y);
-    return vs::check_launch("vs_photometric_sums");
+        omega->x1, omega->y1, need_grad != 0, part, tiles_x, tiles_y);
+    if ((e = vs::check_launch(who))) return e;
+    photo_reduce_kernel<<<n, 256, 0, s>>>(part, tiles_x * tiles_y, need_grad ? NACC : 1, nullptr, out, VS_PHOTO_SUMS);
+    return vs::check_launch(who);
 }
 
 }  // namespace
 
 extern "C" int vs_photometric_fwd(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width,
                                   int32_t height, int32_t pitch, int32_t n, const double* theta, int64_t theta_stride,
-                                  double cx, double cy, double rho, const vs_rect* omega, double* sums, void* stream)
+                                  double cx, double cy, double rho, const vs_rect* omega, double* sums, void* workspace,
+                                  size_t ws_bytes, void* stream)
 {
     return photometric_sums(prev, next, frame_stride, width, height, pitch, n, theta, theta_stride, cx, cy, rho, omega, 0,
-                            sums, stream);
+                            sums, workspace, ws_bytes, stream);
 }
 
 extern "C" int vs_photometric_bwd(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width,
                                   int32_t height, int32_t pitch, int32_t n, const double* theta, int64_t theta_stride,
-                                  double cx, double cy, double rho, const vs_rect* omega, double* sums, void* stream)
+                                  double cx, double cy, double rho, const vs_rect* omega, double* sums, void* workspace,
+                                  size_t ws_bytes, void* stream)
 {
     return photometric_sums(prev, next, frame_stride, width, height, pitch, n, theta, theta_stride, cx, cy, rho, omega, 1,
-                            sums, stream);
+                            sums, workspace, ws_bytes, stream);
 }
 
-extern "C" int vs_photometric_features(const uint8_t* prev, const uint8_t* next, int32_t width, int32_t height,
-                                       int32_t pitch, const float* u, const float* d, int32_t m, int32_t win_half,
-                                       double* loss, double* grad, void* stream)
+extern "C" int vs_photometric_features(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width,
+                                       int32_t height, int32_t pitch, int32_t n, const float* u, const float* d, int32_t m,
+                                       int32_t win_half, double* loss, double* grad, void* stream)
 {
-    if (m < 0 || width <= 0 || height <= 0 || pitch < width)
-        return vs::set_error(VS_ERR_INVALID, "vs_photometric_features: bad size");
-    if (win_half < 0 || win_half > 31) return vs::set_error(VS_ERR_INVALID, "vs_photometric_features: win_half 0..31");
-    if (m == 0) return VS_OK;
-    if (!prev || !next || !u || !d || !loss) return vs::set_error(VS_ERR_INVALID, "vs_photometric_features: null argument");
-    photo_feature_kernel<<<m, 64, 0, vs::as_stream(stream)>>>(prev, next, width, height, pitch, u, d, win_half, loss, grad);
-    return vs::check_launch("vs_photometric_features");
+    const char* who = "vs_photometric_features";
+    if (m < 0 || n < 0 || width <= 0 || height <= 0 || pitch < width) return vs::set_error(VS_ERR_INVALID, "%s: bad size", who);
+    if (win_half < 0 || win_half > 31) return vs::set_error(VS_ERR_INVALID, "%s: win_half 0..31", who);
+    if (m == 0 || n == 0) return VS_OK;
+    if (!prev || !next || !u || !d || !loss) return vs::set_error(VS_ERR_INVALID, "%s: null argument", who);
+    if (n > 1 && frame_stride < (int64_t)pitch * height) return vs::set_error(VS_ERR_INVALID, "%s: frame stride overlaps items", who);
+    if ((int64_t)n * m > 0x7fffffff) return vs::set_error(VS_ERR_INVALID, "%s: too many points", who);
+    photo_feature_kernel<<<(unsigned)((int64_t)n * m), 64, 0, vs::as_stream(stream)>>>(prev, next, frame_stride, width, height,
+                                                                                       pitch, m, u, d, win_half, loss, grad);
+    return vs::check_launch(who);
 }
 
-extern "C" size_t vs_photometric_workspace(int32_t n)
+extern "C" size_t vs_photometric_workspace(int32_t n, int32_t width, int32_t height)
 {
-    return n <= 0 ? 0 : sizeof(PhotoState) * (size_t)n;
+    if (n <= 0 || width <= 0 || height <= 0) return 0;
+    return part_bytes(n, width, height) + sizeof(PhotoState) * (size_t)n;
 }
 
 extern "C" int vs_photometric_refine(const uint8_t* prev, const uint8_t* next, int64_t frame_stride, int32_t width,
@@ -404,12 +469,10 @@ extern "C" int vs_photometric_refine(const uint8_t* prev, const uint8_t* next, i
     if (param_kind != VS_PHOTO_THETA && param_kind != VS_PHOTO_FIT)
         return vs::set_error(VS_ERR_INVALID, "vs_photometric_refine: unknown param_kind");
     if (!(rho > 0.0)) return vs::set_error(VS_ERR_INVALID, "vs_photometric_refine: rho must be positive");
-    if (ws_bytes < vs_photometric_workspace(n))
-        return vs::set_error(VS_ERR_WORKSPACE, "vs_photometric_refine: workspace %zu < %zu", ws_bytes, vs_photometric_workspace(n));
-    if (reinterpret_cast<uintptr_t>(workspace) & 7)
-        return vs::set_error(VS_ERR_INVALID, "vs_photometric_refine: workspace must be 8-byte aligned");
+    if ((e = check_workspace(workspace, ws_bytes, n, width, height, "vs_photometric_refine"))) return e;
     hipStream_t s = vs::as_stream(stream);
-    PhotoState* st = static_cast<PhotoState*>(workspace);
+    double* part = static_cast<double*>(workspace);
+    PhotoState* st = reinterpret_cast<PhotoState*>(static_cast<uint8_t*>(workspace) + part_bytes(n, width, height));
     const int nb = (n + 63) / 64;
     int tiles_x, tiles_y;
     sums_grid(omega, tiles_x, tiles_y);
@@ -420,8 +483,11 @@ extern "C" int vs_photometric_refine(const uint8_t* prev, const uint8_t* next, i
         if (tiles_x * tiles_y == 0) return VS_OK;
         photo_sums_kernel<<<(unsigned)(n * tiles_x * tiles_y), 256, 0, s>>>(
             prev, next, frame_stride, width, height, pitch, nullptr, 0, st, cx, cy, rho, omega->x0, omega->y0, omega->x1,
-            omega->y1, 1, nullptr, 0, tiles_x, tiles_y);
-        return vs::check_launch("vs_photometric_refine(sums)");
+            omega->y1, 1, part, tiles_x, tiles_y);
+        const int e1 = vs::check_launch("vs_photometric_refine(sums)");
+        if (e1) return e1;
+        photo_reduce_kernel<<<n, 256, 0, s>>>(part, tiles_x * tiles_y, NACC, st, nullptr, 0);
+        return vs::check_launch("vs_photometric_refine(reduce)");
     };
     if ((e = pass())) return e;
     refine_first_kernel<<<nb, 64, 0, s>>>(st, n);

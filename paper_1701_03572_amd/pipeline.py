@@ -58,7 +58,7 @@ class _PhotoRefiner:
         n = max(n_pairs_max, 1)
         self.loss = torch.zeros((n, 2), dtype=torch.float64, device=device)
         self.accepted = torch.zeros(n, dtype=torch.int32, device=device)
-        self.ws_bytes = V.vs_photometric_workspace(n)
+        self.ws_bytes = V.vs_photometric_workspace(n, w, h)
         self.ws = _bytes(self.ws_bytes, device)
 
     def __call__(self, prev, nxt, frame_stride: int, n: int, pair_params, info, first_pair: int = 0):

@@ -126,12 +126,12 @@ _SIGS = {
     "vs_warp_frame": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64,
                                 C.c_int32, C.c_int32, C.c_int32, _P]),
     "vs_photometric_fwd": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64,
-                                     C.c_double, C.c_double, C.c_double, C.POINTER(vs_rect), _P, _P]),
+                                     C.c_double, C.c_double, C.c_double, C.POINTER(vs_rect), _P, _P, C.c_size_t, _P]),
     "vs_photometric_bwd": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64,
-                                     C.c_double, C.c_double, C.c_double, C.POINTER(vs_rect), _P, _P]),
-    "vs_photometric_features": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.c_int32, _P, _P, C.c_int32, C.c_int32, _P,
-                                          _P, _P]),
-    "vs_photometric_workspace": (C.c_size_t, [C.c_int32]),
+                                     C.c_double, C.c_double, C.c_double, C.POINTER(vs_rect), _P, _P, C.c_size_t, _P]),
+    "vs_photometric_features": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P,
+                                          C.c_int32, C.c_int32, _P, _P, _P]),
+    "vs_photometric_workspace": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
     "vs_photometric_refine": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P,
                                         C.c_int64, C.c_int32, _P, C.c_int64, C.c_double, C.c_double, C.c_double,
                                         C.POINTER(vs_rect), C.c_int32, _P, _P, _P, C.c_size_t, _P]),
@@ -314,27 +314,30 @@ def vs_warp_frame(src, src_stride: int, width: int, height: int, src_pitch: int,
 
 
 def vs_photometric_fwd(prev, nxt, frame_stride: int, width: int, height: int, pitch: int, n: int, theta,
-                       theta_stride: int, cx: float, cy: float, rho: float, omega: vs_rect, sums, stream=None):
+                       theta_stride: int, cx: float, cy: float, rho: float, omega: vs_rect, sums, workspace,
+                       ws_bytes: int, stream=None):
     _check(load().vs_photometric_fwd(_ptr(prev), _ptr(nxt), frame_stride, width, height, pitch, n, _ptr(theta),
-                                     theta_stride, cx, cy, rho, C.byref(omega), _ptr(sums), _stream(stream)),
-           "vs_photometric_fwd")
+                                     theta_stride, cx, cy, rho, C.byref(omega), _ptr(sums), _ptr(workspace), ws_bytes,
+                                     _stream(stream)), "vs_photometric_fwd")
 
 
 def vs_photometric_bwd(prev, nxt, frame_stride: int, width: int, height: int, pitch: int, n: int, theta,
-                       theta_stride: int, cx: float, cy: float, rho: float, omega: vs_rect, sums, stream=None):
+                       theta_stride: int, cx: float, cy: float, rho: float, omega: vs_rect, sums, workspace,
+                       ws_bytes: int, stream=None):
     _check(load().vs_photometric_bwd(_ptr(prev), _ptr(nxt), frame_stride, width, height, pitch, n, _ptr(theta),
-                                     theta_stride, cx, cy, rho, C.byref(omega), _ptr(sums), _stream(stream)),
-           "vs_photometric_bwd")
+                                     theta_stride, cx, cy, rho, C.byref(omega), _ptr(sums), _ptr(workspace), ws_bytes,
+                                     _stream(stream)), "vs_photometric_bwd")
 
 
-def vs_photometric_features(prev, nxt, width: int, height: int, pitch: int, u, d, m: int, win_half: int, loss,
-                            grad=None, stream=None):
-    _check(load().vs_photometric_features(_ptr(prev), _ptr(nxt), width, height, pitch, _ptr(u), _ptr(d), m, win_half,
-                                          _ptr(loss), _ptr(grad), _stream(stream)), "vs_photometric_features")
+def vs_photometric_features(prev, nxt, frame_stride: int, width: int, height: int, pitch: int, n: int, u, d, m: int,
+                            win_half: int, loss, grad=None, stream=None):
+    _check(load().vs_photometric_features(_ptr(prev), _ptr(nxt), frame_stride, width, height, pitch, n, _ptr(u),
+                                          _ptr(d), m, win_half, _ptr(loss), _ptr(grad), _stream(stream)),
+           "vs_photometric_features")
 
 
-def vs_photometric_workspace(n: int) -> int:
-    return int(load().vs_photometric_workspace(n))
+def vs_photometric_workspace(n: int, width: int, height: int) -> int:
+    return int(load().vs_photometric_workspace(n, width, height))
 
 
 VS_PHOTO_THETA, VS_PHOTO_FIT = 0, 1

@@ -1,7 +1,10 @@
 """GPU parity of the photometric check and refinement (an extension of Eq. 3 under the similarity of
 Eq. 7) against the oracle. Both sides compute in binary64, so sums agree to rounding (bar 1e-8
-relative; the survey's bar is 1e-4). The torch autograd function is checked against central finite
-differences of its own forward pass (h = 1e-3, 1e-3 relative)."""
+relative; the survey's bar is 1e-4). The sums are formed in a fixed order, so repeated calls are
+bit-identical. The torch autograd function, differentiable in the 4 similarity parameters and in
+the per-feature displacements, is checked against central finite differences of its own forward
+pass (h = 1e-3, 1e-3 relative), at 1920x1080 with 1000 features as well (the differentiation pass of
+the 1080p workload)."""
 import numpy as np
 import pytest
 import torch
@@ -56,11 +59,16 @@ def test_sums_match_oracle(w, h, n):
     s = PH.gauss_newton_terms(theta, dev(f0), dev(f1), om)
     raw = torch.empty((n, V.VS_PHOTO_SUMS), dtype=torch.float64, device="cuda")
     cx, cy, rho = PH.frame_geometry(w, h)
-    V.vs_photometric_bwd(dev(f0), dev(f1), w * h, w, h, w, n, theta, 4, cx, cy, rho, om, raw)
+    wsb = V.vs_photometric_workspace(n, w, h)
+    ws = torch.full((wsb,), 0xA5, dtype=torch.uint8, device="cuda")       # stale contents do not matter
+    V.vs_photometric_bwd(dev(f0), dev(f1), w * h, w, h, w, n, theta, 4, cx, cy, rho, om, raw, ws, wsb)
     fwd = torch.empty_like(raw)
-    V.vs_photometric_fwd(dev(f0), dev(f1), w * h, w, h, w, n, theta, 4, cx, cy, rho, om, fwd)
+    V.vs_photometric_fwd(dev(f0), dev(f1), w * h, w, h, w, n, theta, 4, cx, cy, rho, om, fwd, ws, wsb)
+    again = torch.empty_like(raw)
+    V.vs_photometric_bwd(dev(f0), dev(f1), w * h, w, h, w, n, theta, 4, cx, cy, rho, om, again, ws, wsb)
     torch.cuda.synchronize()
     raw, fwd = raw.cpu().numpy(), fwd.cpu().numpy()
+    assert np.array_equal(again.cpu().numpy().view(np.uint64), raw.view(np.uint64))   # bit-reproducible
     for i in range(n):
         ref = O.photo_global(f0[i], f1[i], th[i], rect_tuple(om))
         check_sums(raw[i], ref)
@@ -131,13 +139,136 @@ def test_empty_omega_and_bad_arguments():
     theta = torch.zeros((1, 4), dtype=torch.float64, device="cuda")
     out = torch.full((1, V.VS_PHOTO_SUMS), 7.0, dtype=torch.float64, device="cuda")
     cx, cy, rho = PH.frame_geometry(w, h)
-    V.vs_photometric_bwd(f, f, w * h, w, h, w, 1, theta, 4, cx, cy, rho, V.vs_rect(10, 10, 10, 30), out)
+    wsb = V.vs_photometric_workspace(1, w, h)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    V.vs_photometric_bwd(f, f, w * h, w, h, w, 1, theta, 4, cx, cy, rho, V.vs_rect(10, 10, 10, 30), out, ws, wsb)
     torch.cuda.synchronize()
     assert (out == 0).all()
     with pytest.raises(V.VsError):
-        V.vs_photometric_bwd(f, f, w * h, w, h, w, 1, theta, 4, cx, cy, rho, V.vs_rect(-1, 0, 10, 10), out)
-    with pytest.raises(V.VsError):
+        V.vs_photometric_bwd(f, f, w * h, w, h, w, 1, theta, 4, cx, cy, rho, V.vs_rect(-1, 0, 10, 10), out, ws, wsb)
+    with pytest.raises(V.VsError, match="workspace"):
+        V.vs_photometric_bwd(f, f, w * h, w, h, w, 1, theta, 4, cx, cy, rho, V.vs_rect(4, 4, 60, 44), out, ws, wsb - 8)
+    with pytest.raises(V.VsError, match="workspace"):
         V.vs_photometric_refine(f, f, w * h, w, h, w, 1, theta, theta.clone(), 4, V.VS_PHOTO_THETA, None, 0, cx, cy, rho,
                                 V.vs_rect(4, 4, 60, 44), 5, None, None, torch.empty(8, dtype=torch.uint8, device="cuda"),
                                 8)
-    V.vs_photometric_fwd(f, f, w * h, w, h, w, 0, theta, 4, cx, cy, rho, V.vs_rect(4, 4, 60, 44), out)   # n = 0: no-op
+    V.vs_photometric_fwd(f, f, w * h, w, h, w, 0, theta, 4, cx, cy, rho, V.vs_rect(4, 4, 60, 44), out, ws, wsb)   # n = 0
+
+
+def fd_features(prev, nxt, u, d, hstep=1e-3, win_half=10):
+    """Central differences of the GPU's per-feature loss in each displacement component, at the
+    float32 values the kernel reads (the denominator is the step actually taken)."""
+    d32 = d.to(torch.float32)
+    fd = torch.zeros(d.shape, dtype=torch.float64, device=d.device)
+    for k in range(2):
+        dp, dm = d32.clone(), d32.clone()
+        dp[..., k] += hstep
+        dm[..., k] -= hstep
+        lp = PH.photometric_losses(torch.zeros((prev.shape[0], 4), dtype=torch.float64, device=d.device), dp, prev,
+                                   nxt, V.vs_rect(0, 0, 0, 0), u, win_half)[1]
+        lm = PH.photometric_losses(torch.zeros((prev.shape[0], 4), dtype=torch.float64, device=d.device), dm, prev,
+                                   nxt, V.vs_rect(0, 0, 0, 0), u, win_half)[1]
+        fd[..., k] = (lp - lm) / (dp[..., k].double() - dm[..., k].double())
+    return fd
+
+
+def check_feature_fd(an, fd, u, d, hstep=1e-3):
+    """1e-3 relative, except components whose sample coordinates lie within 2h of an integer (a kink of
+    the bilinear interpolant: all window samples of a displacement share its fractional offset)."""
+    p = (u.double() + d.to(torch.float32).double()).cpu().numpy()
+    frac = p - np.floor(p)
+    near = (frac < 2 * hstep) | (frac > 1 - 2 * hstep)
+    an, fd = an.cpu().numpy(), fd.cpu().numpy()
+    scale = np.abs(an).max(axis=-1, keepdims=True).repeat(2, axis=-1)
+    err = np.abs(an - fd) / np.maximum(np.abs(fd), 1e-3 * scale + 1e-12)
+    ok = ~near
+    assert ok.sum() >= 0.95 * ok.size, ok.mean()
+    assert err[ok].max() <= 1e-3, (err[ok].max(), np.unravel_index(np.argmax(np.where(ok, err, 0)), err.shape))
+    return int(near.sum())
+
+
+def test_autograd_in_theta_and_displacements():
+    w, h, n, m = 256, 192, 2, 40
+    f0, f1, th = pair_batch(w, h, n, seed=9)
+    prev, nxt = dev(f0), dev(f1)
+    rng = np.random.default_rng(4)
+    u = dev(np.stack([np.column_stack([rng.uniform(15, w - 15, m), rng.uniform(15, h - 15, m)])
+                      for _ in range(n)]).astype(np.float32))
+    d = dev(rng.normal(0, 0.7, (n, m, 2)).astype(np.float32)).requires_grad_(True)
+    theta = dev(th).requires_grad_(True)
+    om = PH.omega_for(theta, w, h, extra=1)
+    lg, lf = PH.photometric_losses(theta, d, prev, nxt, om, u)
+    wg = torch.tensor([1.0, 0.5], dtype=torch.float64, device="cuda")
+    wf = dev(rng.uniform(0.5, 2.0, (n, m)))
+    ((lg * wg).sum() + (lf * wf).sum()).backward()
+    # the feature losses equal the oracle's, and so do their gradients
+    for i in range(n):
+        rl, rg = O.photo_feature(f0[i], f1[i], u[i].cpu().numpy().astype(np.float64),
+                                 d[i].detach().cpu().numpy().astype(np.float64))
+        np.testing.assert_allclose(lf[i].detach().cpu().numpy(), rl, rtol=1e-9, atol=1e-6)
+        np.testing.assert_allclose(d.grad[i].cpu().numpy(), wf[i].cpu().numpy()[:, None] * rg, rtol=1e-9,
+                                   atol=1e-6 * (np.abs(rg).max() + 1))
+    fd = fd_features(prev, nxt, u, d.detach()) * wf[..., None]
+    check_feature_fd(d.grad, fd, u, d.detach())
+    g = theta.grad.cpu().numpy()
+    hs = 1e-3
+    for k in range(4):
+        tp, tm = theta.detach().clone(), theta.detach().clone()
+        tp[:, k] += hs
+        tm[:, k] -= hs
+        fdk = (PH.photometric_loss(tp, prev, nxt, om) - PH.photometric_loss(tm, prev, nxt, om)) / (2 * hs) * wg
+        np.testing.assert_allclose(g[:, k], fdk.cpu().numpy(), rtol=1e-3, atol=1e-3 * np.abs(g).max())
+
+
+def test_differentiation_pass_at_1080p_with_1000_features():
+    """The 1080p workload's first pair: the fitted similarity's theta and the tracker's 1000 displacements
+    (dst - src), gradients of the global loss in theta and of the 1000 window losses in the 1000 x 2
+    displacements against central differences of the GPU forward (h = 1e-3, 1e-3 relative) and against
+    the oracle's analytic gradients (1e-8 relative)."""
+    from paper_1701_03572_amd import params
+    from paper_1701_03572_amd.pipeline import SequenceStabilizer
+    P = params.PRESETS["hd"]
+    sq = synth.make_sequence("hd", n_frames=2, device="cuda")
+    w, h = 1920, 1080
+    ss = SequenceStabilizer(w, h, 2, P)
+    ss.run(sq.frames, warp=False)
+    torch.cuda.synchronize()
+    cnt = int(ss.count[0].item())
+    assert cnt == 1000
+    prev, nxt = sq.frames[0:1].contiguous(), sq.frames[1:2].contiguous()
+    u = ss.src[0:1, :cnt].contiguous()
+    d = (ss.dst[0:1, :cnt] - ss.src[0:1, :cnt]).contiguous().requires_grad_(True)
+    theta = PH.theta_from_fit(ss.pair_params[0:1], w, h).requires_grad_(True)
+    om = PH.omega_for(theta, w, h, extra=1)
+    say("1080p differentiation pass: theta", theta.detach().cpu().numpy(), "omega", (om.x0, om.y0, om.x1, om.y1))
+    lg, lf = PH.photometric_losses(theta, d, prev, nxt, om, u)
+    (lg.sum() + lf.sum()).backward()
+    g = theta.grad.cpu().numpy()[0]
+    hs = 1e-3
+    fdt = np.zeros(4)
+    for k in range(4):
+        tp, tm = theta.detach().clone(), theta.detach().clone()
+        tp[0, k] += hs
+        tm[0, k] -= hs
+        fdt[k] = float((PH.photometric_loss(tp, prev, nxt, om) - PH.photometric_loss(tm, prev, nxt, om))[0]) / (2 * hs)
+    say("dL/dtheta", g, "central differences", fdt)
+    np.testing.assert_allclose(g, fdt, rtol=1e-3, atol=1e-3 * np.abs(g).max())
+    fd = fd_features(prev, nxt, u, d.detach())
+    excluded = check_feature_fd(d.grad, fd, u, d.detach())
+    say("displacement components excluded at a kink:", excluded, "of", 2 * cnt)
+    f0, f1 = prev[0].cpu().numpy(), nxt[0].cpu().numpy()
+    ref = O.photo_global(f0, f1, theta.detach().cpu().numpy()[0], (om.x0, om.y0, om.x1, om.y1))
+    np.testing.assert_allclose(g, ref["grad"], rtol=1e-8, atol=1e-9 * np.abs(ref["grad"]).max())
+    rl, rg = O.photo_feature(f0, f1, u[0].cpu().numpy().astype(np.float64), d[0].detach().cpu().numpy().astype(np.float64))
+    np.testing.assert_allclose(lf[0].detach().cpu().numpy(), rl, rtol=1e-9, atol=1e-6)
+    np.testing.assert_allclose(d.grad[0].cpu().numpy(), rg, rtol=1e-9, atol=1e-6 * (np.abs(rg).max() + 1))
+
+
+def test_refinement_is_bit_reproducible():
+    w, h, n = 320, 240, 3
+    f0, f1, th0 = pair_batch(w, h, n, seed=21)
+    om = PH.omega_for(dev(th0), w, h, extra=4)
+    a = PH.refine(dev(f0), dev(f1), dev(th0), om, max_steps=5)
+    b = PH.refine(dev(f0), dev(f1), dev(th0), om, max_steps=5)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
