@@ -8,7 +8,7 @@ resident in HBM before timing.
 
 One step = the whole hot path over the whole sequence through the segment-parallel sequence
 path (pyramids, corners, tracking, fits, smoothing, warps of all 600 frames). value = frames/s
-over the timed steps. Also reported: the plain per-frame streaming path (throughput when frames
+over the timed steps (the median of three timed runs of --steps steps each). Also reported: the plain per-frame streaming path (throughput when frames
 are pushed back to back, and per-frame compute latency p50/p99 when each frame is processed on
 arrival), the roofline of the dominant kernel measured with HIP events on its stream, and the
 CPU oracle timed on a bounded sample.
@@ -25,12 +25,21 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic FP32 work of the tracker, per 21x21 window sample (multiply and add count 1 each):
-# set-up of a window at one level: bilinear I (9), dI/dx and dI/dy (4 differences + 9 + 1 each),
-# tensor products and sums (6); one Gauss-Newton iteration: bilinear J (9), residual (1), two
-# products and sums (4).
+# algorithmic FP32 work of the tracker per 21x21 window (point x level x direction): 8 kFLOP per
+# window set-up and 5.3 kFLOP per Gauss-Newton iteration (about 18 and 12 FLOP per sample, an FMA
+# counted as 2), the figures the roofline fraction is reported in.
+LK_FLOP_SETUP = 8000.0
+LK_FLOP_ITER = 5300.0
+# the same work counted per operation of the method as written (a multiply and an add count 1 each):
+# set-up: bilinear I (9), dI/dx and dI/dy (4 differences + 9 + 1 each), tensor products and sums
+# (6); iteration: bilinear J (9), residual (1), two products and sums (4). Reported beside it.
 LK_FLOP_SETUP_PER_SAMPLE = 43
 LK_FLOP_ITER_PER_SAMPLE = 14
+# the paper's own figure (context: another machine, another workload)
+PAPER_FIGURE = {"fps": 50, "what": "Stage I (offline) average speed, motion estimation and trajectory smoothing "
+                                  "(Table 2: 34.9 to 107.8 fps per video)",
+                "hardware": "notebook with a dual-core 1.70 GHz CPU", "resolution": "320x240 to 640x480, 50 corners",
+                "cite": "Abstract; Section 7.2, Table 2"}
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 # rocprofv3 summary of this workload (kernel trace + FETCH_SIZE / WRITE_SIZE passes)
@@ -103,6 +112,58 @@ def hbm_figures(V, ss, frames, P, n: int, W: int, H: int, ms_per_step: float) ->
     return {"pyramid": fig(pyr_b, pyr_ms), "warp": fig(warp_b, warp_ms),
             "step": dict(fig(per_frame, ms_per_step), parts_per_frame={"pyramid": pyr_b, "warp": warp_b,
                                                                         "detect": det_b, "track": lk_b})}
+
+
+def differentiation_pass(V, ss, frames, P, n: int, W: int, H: int, steps: int) -> dict:
+    """The differentiation pass of the 1080p workload over every pair of the sequence: the global
+    photometric loss (vs_photometric_fwd) and its gradient, J^T J and J^T r in the 4 similarity
+    parameters (vs_photometric_bwd) at each pair's fitted similarity, and the window loss of every one
+    of the pair's 1000 features with its gradient in the 2 displacement components
+    (vs_photometric_features, d = tracked - detected position). Timed with HIP events, median of 3
+    runs of ``steps`` passes."""
+    import numpy as np
+    import torch
+    from paper_1701_03572_amd import photometric as PH
+    n_pairs = n - 1
+    cap = ss.cap
+    cx, cy, rho = PH.frame_geometry(W, H)
+    m = P.photo_margin(W, H)
+    omega = V.vs_rect(m, m, W - m, H - m)
+    theta = PH.theta_from_fit(ss.pair_params[:n_pairs], W, H).contiguous()
+    u = ss.src[:n_pairs].contiguous()
+    d = (ss.dst[:n_pairs] - ss.src[:n_pairs]).contiguous()
+    fs = W * H
+    loss = torch.empty((n_pairs, V.VS_PHOTO_SUMS), dtype=torch.float64, device="cuda")
+    sums = torch.empty_like(loss)
+    wsb = V.vs_photometric_workspace(n_pairs, W, H)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    floss = torch.empty((n_pairs, cap), dtype=torch.float64, device="cuda")
+    fgrad = torch.empty((n_pairs, cap, 2), dtype=torch.float64, device="cuda")
+
+    def one():
+        V.vs_photometric_fwd(frames, frames[1:], fs, W, H, W, n_pairs, theta, 4, cx, cy, rho, omega, loss, ws, wsb)
+        V.vs_photometric_bwd(frames, frames[1:], fs, W, H, W, n_pairs, theta, 4, cx, cy, rho, omega, sums, ws, wsb)
+        V.vs_photometric_features(frames, frames[1:], fs, W, H, W, n_pairs, u, d, cap, P.win_half, floss, fgrad)
+
+    one()
+    torch.cuda.synchronize()
+    runs = []
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            one()
+        b.record()
+        torch.cuda.synchronize()
+        runs.append(a.elapsed_time(b) / steps)
+    ms = float(np.median(runs))
+    px = (omega.x1 - omega.x0) * (omega.y1 - omega.y0)
+    return {"what": "photometric loss and its backward over all %d pairs: global loss + dL/dtheta, J^T J, J^T r over "
+                    "%dx%d pixels per pair, and %d features x 2 displacement gradients per pair (21x21 windows), "
+                    "binary64" % (n_pairs, omega.x1 - omega.x0, omega.y1 - omega.y0, cap),
+            "pairs": n_pairs, "features_per_pair": cap, "ms_per_pass": round(ms, 4),
+            "runs_ms": [round(r, 4) for r in runs], "pairs_per_s": round(n_pairs / (ms / 1e3), 1),
+            "pixels_per_s": round(2 * n_pairs * px / (ms / 1e3), 1)}
 
 
 def run_batched(n_streams: int, n_frames: int, steps: int, warmup: int, cpu_frames: int = 0) -> dict:
@@ -228,6 +289,7 @@ def main() -> int:
     ap.add_argument("--batched-streams", type=int, default=64)
     ap.add_argument("--batched-frames", type=int, default=120)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiation pass timing")
     ap.add_argument("--no-hbm", action="store_true", help="skip the extra pyramid/warp launches of the HBM figures")
     ap.add_argument("--serving-seconds", type=float, default=4.0)
     ap.add_argument("--tuning", choices=["auto", "default", "cached"], default="auto",
@@ -292,41 +354,54 @@ def main() -> int:
         ss.run(frames)
         torch.cuda.synchronize()
         log("warmup step %d done" % i)
+    # three timed runs of `steps` steps each; the reported figures are the median run's
     lk_events = []
     work = []
-    torch.cuda.synchronize()
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
+    runs_ms = []
     wall0 = time.perf_counter()
-    t_start.record()
-    for i in range(args.steps):
-        ss.run(frames, lk_events=lk_events)
-        work.append(ss.lk_work.clone())
-    t_end.record()
-    torch.cuda.synchronize()
+    for r in range(3):
+        torch.cuda.synchronize()
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        t_start.record()
+        for i in range(args.steps):
+            ss.run(frames, lk_events=lk_events)
+            work.append(ss.lk_work.clone())
+        t_end.record()
+        torch.cuda.synchronize()
+        runs_ms.append(t_start.elapsed_time(t_end))
+        log("timed run %d: %.3f ms/step" % (r, runs_ms[-1] / max(args.steps, 1)))
     wall = time.perf_counter() - wall0
-    ms_total = t_start.elapsed_time(t_end)
+    ms_total = float(np.median(runs_ms))
     ms_per_step = ms_total / max(args.steps, 1)
     fps = n * args.steps / (ms_total / 1e3)
-    log("sequence path: %.3f ms/step, %.0f frames/s (wall %.3f s)" % (ms_per_step, fps, wall))
+    log("sequence path: %.3f ms/step (median of 3 runs), %.0f frames/s (wall of the 3 runs %.3f s)" %
+        (ms_per_step, fps, wall))
 
     # roofline of the dominant kernel: the tracker (FP32 VALU bound)
     lk_ms = [a.elapsed_time(b) for a, b in lk_events]
-    w = torch.stack(work).sum(dim=2).cpu().numpy()   # [steps, 5, segments, 2] -> [steps, 5, 2]
+    w = torch.stack(work).sum(dim=2).cpu().numpy()   # [runs x steps, 5, segments, 2] -> [runs x steps, 5, 2]
     nwin = (2 * P.win_half + 1) ** 2
-    flop = (w[..., 0].astype(np.float64) * LK_FLOP_SETUP_PER_SAMPLE + w[..., 1] * LK_FLOP_ITER_PER_SAMPLE) * nwin
-    flop_per_launch = float(flop.sum() / max(len(lk_ms), 1))
+    setups, iters = float(w[..., 0].sum()), float(w[..., 1].sum())
+    n_launch = max(len(lk_ms), 1)
+    flop_per_launch = (setups * LK_FLOP_SETUP + iters * LK_FLOP_ITER) / n_launch
+    flop_per_launch_ops = (setups * LK_FLOP_SETUP_PER_SAMPLE + iters * LK_FLOP_ITER_PER_SAMPLE) * nwin / n_launch
     avg_lk_ms = float(np.mean(lk_ms)) if lk_ms else float("nan")
     achieved_tflops = flop_per_launch / (avg_lk_ms / 1e3) / 1e12
-    lk_share = float(np.sum(lk_ms) / ms_total) if ms_total > 0 else float("nan")
-    log("tracker: %.3f ms per launch avg, %.3e FLOP per launch, %.2f TFLOP/s, %.0f%% of the step" %
-        (avg_lk_ms, flop_per_launch, achieved_tflops, 100 * lk_share))
+    achieved_ops = flop_per_launch_ops / (avg_lk_ms / 1e3) / 1e12
+    lk_share = float(np.sum(lk_ms) / np.sum(runs_ms)) if runs_ms else float("nan")
+    log("tracker: %.3f ms per launch avg, %.3e FLOP per launch, %.2f TFLOP/s (%.3f of peak), %.0f%% of the step" %
+        (avg_lk_ms, flop_per_launch, achieved_tflops, achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 100 * lk_share))
     roofline = {"kernel": "lk_kernel (vs_track_lk)", "bound": "alu", "achieved": round(achieved_tflops, 4),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 5),
                 "traffic": tracker_traffic_from_profile(), "avg_launch_ms": round(avg_lk_ms, 4),
                 "flop_per_launch": flop_per_launch,
+                "flop_units": "8 kFLOP per window set-up, 5.3 kFLOP per iteration (point x level x direction)",
+                "setups_per_launch": setups / n_launch, "iterations_per_launch": iters / n_launch,
+                "achieved_per_operation_count": round(achieved_ops, 4),
+                "frac_per_operation_count": round(achieved_ops / FP32_VECTOR_PEAK_TFLOPS, 5),
                 "share_of_step": round(lk_share, 4),
-                "iterations_per_setup": float(w[..., 1].sum() / max(w[..., 0].sum(), 1))}
+                "iterations_per_setup": iters / max(setups, 1.0)}
 
     hbm = None
     if not args.no_hbm:
@@ -341,6 +416,12 @@ def main() -> int:
         torch.neg(a, out=b)
         torch.cuda.synchronize()
         del a, b
+
+    diff = None
+    if not args.no_diff:
+        diff = differentiation_pass(V, ss, frames, P, n, W, H, max(1, min(args.steps, 5)))
+        log("differentiation pass: %.3f ms over %d pairs (%.0f pairs/s)" % (diff["ms_per_pass"], diff["pairs"],
+                                                                            diff["pairs_per_s"]))
 
     plain = None
     if not args.no_plain:
@@ -413,6 +494,7 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
+        "runs_ms_per_step": [round(r / max(args.steps, 1), 4) for r in runs_ms],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -423,12 +505,14 @@ def main() -> int:
                    "path": "sequence (segment-parallel, one launch per stage per 5-frame step)",
                    "frames": n, "width": W, "height": H, "corners": P.max_corners, "levels": P.levels},
         "plain_path": plain,
+        "differentiation_pass": diff,
         "batched": batched,
         "serving": serving,
         "tuning": tuning,
         "roofline": roofline,
         "hbm": hbm,
         "cpu_baseline": cpu,
+        "paper": PAPER_FIGURE,
     }
     print(json.dumps(out))
     return 0
