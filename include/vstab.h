@@ -401,6 +401,10 @@ typedef struct {
     void* ready_event;         /* optional hipEvent_t (NULL: none), recorded on `stream` by every
                                   push once the frames it emits are written, before the re-detection
                                   that only serves the next pair */
+    const uint8_t* ring;       /* batched use (vs_batch_push): the stream's frames, frame j at
+                                  ring + (j % ring_len) * width * height (16-byte aligned; NULL otherwise) */
+    int32_t ring_len;          /* >= lag + 2 when ring is set */
+    int32_t ring_pad;
     /* progress, maintained by the library */
     int64_t next_frame;        /* index of the next pushed frame */
     int64_t emitted;           /* frames emitted so far */
@@ -410,6 +414,54 @@ typedef struct {
 int vs_stream_reset(vs_stream* s, void* stream);
 int vs_stream_push(vs_stream* s, const uint8_t* frame, int64_t* first_emitted, int32_t* n_emitted, void* stream);
 int vs_stream_flush(vs_stream* s, int64_t* first_emitted, int32_t* n_emitted, void* stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * batch_push -- the real-time version of Section 6 for many streams at once: one call processes the
+ * next frame of every listed stream of a batch with ONE launch per stage (pyramids, tracking with the
+ * backward check, fits with the dwell switch and skip rule, the smoother's step, the warps of the
+ * emitted frames, the re-detections), the stages and their order being those of vs_stream_push. Every
+ * stream's outputs are those vs_stream_push gives on the same frames, bit for bit.
+ * A batch is one class of streams: same geometry, capacity and parameters except the corner budget
+ * (detect.max_corners), the RANSAC seed and the stream id (fit.seed, fit.stream_id), which are per
+ * stream. The prototype given to vs_batch_init fixes the class; photometric refinement is not part of
+ * the batched step (photo_steps must be 0).
+ * Each stream keeps its own vs_stream struct and device buffers (as for vs_stream_push, plus a frame
+ * ring: frame j must be at ring + (j % ring_len) * width * height when the push that processes it
+ * runs, and stay there until emitted). vs_batch_attach resets the stream (frame 0 next) and records
+ * its buffers in a device descriptor in the batch workspace; from then on the stream advances only
+ * through vs_batch_push until vs_batch_detach; vs_stream_flush ends it as usual (its state is the
+ * single-stream one).
+ * vs_batch_push(b, n, slots, first_emitted, n_emitted, stream): items are the n distinct attached
+ * slots (host array); first_emitted[k] / n_emitted[k] (host) receive the index and count (0 or 1) of
+ * the frames item k emits: frame e is in out + (e % out_slots) * width * height once the stream reaches
+ * the call's end (and ready_event, when set, is recorded after the warps, before the re-detections).
+ * The device work depends only on the slots (each stream's frame counter is kept on the device), so a
+ * push over a fixed slot list may be captured in a graph and replayed once per frame: the capture
+ * advances the host progress once; after k replays call vs_batch_note_replayed(b, n, slots, k - 1).
+ * workspace (device, 256-byte aligned): vs_batch_workspace(proto, max_streams, detect_chunk) bytes:
+ * descriptors, the step's slot list, the fit workspace of max_streams pairs and the detection
+ * workspace of detect_chunk frames (the detection runs in chunks of that many items).
+ * Errors: VS_ERR_INVALID for a bad slot, a slot listed twice, a stream of another class, a missing or
+ * misaligned ring or pyramid; nothing is enqueued then. */
+#define VS_BATCH_MAX_STREAMS 256
+typedef struct {
+    vs_stream proto;           /* the class: geometry and shared parameters (copied by vs_batch_init) */
+    int32_t max_streams;       /* descriptor slots, <= VS_BATCH_MAX_STREAMS */
+    int32_t detect_chunk;      /* items per detection launch */
+    void* workspace;           /* device */
+    size_t ws_bytes;
+    void* ready_event;         /* optional hipEvent_t recorded after each push's warps (NULL: none) */
+    vs_stream* attached[VS_BATCH_MAX_STREAMS];   /* host: the stream of each slot (NULL: free) */
+} vs_batch;
+
+size_t vs_batch_workspace(const vs_stream* proto, int32_t max_streams, int32_t detect_chunk);
+int vs_batch_init(vs_batch* b, const vs_stream* proto, int32_t max_streams, int32_t detect_chunk, void* workspace,
+                  size_t ws_bytes);
+int vs_batch_attach(vs_batch* b, int32_t slot, vs_stream* s, void* stream);
+int vs_batch_detach(vs_batch* b, int32_t slot);
+int vs_batch_push(vs_batch* b, int32_t n, const int32_t* slots, int64_t* first_emitted, int32_t* n_emitted,
+                  void* stream);
+int vs_batch_note_replayed(vs_batch* b, int32_t n, const int32_t* slots, int32_t steps);
 
 /* ---------------------------------------------------------------------------------------------
  * tuning -- launch-shape choices that change speed only, never a result bit (the choices only

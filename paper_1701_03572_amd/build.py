@@ -22,7 +22,7 @@ ARCH = os.environ.get("VSTAB_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["common.hip", "pyramid.hip", "corners.hip", "lk.hip", "fit.hip", "smooth.hip", "warp.hip", "photometric.hip",
-           "stream.hip"]
+           "stream.hip", "batch.hip"]
 NO_CONTRACT = {"fit.hip", "smooth.hip", "corners.hip", "photometric.hip"}
 
 BASE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

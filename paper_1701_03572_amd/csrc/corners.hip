@@ -80,16 +80,64 @@ __device__ __forceinline__ uint4* raw_of(uint8_t* ws, int64_t item_bytes, int it
     return reinterpret_cast<uint4*>(ws + item * item_bytes + HDR + 12 * (int64_t)w * h);
 }
 
-__device__ __forceinline__ bool gated_off(const int32_t* gate, int gate_min, int64_t rec)
-{
-    return gate != nullptr && gate[rec] >= gate_min;
-}
+// Item addressing of a strided call: item i reads frames + i * frame_stride and owns the records
+// g = i * istride; it is skipped when gate[g] >= gate_min.
+struct Strided {
+    const uint8_t* frames;
+    int64_t frame_stride;
+    int istride;
+    const int32_t* gate;
+    int gate_min;
+    const int32_t* k_items;
+    int capacity;
+    float* xy;
+    double* score;
+    int32_t* count;
+    uint8_t* alive;
+    __device__ __forceinline__ bool off(int i) const { return gate != nullptr && gate[(int64_t)i * istride] >= gate_min; }
+    __device__ __forceinline__ const uint8_t* img(int i) const { return frames + i * frame_stride; }
+    __device__ __forceinline__ int budget(int i, int Kmax) const
+    {
+        if (!k_items) return Kmax;
+        const int k = k_items[i];
+        return k < 0 ? 0 : (k < Kmax ? k : Kmax);
+    }
+    __device__ __forceinline__ int64_t rec(int i) const { return (int64_t)i * istride; }
+    __device__ __forceinline__ float* xy_of(int i) const { return xy + rec(i) * capacity * 2; }
+    __device__ __forceinline__ double* score_of(int i) const { return score ? score + rec(i) * capacity : nullptr; }
+    __device__ __forceinline__ int32_t* count_of(int i) const { return count + rec(i); }
+    __device__ __forceinline__ uint8_t* alive_of(int i) const { return alive + rec(i) * capacity; }
+};
 
-__global__ void detect_init_kernel(uint8_t* ws, int64_t item_bytes, int n, int istride, const int32_t* gate,
-                                   int gate_min)
+// Item addressing of a batched step: frame j of the item's stream, detected on at j = 0 and every
+// redetect_every frames, otherwise only when the pair just tracked has fewer than min_valid valid
+// points; the corners go to the stream's point record [j & 1] (the points tracked from frame j).
+struct Step {
+    vs::StepView v;
+    __device__ __forceinline__ bool off(int i) const
+    {
+        const vs::StepStream& d = v.s(i);
+        const int64_t j = d.next_frame;
+        return j != 0 && j % v.redetect_every != 0 && *d.n_valid >= v.min_valid;
+    }
+    __device__ __forceinline__ const uint8_t* img(int i) const { return v.frame(i, v.j(i)); }
+    __device__ __forceinline__ int budget(int i, int Kmax) const
+    {
+        const int k = v.s(i).max_corners;
+        return k < 0 ? 0 : (k < Kmax ? k : Kmax);
+    }
+    __device__ __forceinline__ int cur(int i) const { return (int)(v.j(i) & 1); }
+    __device__ __forceinline__ float* xy_of(int i) const { return v.s(i).pts + (int64_t)cur(i) * v.capacity * 2; }
+    __device__ __forceinline__ double* score_of(int) const { return nullptr; }
+    __device__ __forceinline__ int32_t* count_of(int i) const { return v.s(i).count; }
+    __device__ __forceinline__ uint8_t* alive_of(int i) const { return v.s(i).alive + (int64_t)cur(i) * v.capacity; }
+};
+
+template <class IO>
+__global__ void detect_init_kernel(uint8_t* ws, int64_t item_bytes, int n, IO io)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || gated_off(gate, gate_min, (int64_t)i * istride)) return;
+    if (i >= n || io.off(i)) return;
     CandHeader* h = hdr_of(ws, item_bytes, i);
     h->count = 0;
     h->raw_count = 0;
@@ -302,17 +350,16 @@ __device__ __forceinline__ void resp_step(RespState& st, uint32_t P, int t, cons
     }
 }
 
-__global__ __launch_bounds__(256) void corner_response_kernel(const uint8_t* __restrict__ frames, int64_t frame_stride,
-                                                              int W, int H, int pitch, int mx, int my, int n_items,
-                                                              int strips, int segs, int sr, int istride,
-                                                              const int32_t* gate, int gate_min, uint8_t* ws,
+template <class IO>
+__global__ __launch_bounds__(256) void corner_response_kernel(IO io, int W, int H, int pitch, int mx, int my, int n_items,
+                                                              int strips, int segs, int sr, uint8_t* ws,
                                                               int64_t item_bytes)
 {
     const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);   // one independent wave per (item, strip, segment)
     const int per_item = strips * segs;
     const int item = gw / per_item;
     if (item >= n_items) return;
-    if (gated_off(gate, gate_min, (int64_t)item * istride)) return;
+    if (io.off(item)) return;
     const int rem = gw - item * per_item;
     const int seg = rem / strips, strip = rem - seg * strips;
 
@@ -331,7 +378,7 @@ __global__ __launch_bounds__(256) void corner_response_kernel(const uint8_t* __r
     // pixel rows are read through a buffer descriptor: rows or columns past the image read as 0 and
     // only feed estimates outside the ROI, which the NMS ignores
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<uint8_t*>(frames + item * frame_stride), (short)0, pitch * H, 0x00020000);
+        const_cast<uint8_t*>(io.img(item)), (short)0, pitch * H, 0x00020000);
     auto load_row = [&](int yp) -> uint32_t {
         return __builtin_amdgcn_raw_buffer_load_b32(rs, yp * pitch + cx.xb, 0, 0);
     };
@@ -373,19 +420,18 @@ __global__ __launch_bounds__(256) void corner_response_kernel(const uint8_t* __r
 }
 
 // Exact scores of the survivors; flagged ones get the exact NMS against their in-ROI neighbours.
-__global__ __launch_bounds__(256) void corner_keys_kernel(const uint8_t* __restrict__ frames, int64_t frame_stride,
-                                                          int W, int H, int pitch, int mx, int my, int istride,
-                                                          const int32_t* gate, int gate_min, uint8_t* ws,
+template <class IO>
+__global__ __launch_bounds__(256) void corner_keys_kernel(IO io, int W, int H, int pitch, int mx, int my, uint8_t* ws,
                                                           int64_t item_bytes)
 {
     const int item = blockIdx.y;
-    if (gated_off(gate, gate_min, (int64_t)item * istride)) return;
+    if (io.off(item)) return;
     CandHeader* hd = hdr_of(ws, item_bytes, item);
     const uint32_t nraw = hd->raw_count;
     const uint4* raw = raw_of(ws, item_bytes, item, W, H);
     uint64_t* keys = keys_of(ws, item_bytes, item);
     uint32_t* idx = idx_of(ws, item_bytes, item, W, H);
-    const uint8_t* img = frames + item * frame_stride;
+    const uint8_t* img = io.img(item);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int rx0 = mx, rx1 = W - mx, ry0 = my, ry1 = H - my;
     __shared__ uint32_t s_wcnt[4], s_base;
@@ -481,23 +527,16 @@ __device__ __forceinline__ void for_each_key(const uint64_t* keys, const uint32_
     }
 }
 
-__global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_t item_bytes, int W, int H,
-                                                             int istride, const int32_t* gate, int gate_min, int Kmax,
-                                                             const int32_t* k_items, double quality, int min_dist,
-                                                             int capacity, float* __restrict__ xy_out,
-                                                             double* __restrict__ score_out,
-                                                             int32_t* __restrict__ count_out,
-                                                             uint8_t* __restrict__ alive_out)
+template <class IO>
+__global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_t item_bytes, int W, int H, IO io,
+                                                             int Kmax, double quality, int min_dist, int capacity)
 {
     const int item = blockIdx.x;
-    const int64_t rec = (int64_t)item * istride;
-    if (gated_off(gate, gate_min, rec)) return;
+    if (io.off(item)) return;
     // per-item corner budget, clamped to [0, Kmax]
-    int K = Kmax;
-    if (k_items) {
-        const int k = k_items[item];
-        K = k < 0 ? 0 : (k < Kmax ? k : Kmax);
-    }
+    const int K = io.budget(item, Kmax);
+    float* __restrict__ xy_out = io.xy_of(item);
+    double* __restrict__ score_out = io.score_of(item);
     __shared__ uint64_t bkey[CAP];
     __shared__ uint32_t bidx[CAP];
     __shared__ uint32_t hist[NBIN];
@@ -727,11 +766,10 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
                     const int rank = na + rank_in;
                     acc_x[rank] = cx;
                     acc_y[rank] = cy;
-                    float* o = xy_out + (rec * capacity + rank) * 2;
+                    float* o = xy_out + rank * 2;
                     o[0] = (float)cx;
                     o[1] = (float)cy;
-                    if (score_out)
-                        score_out[rec * capacity + rank] = __longlong_as_double((long long)bkey[g0 + lane]);
+                    if (score_out) score_out[rank] = __longlong_as_double((long long)bkey[g0 + lane]);
                 }
                 if (lane == 0) s_nacc = na + min(__popcll(acc), allowed);
                 // stage the next group
@@ -753,8 +791,52 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
     }
     __syncthreads();
     const int na = s_nacc;
-    for (int k = tid; k < capacity; k += 1024) alive_out[rec * capacity + k] = k < na ? 1 : 0;
-    if (tid == 0) count_out[rec] = na;
+    uint8_t* alive_out = io.alive_of(item);
+    for (int k = tid; k < capacity; k += 1024) alive_out[k] = k < na ? 1 : 0;
+    if (tid == 0) *io.count_of(item) = na;
+}
+
+// the four detection launches over n items
+template <class IO>
+int launch_detect(const IO& io, int n, int width, int height, int pitch, const vs_detect_params& p, int Kmax,
+                  int capacity, uint8_t* w8, hipStream_t s)
+{
+    const int64_t ib = per_item_bytes(width, height);
+    detect_init_kernel<<<(n + 255) / 256, 256, 0, s>>>(w8, ib, n, io);
+    int e = vs::check_launch("vs_detect_corners(init)");
+    if (e) return e;
+    const int rw = width - 2 * p.roi_mx, rh = height - 2 * p.roi_my;
+    // each output row belongs to one wave's segment and the survivors are sorted afterwards, so the
+    // segment height only trades per-wave warm-up rows against waves per frame
+    const int sr = n <= 8 ? SR_FEW : SR;
+    const int strips = (rw + SW - 1) / SW, segs = (rh + sr - 1) / sr;
+    const int64_t nwaves = (int64_t)n * strips * segs;
+    corner_response_kernel<<<(unsigned)((nwaves + 3) / 4), 256, 0, s>>>(io, width, height, pitch, p.roi_mx, p.roi_my, n,
+                                                                      strips, segs, sr, w8, ib);
+    e = vs::check_launch("vs_detect_corners(response)");
+    if (e) return e;
+    // survivors are a small fraction of the ROI: 32 blocks per item stride over them (256 for
+    // batches of at most 8 frames)
+    corner_keys_kernel<<<dim3(n <= 8 ? 256 : 32, n), 256, 0, s>>>(io, width, height, pitch, p.roi_mx, p.roi_my, w8, ib);
+    e = vs::check_launch("vs_detect_corners(keys)");
+    if (e) return e;
+    corner_select_kernel<<<n, 1024, 0, s>>>(w8, ib, width, height, io, Kmax, p.quality, p.min_dist, capacity);
+    return vs::check_launch("vs_detect_corners(select)");
+}
+
+int check_detect(const vs_detect_params& p, int width, int height, int pitch, int capacity)
+{
+    if (width < 8 || height < 8 || pitch < width) return vs::set_error(VS_ERR_INVALID, "vs_detect_corners: bad size");
+    if (capacity > VS_MAX_CORNERS) return vs::set_error(VS_ERR_UNSUPPORTED, "vs_detect_corners: capacity > %d", VS_MAX_CORNERS);
+    if (p.max_corners < 0 || p.max_corners > capacity || capacity <= 0)
+        return vs::set_error(VS_ERR_INVALID, "vs_detect_corners: need 0 <= max_corners <= capacity");
+    if (p.roi_mx < 2 || p.roi_my < 2 || width - 2 * p.roi_mx <= 0 || height - 2 * p.roi_my <= 0)
+        return vs::set_error(VS_ERR_INVALID, "vs_detect_corners: ROI margins must be >= 2 and leave a non-empty ROI");
+    if (p.min_dist < 0 || !(p.quality >= 0.0) || p.quality > 1.0)
+        return vs::set_error(VS_ERR_INVALID, "vs_detect_corners: bad min_dist or quality");
+    if ((int64_t)pitch * height >= (int64_t)1 << 31)
+        return vs::set_error(VS_ERR_UNSUPPORTED, "vs_detect_corners: frame too large");
+    return VS_OK;
 }
 
 }  // namespace
@@ -772,50 +854,35 @@ extern "C" int vs_detect_corners(const uint8_t* frames, int64_t frame_stride, in
 {
     if (!p || (n > 0 && (!frames || !xy || !count || !alive || !workspace)))
         return vs::set_error(VS_ERR_INVALID, "vs_detect_corners: null argument");
-    if (n < 0 || istride < 1 || width < 8 || height < 8 || pitch < width)
-        return vs::set_error(VS_ERR_INVALID, "vs_detect_corners: bad size");
-    if (capacity > VS_MAX_CORNERS) return vs::set_error(VS_ERR_UNSUPPORTED, "vs_detect_corners: capacity > %d", VS_MAX_CORNERS);
-    if (p->max_corners < 0 || p->max_corners > capacity || capacity <= 0)
-        return vs::set_error(VS_ERR_INVALID, "vs_detect_corners: need 0 <= max_corners <= capacity");
-    if (p->roi_mx < 2 || p->roi_my < 2 || width - 2 * p->roi_mx <= 0 || height - 2 * p->roi_my <= 0)
-        return vs::set_error(VS_ERR_INVALID, "vs_detect_corners: ROI margins must be >= 2 and leave a non-empty ROI");
-    if (p->min_dist < 0 || !(p->quality >= 0.0) || p->quality > 1.0)
-        return vs::set_error(VS_ERR_INVALID, "vs_detect_corners: bad min_dist or quality");
+    if (n < 0 || istride < 1) return vs::set_error(VS_ERR_INVALID, "vs_detect_corners: bad size");
+    int e = check_detect(*p, width, height, pitch, capacity);
+    if (e) return e;
     if (n == 0) return VS_OK;
     if (n > 65535) return vs::set_error(VS_ERR_INVALID, "vs_detect_corners: more than 65535 items");
     if (n > 1 && frame_stride < (int64_t)pitch * height)
         return vs::set_error(VS_ERR_INVALID, "vs_detect_corners: frame stride overlaps items");
-    if ((int64_t)pitch * height >= (int64_t)1 << 31)
-        return vs::set_error(VS_ERR_UNSUPPORTED, "vs_detect_corners: frame too large");
     const size_t need = vs_detect_workspace(width, height, n);
     if (ws_bytes < need) return vs::set_error(VS_ERR_WORKSPACE, "vs_detect_corners: workspace %zu < %zu", ws_bytes, need);
     if (reinterpret_cast<uintptr_t>(workspace) & 255)
         return vs::set_error(VS_ERR_INVALID, "vs_detect_corners: workspace must be 256-byte aligned");
-    hipStream_t s = vs::as_stream(stream);
-    const int64_t ib = per_item_bytes(width, height);
-    uint8_t* w8 = static_cast<uint8_t*>(workspace);
-    detect_init_kernel<<<(n + 255) / 256, 256, 0, s>>>(w8, ib, n, istride, gate, gate_min);
-    int e = vs::check_launch("vs_detect_corners(init)");
-    if (e) return e;
-    const int rw = width - 2 * p->roi_mx, rh = height - 2 * p->roi_my;
-    // each output row belongs to one wave's segment and the survivors are sorted afterwards, so the
-    // segment height only trades per-wave warm-up rows against waves per frame
-    const int sr = n <= 8 ? SR_FEW : SR;
-    const int strips = (rw + SW - 1) / SW, segs = (rh + sr - 1) / sr;
-    const int64_t nwaves = (int64_t)n * strips * segs;
-    corner_response_kernel<<<(unsigned)((nwaves + 3) / 4), 256, 0, s>>>(frames, frame_stride, width, height, pitch,
-                                                                      p->roi_mx, p->roi_my, n, strips, segs, sr,
-                                                                      istride, gate, gate_min, w8, ib);
-    e = vs::check_launch("vs_detect_corners(response)");
-    if (e) return e;
-    // survivors are a small fraction of the ROI: 32 blocks per item stride over them (256 for
-    // batches of at most 8 frames)
-    corner_keys_kernel<<<dim3(n <= 8 ? 256 : 32, n), 256, 0, s>>>(frames, frame_stride, width, height, pitch, p->roi_mx, p->roi_my,
-                                                   istride, gate, gate_min, w8, ib);
-    e = vs::check_launch("vs_detect_corners(keys)");
-    if (e) return e;
-    corner_select_kernel<<<n, 1024, 0, s>>>(w8, ib, width, height, istride, gate, gate_min, p->max_corners,
-                                            p->max_corners_per_item, p->quality,
-                                            p->min_dist, capacity, xy, score, count, alive);
-    return vs::check_launch("vs_detect_corners(select)");
+    const Strided io{frames, frame_stride, istride, gate, gate_min, p->max_corners_per_item, capacity, xy, score, count,
+                     alive};
+    return launch_detect(io, n, width, height, pitch, *p, p->max_corners, capacity, static_cast<uint8_t*>(workspace),
+                         vs::as_stream(stream));
 }
+
+namespace vs {
+
+// the detection of every item of a batched step (items whose detection is not due return at once);
+// the workspace holds vs_detect_workspace(W, H, n) bytes
+int step_detect(const StepView& v, int n, int W, int H, const vs_detect_params& p, uint8_t* ws, hipStream_t s)
+{
+    if (n <= 0) return VS_OK;
+    vs_detect_params q = p;
+    q.max_corners = v.capacity;   // each stream's own budget applies (clamped to the capacity)
+    const int e = check_detect(q, W, H, W, v.capacity);
+    if (e) return e;
+    return launch_detect(Step{v}, n, W, H, W, q, v.capacity, v.capacity, ws, s);
+}
+
+}  // namespace vs

@@ -423,13 +423,74 @@ __device__ __forceinline__ int model_of(int mode, int mi)
 
 __host__ __device__ __forceinline__ int models_in(int mode) { return mode == VS_HYBRID3 ? 3 : mode == VS_HYBRID ? 2 : 1; }
 
+// Point records of one fitted item: its slots, pair index and RANSAC stream.
+struct FitItem {
+    const float* src;
+    const float* dst;
+    const uint8_t* valid;
+    int64_t pair;
+    uint64_t seed;
+    int64_t stream_id;
+};
+
+// item i of a strided call: pair pair_index0 + i, records at i * capacity
+struct Strided {
+    const float* src;
+    const float* dst;
+    const uint8_t* valid;
+    int capacity;
+    int64_t pair_index0;
+    double* params;
+    double* affine6;
+    vs_fit_info* info;
+    uint8_t* inliers;
+    __device__ __forceinline__ bool at(int i, const FitArgs& a, FitItem& it) const
+    {
+        const int64_t k = (int64_t)i * capacity;
+        it.src = src + 2 * k;
+        it.dst = dst + 2 * k;
+        it.valid = valid + k;
+        it.pair = pair_index0 + i;
+        it.seed = a.seed;
+        it.stream_id = a.stream_id;
+        return true;
+    }
+    __device__ __forceinline__ double* params_of(int i) const { return params + 4 * (int64_t)i; }
+    __device__ __forceinline__ double* affine6_of(int i) const { return affine6 ? affine6 + 6 * (int64_t)i : nullptr; }
+    __device__ __forceinline__ vs_fit_info* info_of(int i) const { return info + i; }
+    __device__ __forceinline__ uint8_t* inliers_of(int i) const { return inliers ? inliers + (int64_t)i * capacity : nullptr; }
+};
+
+// item i of a batched step: pair j - 1 of its stream (none at j = 0), the points tracked from frame
+// j - 1 (record [(j - 1) & 1]) to the tracker's outputs, the stream's own RANSAC seed and stream id
+struct Step {
+    vs::StepView v;
+    __device__ __forceinline__ bool at(int i, const FitArgs&, FitItem& it) const
+    {
+        const vs::StepStream& d = v.s(i);
+        const int64_t j = d.next_frame;
+        if (j == 0) return false;
+        const int prv = (int)((j - 1) & 1);
+        it.src = d.pts + (int64_t)prv * v.capacity * 2;
+        it.dst = d.dst;
+        it.valid = d.status;
+        it.pair = j - 1;
+        it.seed = d.seed;
+        it.stream_id = d.stream_id;
+        return true;
+    }
+    __device__ __forceinline__ double* params_of(int i) const { return v.s(i).pair_params; }
+    __device__ __forceinline__ double* affine6_of(int i) const { return v.s(i).affine6; }
+    __device__ __forceinline__ vs_fit_info* info_of(int i) const { return v.s(i).info; }
+    __device__ __forceinline__ uint8_t* inliers_of(int i) const { return v.s(i).inliers; }
+};
+
 // Kernel 1a (fit_hyp): workgroup (pair, s) of `split` per pair scores the hypotheses h = s, s + split,
 // ... of every requested model (wave w takes h = s + split (w + 4k)) and records its best in the
 // pair's workspace record. Splitting a pair's hypotheses over several workgroups shortens the
 // dependent FP64 chains when there are few pairs.
-__global__ __launch_bounds__(NT, 3) void fit_hyp_kernel(const float* __restrict__ src, const float* __restrict__ dst,
-                                                     const uint8_t* __restrict__ valid, int capacity, FitArgs a,
-                                                     int64_t pair_index0, int split, uint8_t* ws)
+template <class IO>
+__global__ __launch_bounds__(NT, 3) void fit_hyp_kernel(IO io, int capacity, FitArgs a, int split, uint8_t* ws)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char pair_lds[];
     const int capA = lds_cap(capacity);
@@ -442,9 +503,13 @@ __global__ __launch_bounds__(NT, 3) void fit_hyp_kernel(const float* __restrict_
     __shared__ double w_model[4][6];
     const int item = blockIdx.x / split, sp = blockIdx.x - item * split;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int64_t pair = pair_index0 + item;
+    FitItem it;
+    if (!io.at(item, a, it)) return;
+    a.seed = it.seed;
+    a.stream_id = it.stream_id;
+    const int64_t pair = it.pair;
     HypRec* hyp = reinterpret_cast<HypRec*>(ws + item * rec_bytes(capacity) + hyp_offset(capacity));
-    const int n = compact_valid(src, dst, valid, (int64_t)item * capacity, capacity, xs, ys, xd, yd, nullptr, red4);
+    const int n = compact_valid(it.src, it.dst, it.valid, 0, capacity, xs, ys, xd, yd, nullptr, red4);
     const int nm = models_in(a.model);
     for (int mi = 0; mi < nm; ++mi) {
         const int model = model_of(a.model, mi);
@@ -474,9 +539,8 @@ __global__ __launch_bounds__(NT, 3) void fit_hyp_kernel(const float* __restrict_
     }
 }
 
-__global__ __launch_bounds__(NT, 3) void fit_pair_kernel(const float* __restrict__ src, const float* __restrict__ dst,
-                                                      const uint8_t* __restrict__ valid, int capacity, FitArgs a,
-                                                      int64_t pair_index0, int split, uint8_t* ws)
+template <class IO>
+__global__ __launch_bounds__(NT, 3) void fit_pair_kernel(IO io, int capacity, FitArgs a, int split, uint8_t* ws)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char pair_lds[];
     const int capA = lds_cap(capacity);
@@ -495,12 +559,13 @@ __global__ __launch_bounds__(NT, 3) void fit_pair_kernel(const float* __restrict
     // one workgroup per (pair, model): the hybrid's candidates are fitted side by side
     const int n_models = models_in(a.model);
     const int item = blockIdx.x / n_models, mi = blockIdx.x - item * n_models, t = threadIdx.x;
+    FitItem it;
+    if (!io.at(item, a, it)) return;
     PairRec* rec = reinterpret_cast<PairRec*>(ws + item * rec_bytes(capacity));
     uint8_t* masks = ws + item * rec_bytes(capacity) + 256;
-    const int64_t base = (int64_t)item * capacity;
     const int model = model_of(a.model, mi);
 
-    const int n = compact_valid(src, dst, valid, base, capacity, xs, ys, xd, yd, slot_of, red4);
+    const int n = compact_valid(it.src, it.dst, it.valid, 0, capacity, xs, ys, xd, yd, slot_of, red4);
     const HypRec* hyp = reinterpret_cast<const HypRec*>(ws + item * rec_bytes(capacity) + hyp_offset(capacity));
     uint8_t* mk = masks + slot_of_model(model) * cap_aligned(capacity);
     for (int k = t; k < cap_aligned(capacity); k += NT) mk[k] = 0;
@@ -681,11 +746,15 @@ __global__ __launch_bounds__(NT) void fit_resolve_kernel(int n, int capacity, Fi
 // One workgroup per pair: writes the chosen model's parameters (an affine as its nearest
 // similarity, a = (a11 + a22) / 2, b = (a21 - a12) / 2), the 2x3 matrices (optional), info record
 // and inlier flags.
-__global__ __launch_bounds__(NT) void fit_emit_kernel(int capacity, int32_t model_mode, const uint8_t* ws,
-                                                      double* __restrict__ params, double* __restrict__ affine6,
-                                                      vs_fit_info* __restrict__ info, uint8_t* __restrict__ inliers)
+template <class IO>
+__global__ __launch_bounds__(NT) void fit_emit_kernel(int capacity, int32_t model_mode, const uint8_t* ws, IO io,
+                                                      FitArgs a)
 {
     const int i = blockIdx.x, t = threadIdx.x;
+    FitItem it;
+    if (!io.at(i, a, it)) return;
+    double* __restrict__ affine6 = io.affine6_of(i);
+    uint8_t* __restrict__ inliers = io.inliers_of(i);
     const PairRec* rec = reinterpret_cast<const PairRec*>(ws + i * rec_bytes(capacity));
     const int ch = rec->pad[0];
     if (t == 0) {
@@ -697,7 +766,7 @@ __global__ __launch_bounds__(NT) void fit_emit_kernel(int capacity, int32_t mode
         f.err_rigid = __longlong_as_double(0x7ff8000000000000ll);
         f.err_sim = f.err_rigid;
         f.err_affine = f.err_rigid;
-        double* po = params + 4 * (int64_t)i;
+        double* po = io.params_of(i);
         double m6[6] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0};
         if (ch < 0) {
             f.model = -1 - ch;
@@ -725,14 +794,51 @@ __global__ __launch_bounds__(NT) void fit_emit_kernel(int capacity, int32_t mode
             }
         }
         if (affine6)
-            for (int k = 0; k < 6; ++k) affine6[6 * (int64_t)i + k] = m6[k];
-        info[i] = f;
+            for (int k = 0; k < 6; ++k) affine6[k] = m6[k];
+        *io.info_of(i) = f;
     }
     if (inliers) {
         const uint8_t* mk = ws + i * rec_bytes(capacity) + 256 + (ch < 0 ? 0 : slot_of_model(ch)) * cap_aligned(capacity);
-        uint8_t* o = inliers + (int64_t)i * capacity;
-        for (int k = t; k < capacity; k += NT) o[k] = ch < 0 ? 0 : mk[k];
+        for (int k = t; k < capacity; k += NT) inliers[k] = ch < 0 ? 0 : mk[k];
     }
+}
+
+// The dwell-block state machine for a batched step: item i fits one pair (j - 1) of its own stream,
+// so each item is resolved alone by one thread, exactly as fit_resolve_kernel resolves a call of one
+// pair: a hybrid block is decided at its first non-skipped pair (unless the state already decided
+// it); the model in force is carried otherwise.
+__global__ void fit_resolve_step_kernel(int n, int capacity, FitArgs a, vs::StepView v, uint8_t* ws)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    vs::StepStream& d = v.s(i);
+    if (d.next_frame == 0) return;
+    const int64_t pair = d.next_frame - 1;
+    PairRec* rec = reinterpret_cast<PairRec*>(ws + i * rec_bytes(capacity));
+    const bool hybrid = a.model == VS_HYBRID || a.model == VS_HYBRID3;
+    const int64_t dw = a.dwell > 0 ? a.dwell : 1;
+    const int64_t blk = pair / dw;
+    vs_fit_state st = *d.fit_state;
+    const bool done = st.block == blk && st.decided;
+    int m = a.model, dh = 0;
+    if (hybrid) {
+        m = st.model;
+        if (!done && !rec->skipped) {
+            m = decide(a.model, rec->m[0].err, rec->m[1].err, rec->m[2].err);
+            dh = 1;
+        }
+    }
+    rec->pad[0] = rec->skipped ? -1 - m : m;   // a skipped pair is the identity under the reported model
+    rec->pad[1] = dh;
+    if (st.block != blk) {
+        st.block = blk;
+        st.decided = 0;
+    }
+    if (hybrid) {
+        st.model = m;
+        if (dh) st.decided = 1;
+    }
+    *d.fit_state = st;
 }
 
 __global__ void fit_state_init_kernel(vs_fit_state* s)
@@ -797,24 +903,52 @@ int launch_fit(const char* who, const float* src, const float* dst, const uint8_
     const size_t lds = pair_lds_bytes(capacity);
     if (lds > 65536) {
         // capacities above ~3400 points need more than the default 64 KiB of dynamic LDS
-        hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(&fit_pair_kernel),
+        hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(&fit_pair_kernel<Strided>),
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (he == hipSuccess)
-            he = hipFuncSetAttribute(reinterpret_cast<const void*>(&fit_hyp_kernel),
+            he = hipFuncSetAttribute(reinterpret_cast<const void*>(&fit_hyp_kernel<Strided>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (he != hipSuccess) return vs::set_error(VS_ERR_HIP, "%s: %s", who, hipGetErrorString(he));
     }
     // spread each pair's hypotheses over workgroups until about 2048 are in flight (up to MAX_SPLIT
     // per pair): the scoring loops are chains of dependent FP64 operations, hidden only by other waves
     const int split = a.iters > 0 ? std::min(std::max((2048 + n - 1) / n, 1), MAX_SPLIT) : 1;
-    fit_hyp_kernel<<<n * split, NT, lds, s>>>(src, dst, valid, capacity, a, pair_index0, split, w8);
+    const Strided io{src, dst, valid, capacity, pair_index0, params, affine6, info, inliers};
+    fit_hyp_kernel<<<n * split, NT, lds, s>>>(io, capacity, a, split, w8);
     int e = vs::check_launch(who);
     if (e) return e;
-    fit_pair_kernel<<<n * models_in(a.model), NT, lds, s>>>(src, dst, valid, capacity, a, pair_index0, split, w8);
+    fit_pair_kernel<<<n * models_in(a.model), NT, lds, s>>>(io, capacity, a, split, w8);
     if ((e = vs::check_launch(who))) return e;
     fit_resolve_kernel<<<1, NT, 0, s>>>(n, capacity, a, pair_index0, state, w8);
     if ((e = vs::check_launch(who))) return e;
-    fit_emit_kernel<<<n, NT, 0, s>>>(capacity, a.model, w8, params, affine6, info, inliers);
+    fit_emit_kernel<<<n, NT, 0, s>>>(capacity, a.model, w8, io, a);
+    return vs::check_launch(who);
+}
+
+// the fit of every item of a batched step with j > 0
+int launch_fit_step(const vs::StepView& v, int n, const FitArgs& a, uint8_t* w8, hipStream_t s)
+{
+    const char* who = "vs_batch_push(fit)";
+    const int capacity = v.capacity;
+    const size_t lds = pair_lds_bytes(capacity);
+    if (lds > 65536) {
+        hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(&fit_pair_kernel<Step>),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (he == hipSuccess)
+            he = hipFuncSetAttribute(reinterpret_cast<const void*>(&fit_hyp_kernel<Step>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (he != hipSuccess) return vs::set_error(VS_ERR_HIP, "%s: %s", who, hipGetErrorString(he));
+    }
+    const Step io{v};
+    const int split = a.iters > 0 ? std::min(std::max((2048 + n - 1) / n, 1), MAX_SPLIT) : 1;
+    fit_hyp_kernel<<<n * split, NT, lds, s>>>(io, capacity, a, split, w8);
+    int e = vs::check_launch(who);
+    if (e) return e;
+    fit_pair_kernel<<<n * models_in(a.model), NT, lds, s>>>(io, capacity, a, split, w8);
+    if ((e = vs::check_launch(who))) return e;
+    fit_resolve_step_kernel<<<(n + 63) / 64, 64, 0, s>>>(n, capacity, a, v, w8);
+    if ((e = vs::check_launch(who))) return e;
+    fit_emit_kernel<<<n, NT, 0, s>>>(capacity, a.model, w8, io, a);
     return vs::check_launch(who);
 }
 
@@ -905,3 +1039,24 @@ extern "C" int vs_fit_similarity(const float* src, const float* dst, const uint8
     return vs_fit_motion(src, dst, valid, capacity, n, p, pair_index0, state, params, nullptr, info, inliers, workspace,
                          ws_bytes, stream);
 }
+
+namespace vs {
+
+size_t step_fit_workspace(int n, int capacity) { return vs_fit_workspace(n, capacity); }
+
+int step_fit(const StepView& v, int n, const vs_fit_params& p, uint8_t* ws, hipStream_t s)
+{
+    if (n <= 0) return VS_OK;
+    FitArgs a;
+    // the point pointers are only checked for null: the step's come from the descriptors
+    const float one = 0.f;
+    const uint8_t flag = 0;
+    const vs_fit_state st{};
+    const double prm = 0.0;
+    const vs_fit_info inf{};
+    const int e = check_fit_args("vs_batch_push(fit)", &one, &one, &flag, v.capacity, n, &p, 0, &st, &prm, &inf, &a);
+    if (e) return e;
+    return launch_fit_step(v, n, a, ws, s);
+}
+
+}  // namespace vs

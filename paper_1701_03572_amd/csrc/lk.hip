@@ -475,15 +475,81 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
     return ok;
 }
 
-template <int RMAX>
-__global__ __launch_bounds__(256) void lk_kernel(const uint8_t* __restrict__ prev_frames,
-                                                const uint8_t* __restrict__ prev_pyrs,
-                                                const uint8_t* __restrict__ next_frames,
-                                                const uint8_t* __restrict__ next_pyrs, int64_t frame_stride,
-                                                int64_t pyr_stride, int istride, vs::LevelDesc d, const float* xy_prev,
-                                                const uint8_t* alive_prev, int capacity, LKConst c, int fb,
-                                                float fb_thresh, float* xy_next, uint8_t* status, float* fb_err,
-                                                int32_t* n_valid, float* xy_chain, uint8_t* alive_chain,
+// what one tracked item reads and writes; slot k's point is xy_prev[2k], its outputs at index k
+struct LkItem {
+    const uint8_t *fa, *pa, *fb, *pb;   // previous frame and pyramid, next frame and pyramid
+    const float* xy_prev;
+    const uint8_t* alive_prev;
+    float* xy_next;
+    uint8_t* status;
+    float* fb_err;
+    int32_t* n_valid;
+    float* xy_chain;
+    uint8_t* alive_chain;
+};
+
+// item i of a strided call: frames and pyramids at i * stride, records at g = i * istride
+struct Strided {
+    const uint8_t *prev_frames, *prev_pyrs, *next_frames, *next_pyrs;
+    int64_t frame_stride, pyr_stride;
+    int istride, capacity;
+    const float* xy_prev;
+    const uint8_t* alive_prev;
+    float* xy_next;
+    uint8_t* status;
+    float* fb_err;
+    int32_t* n_valid;
+    float* xy_chain;
+    uint8_t* alive_chain;
+    __device__ __forceinline__ bool at(int i, LkItem& it) const
+    {
+        const int64_t g = (int64_t)i * istride, k = g * capacity;
+        it.fa = prev_frames + i * frame_stride;
+        it.pa = prev_pyrs + i * pyr_stride;
+        it.fb = next_frames + i * frame_stride;
+        it.pb = next_pyrs + i * pyr_stride;
+        it.xy_prev = xy_prev + 2 * k;
+        it.alive_prev = alive_prev ? alive_prev + k : nullptr;
+        it.xy_next = xy_next + 2 * k;
+        it.status = status + k;
+        it.fb_err = fb_err ? fb_err + k : nullptr;
+        it.n_valid = n_valid ? n_valid + g : nullptr;
+        it.xy_chain = xy_chain ? xy_chain + 2 * k : nullptr;
+        it.alive_chain = alive_chain ? alive_chain + k : nullptr;
+        return true;
+    }
+};
+
+// item i of a batched step: the pair (frame j - 1, frame j) of its stream, skipped at j = 0; the
+// points tracked from frame j - 1 sit at [(j - 1) & 1] of the stream's point records, the tracked
+// points are chained to [j & 1]
+struct Step {
+    vs::StepView v;
+    __device__ __forceinline__ bool at(int i, LkItem& it) const
+    {
+        const vs::StepStream& d = v.s(i);
+        const int64_t j = d.next_frame;
+        if (j == 0) return false;
+        const int cur = (int)(j & 1), prv = cur ^ 1;
+        const int64_t cap = v.capacity;
+        it.fa = v.frame(i, j - 1);
+        it.pa = d.pyr + prv * v.pyr_bytes;
+        it.fb = v.frame(i, j);
+        it.pb = d.pyr + cur * v.pyr_bytes;
+        it.xy_prev = d.pts + prv * cap * 2;
+        it.alive_prev = d.alive + prv * cap;
+        it.xy_next = d.dst;
+        it.status = d.status;
+        it.fb_err = d.fb_err;
+        it.n_valid = d.n_valid;
+        it.xy_chain = d.pts + cur * cap * 2;
+        it.alive_chain = d.alive + cur * cap;
+        return true;
+    }
+};
+
+template <int RMAX, class A>
+__global__ __launch_bounds__(256) void lk_kernel(A io, vs::LevelDesc d, int capacity, LKConst c, int fb, float fb_thresh,
                                                 unsigned long long* work, int n_items, int by_xcd)
 {
     // each wave of the workgroup tracks one point slot on its own (no barriers): slot = group *
@@ -496,6 +562,8 @@ __global__ __launch_bounds__(256) void lk_kernel(const uint8_t* __restrict__ pre
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
     const int slot = group * ppg + wave;
     if (slot >= capacity) return;
+    LkItem it;
+    if (!io.at(item, it)) return;
     const int lane = threadIdx.x & 63;
     extern __shared__ float lk_lds[];
     float* red = lk_lds + wave * WAVE_LDS_FLOATS;
@@ -503,37 +571,32 @@ __global__ __launch_bounds__(256) void lk_kernel(const uint8_t* __restrict__ pre
     red[RED_FLOATS + lane] = 0.f;
     if (lane < ZERO_FLOATS - 64) red[RED_FLOATS + 64 + lane] = 0.f;
     wave_lds_sync();
-    const int64_t rec = (int64_t)item * istride;
-    const int64_t k = rec * capacity + slot;
-    const float ux = xy_prev[2 * k], uy = xy_prev[2 * k + 1];
-    const bool alive = alive_prev ? alive_prev[k] != 0 : true;
+    const int k = slot;
+    const float ux = it.xy_prev[2 * k], uy = it.xy_prev[2 * k + 1];
+    const bool alive = it.alive_prev ? it.alive_prev[k] != 0 : true;
     float vx = ux, vy = uy, err = __int_as_float(0x7fc00000);
     bool ok = false;
     uint32_t n_setup = 0, n_iter = 0;
     if (alive) {
-        const uint8_t* fa = prev_frames + item * frame_stride;
-        const uint8_t* pa = prev_pyrs + item * pyr_stride;
-        const uint8_t* fb_ = next_frames + item * frame_stride;
-        const uint8_t* pb = next_pyrs + item * pyr_stride;
-        ok = track_one<RMAX>(fa, pa, fb_, pb, d, c, ux, uy, vx, vy, n_setup, n_iter, red);
+        ok = track_one<RMAX>(it.fa, it.pa, it.fb, it.pb, d, c, ux, uy, vx, vy, n_setup, n_iter, red);
         if (ok && fb) {
             float bx = vx, by = vy;
-            const bool okb = track_one<RMAX>(fb_, pb, fa, pa, d, c, vx, vy, bx, by, n_setup, n_iter, red);
+            const bool okb = track_one<RMAX>(it.fb, it.pb, it.fa, it.pa, d, c, vx, vy, bx, by, n_setup, n_iter, red);
             err = sqrtf((bx - ux) * (bx - ux) + (by - uy) * (by - uy));
             ok = okb && err <= fb_thresh;
         }
     }
     if (lane == 0) {
-        xy_next[2 * k] = vx;
-        xy_next[2 * k + 1] = vy;
-        status[k] = ok ? 1 : 0;
-        if (fb_err) fb_err[k] = err;
-        if (xy_chain) {
-            xy_chain[2 * k] = vx;
-            xy_chain[2 * k + 1] = vy;
+        it.xy_next[2 * k] = vx;
+        it.xy_next[2 * k + 1] = vy;
+        it.status[k] = ok ? 1 : 0;
+        if (it.fb_err) it.fb_err[k] = err;
+        if (it.xy_chain) {
+            it.xy_chain[2 * k] = vx;
+            it.xy_chain[2 * k + 1] = vy;
         }
-        if (alive_chain) alive_chain[k] = ok ? 1 : 0;
-        if (ok && n_valid) atomicAdd(&n_valid[rec], 1);
+        if (it.alive_chain) it.alive_chain[k] = ok ? 1 : 0;
+        if (ok && it.n_valid) atomicAdd(it.n_valid, 1);
         if (work && n_setup) {   // per-item counters: one address per item keeps the atomics uncontended
             atomicAdd(&work[2 * item], (unsigned long long)n_setup);
             atomicAdd(&work[2 * item + 1], (unsigned long long)n_iter);
@@ -551,7 +614,70 @@ __global__ void zero_counters(int32_t* p, int n, int istride, unsigned long long
     }
 }
 
+LKConst lk_const(const vs_lk_params& p)
+{
+    LKConst c;
+    c.hw = p.win_half;
+    c.cols = 2 * c.hw + 1;
+    c.groups = 64 / c.cols;
+    c.rows = (c.cols + c.groups - 1) / c.groups;
+    c.nwin = c.cols * c.cols;
+    c.max_iter = p.max_iter;
+    c.eps2 = p.eps * p.eps;
+    c.full = c.groups * c.rows == c.cols && c.rows == (c.rows <= 7 ? 7 : 16);
+    c.eig_thr = (float)(4.0 * (double)p.min_eig * (double)c.nwin);
+    return c;
+}
+
+template <class A>
+int launch_lk(const A& io, const vs_pyramid& layout, int capacity, const LKConst& c, const vs_lk_params& p,
+              unsigned long long* wk, int n, hipStream_t s)
+{
+    const vs::LevelDesc d = vs::level_desc(layout);
+    const bool by_xcd = n >= vs::xcd_min_items(vs::XCD_LK);
+    const int ppg = vs::lk_points_per_group();
+    const int64_t nblk = vs::xcd_grid(n, (capacity + ppg - 1) / ppg, by_xcd);
+    if (nblk > 0x7fffffff) return vs::set_error(VS_ERR_INVALID, "vs_track_lk: grid too large");
+    const unsigned grid = (unsigned)nblk;
+    const unsigned threads = 64u * (unsigned)ppg;
+    const size_t lds = sizeof(float) * WAVE_LDS_FLOATS * (size_t)ppg;
+    if (c.rows <= 7)
+        lk_kernel<7, A><<<grid, threads, lds, s>>>(io, d, capacity, c, p.fb, p.fb_thresh, wk, n, by_xcd);
+    else
+        lk_kernel<16, A><<<grid, threads, lds, s>>>(io, d, capacity, c, p.fb, p.fb_thresh, wk, n, by_xcd);
+    return vs::check_launch("vs_track_lk");
+}
+
+// checks shared by the tracking entry points
+int check_lk(const vs_pyramid& layout, const vs_lk_params& p, int capacity, int n)
+{
+    if (layout.levels < 1 || layout.levels > VS_MAX_LEVELS)
+        return vs::set_error(VS_ERR_UNSUPPORTED, "vs_track_lk: levels out of range");
+    if (capacity > VS_MAX_CORNERS) return vs::set_error(VS_ERR_UNSUPPORTED, "vs_track_lk: capacity > %d", VS_MAX_CORNERS);
+    if (p.win_half < 1 || p.win_half > 15) return vs::set_error(VS_ERR_UNSUPPORTED, "vs_track_lk: win_half must be 1..15");
+    if (p.max_iter < 1 || !(p.eps >= 0.f) || !(p.min_eig >= 0.f) || !(p.fb_thresh >= 0.f))
+        return vs::set_error(VS_ERR_INVALID, "vs_track_lk: bad parameters");
+    if (n > 65535) return vs::set_error(VS_ERR_INVALID, "vs_track_lk: more than 65535 items");
+    if ((int64_t)layout.pitch[0] * layout.height[0] >= ((int64_t)1 << 31) || layout.pitch[0] >= (1 << 24))
+        return vs::set_error(VS_ERR_UNSUPPORTED, "vs_track_lk: frame larger than 2 GiB or rows of 16 MiB");
+    return VS_OK;
+}
+
 }  // namespace
+
+namespace vs {
+
+// the tracking of every item of a batched step with j > 0 (its n_valid is cleared by the step's
+// set-up kernel)
+int step_track(const StepView& v, int n, const vs_pyramid& L, const vs_lk_params& p, hipStream_t s)
+{
+    if (n <= 0) return VS_OK;
+    const int e = check_lk(L, p, v.capacity, n);
+    if (e) return e;
+    return launch_lk(Step{v}, L, v.capacity, lk_const(p), p, nullptr, n, s);
+}
+
+}  // namespace vs
 
 extern "C" int vs_track_lk(const uint8_t* prev_frames, const uint8_t* prev_pyrs, const uint8_t* next_frames,
                            const uint8_t* next_pyrs, int64_t frame_stride, int64_t pyr_stride, int32_t n,
@@ -566,25 +692,9 @@ extern "C" int vs_track_lk(const uint8_t* prev_frames, const uint8_t* prev_pyrs,
         return vs::set_error(VS_ERR_INVALID, "vs_track_lk: null argument");
     if (layout->levels > 1 && (!prev_pyrs || !next_pyrs))
         return vs::set_error(VS_ERR_INVALID, "vs_track_lk: null pyramid");
-    if (layout->levels < 1 || layout->levels > VS_MAX_LEVELS)
-        return vs::set_error(VS_ERR_UNSUPPORTED, "vs_track_lk: levels out of range");
-    if (capacity > VS_MAX_CORNERS) return vs::set_error(VS_ERR_UNSUPPORTED, "vs_track_lk: capacity > %d", VS_MAX_CORNERS);
-    if (p->win_half < 1 || p->win_half > 15) return vs::set_error(VS_ERR_UNSUPPORTED, "vs_track_lk: win_half must be 1..15");
-    if (p->max_iter < 1 || !(p->eps >= 0.f) || !(p->min_eig >= 0.f) || !(p->fb_thresh >= 0.f))
-        return vs::set_error(VS_ERR_INVALID, "vs_track_lk: bad parameters");
-    if (n > 65535) return vs::set_error(VS_ERR_INVALID, "vs_track_lk: more than 65535 items");
-    if ((int64_t)layout->pitch[0] * layout->height[0] >= ((int64_t)1 << 31) || layout->pitch[0] >= (1 << 24))
-        return vs::set_error(VS_ERR_UNSUPPORTED, "vs_track_lk: frame larger than 2 GiB or rows of 16 MiB");
-    LKConst c;
-    c.hw = p->win_half;
-    c.cols = 2 * c.hw + 1;
-    c.groups = 64 / c.cols;
-    c.rows = (c.cols + c.groups - 1) / c.groups;
-    c.nwin = c.cols * c.cols;
-    c.max_iter = p->max_iter;
-    c.eps2 = p->eps * p->eps;
-    c.full = c.groups * c.rows == c.cols && c.rows == (c.rows <= 7 ? 7 : 16);
-    c.eig_thr = (float)(4.0 * (double)p->min_eig * (double)c.nwin);
+    const int ec = check_lk(*layout, *p, capacity, n);
+    if (ec) return ec;
+    const LKConst c = lk_const(*p);
     hipStream_t s = vs::as_stream(stream);
     unsigned long long* wk = reinterpret_cast<unsigned long long*>(work);
     if (n_valid || wk) {
@@ -592,21 +702,7 @@ extern "C" int vs_track_lk(const uint8_t* prev_frames, const uint8_t* prev_pyrs,
         int e = vs::check_launch("vs_track_lk(zero)");
         if (e) return e;
     }
-    const vs::LevelDesc d = vs::level_desc(*layout);
-    const bool by_xcd = n >= vs::xcd_min_items(vs::XCD_LK);
-    const int ppg = vs::lk_points_per_group();
-    const int64_t nblk = vs::xcd_grid(n, (capacity + ppg - 1) / ppg, by_xcd);
-    if (nblk > 0x7fffffff) return vs::set_error(VS_ERR_INVALID, "vs_track_lk: grid too large");
-    const unsigned grid = (unsigned)nblk;
-    const unsigned threads = 64u * (unsigned)ppg;
-    const size_t lds = sizeof(float) * WAVE_LDS_FLOATS * (size_t)ppg;
-    if (c.rows <= 7)
-        lk_kernel<7><<<grid, threads, lds, s>>>(prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride,
-                                         istride, d, xy_prev, alive_prev, capacity, c, p->fb, p->fb_thresh, xy_next,
-                                         status, fb_err, n_valid, xy_chain, alive_chain, wk, n, by_xcd);
-    else
-        lk_kernel<16><<<grid, threads, lds, s>>>(prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride,
-                                          istride, d, xy_prev, alive_prev, capacity, c, p->fb, p->fb_thresh, xy_next,
-                                          status, fb_err, n_valid, xy_chain, alive_chain, wk, n, by_xcd);
-    return vs::check_launch("vs_track_lk");
+    const Strided io{prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride, istride, capacity,
+                     xy_prev, alive_prev, xy_next, status, fb_err, n_valid, xy_chain, alive_chain};
+    return launch_lk(io, *layout, capacity, c, *p, wk, n, s);
 }

@@ -30,17 +30,39 @@ __device__ __forceinline__ int refl101_clamped(int t, int n)
     return vs::clampi(t, 0, n - 1);    // rows/columns only used by outputs past the edge
 }
 
-__global__ __launch_bounds__(256) void pyr_down_kernel(const uint8_t* __restrict__ src, int64_t src_stride,
-                                                        int src_pitch, int sw, int sh, uint8_t* __restrict__ dst,
-                                                        int64_t dst_stride, int dst_pitch, int dw, int dh, int n_items,
-                                                        int tiles_x, int tiles_y, int by_xcd, int vec_ok)
+// item i of a strided call reads src + i * src_stride and writes dst + i * dst_stride
+struct Strided {
+    const uint8_t* src;
+    int64_t src_stride;
+    uint8_t* dst;
+    int64_t dst_stride;
+    __device__ __forceinline__ const uint8_t* in(int i) const { return src + i * src_stride; }
+    __device__ __forceinline__ uint8_t* out(int i) const { return dst + i * dst_stride; }
+};
+
+// item i of a batched step: level l - 1 of the current frame's pyramid (level 0: the frame) to level l
+struct Step {
+    vs::StepView v;
+    int64_t src_off, dst_off;
+    int from_frame;
+    __device__ __forceinline__ const uint8_t* in(int i) const
+    {
+        return from_frame ? v.frame(i, v.j(i)) : v.cur_pyr(i) + src_off;
+    }
+    __device__ __forceinline__ uint8_t* out(int i) const { return v.cur_pyr(i) + dst_off; }
+};
+
+template <class A>
+__global__ __launch_bounds__(256) void pyr_down_kernel(A io, int src_pitch, int sw, int sh, int dst_pitch, int dw,
+                                                        int dh, int n_items, int tiles_x, int tiles_y, int by_xcd,
+                                                        int vec_ok)
 {
     __shared__ __attribute__((aligned(16))) uint8_t tin[IH * LP];
     int item, tile;
     if (!vs::xcd_map(blockIdx.x, n_items, tiles_x * tiles_y, by_xcd != 0, item, tile)) return;
     const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-    const uint8_t* s = src + item * src_stride;
-    uint8_t* d = dst + item * dst_stride;
+    const uint8_t* s = io.in(item);
+    uint8_t* d = io.out(item);
     const int ox = tx * TW, oy = ty * TH;
     const int ix0 = 2 * ox - 2, iy0 = 2 * oy - 2;
     const int tid = threadIdx.x;
@@ -179,11 +201,33 @@ extern "C" int vs_build_pyramid(const uint8_t* frames, int64_t frame_stride, uin
         const bool vec_ok = (spitch % 16 == 0) && (reinterpret_cast<uintptr_t>(src) % 16 == 0) &&
                             (n == 1 || sstride % 16 == 0);
         const int64_t nblk = vs::xcd_grid(n, tiles_x * tiles_y, by_xcd);
-        pyr_down_kernel<<<(unsigned)nblk, 256, 0, s>>>(src, sstride, spitch, layout->width[l - 1],
-                                                       layout->height[l - 1], pyrs + layout->offset[l], pyr_stride,
+        const Strided io{src, sstride, pyrs + layout->offset[l], pyr_stride};
+        pyr_down_kernel<<<(unsigned)nblk, 256, 0, s>>>(io, spitch, layout->width[l - 1], layout->height[l - 1],
                                                        layout->pitch[l], dw, dh, n, tiles_x, tiles_y, by_xcd, vec_ok);
         int e = vs::check_launch("vs_build_pyramid");
         if (e) return e;
     }
     return VS_OK;
 }
+
+namespace vs {
+
+// levels 1..L-1 of the current frame of every item of a batched step
+int step_pyramid(const StepView& v, int n, const vs_pyramid& L, bool vec_ok, hipStream_t s)
+{
+    if (n <= 0 || L.levels == 1) return VS_OK;
+    const bool by_xcd = n >= xcd_min_items(XCD_PYRAMID);
+    for (int l = 1; l < L.levels; ++l) {
+        const int dw = L.width[l], dh = L.height[l];
+        const int tiles_x = (dw + TW - 1) / TW, tiles_y = (dh + TH - 1) / TH;
+        const Step io{v, l == 1 ? 0 : L.offset[l - 1], L.offset[l], l == 1 ? 1 : 0};
+        const int64_t nblk = xcd_grid(n, tiles_x * tiles_y, by_xcd);
+        pyr_down_kernel<<<(unsigned)nblk, 256, 0, s>>>(io, L.pitch[l - 1], L.width[l - 1], L.height[l - 1], L.pitch[l],
+                                                       dw, dh, n, tiles_x, tiles_y, by_xcd, (l == 1 ? vec_ok : true));
+        const int e = check_launch("vs_batch_push(pyramid)");
+        if (e) return e;
+    }
+    return VS_OK;
+}
+
+}  // namespace vs

@@ -76,10 +76,44 @@ __device__ void emit_frame(const double (*ring)[4], const double (*kq)[4], const
     M[5] = z * (dy - sb * a.cx - ca * a.cy) + a.cy;
 }
 
-__global__ __launch_bounds__(256) void smooth_kernel(const double* __restrict__ pairs, int n_new, int eos, SmoothArgs a,
-                                                     TrajState* s, double* __restrict__ mats, int mats_cap,
-                                                     int32_t* n_emitted, int64_t* first_frame)
+// What one smoothing item reads and writes.
+struct SmoothItem {
+    const double* pairs;
+    int n_new;
+    TrajState* s;
+    double* mats;
+    int32_t* n_emitted;
+    int64_t* first_frame;
+};
+
+// the one stream of a vs_smooth_trajectory call
+struct Single {
+    SmoothItem it;
+    __device__ __forceinline__ SmoothItem at(int) const { return it; }
+};
+
+// item i of a batched step: the stream's pair j - 1 (none at j = 0)
+struct Step {
+    vs::StepView v;
+    __device__ __forceinline__ SmoothItem at(int i) const
+    {
+        const vs::StepStream& d = v.s(i);
+        return SmoothItem{d.pair_params, d.next_frame > 0 ? 1 : 0, static_cast<TrajState*>(d.traj_state), d.mats,
+                          d.n_emitted, d.first_frame};
+    }
+};
+
+// one workgroup per item (blockIdx.x)
+template <class IO>
+__global__ __launch_bounds__(256) void smooth_kernel(IO io, int eos, SmoothArgs a, int mats_cap)
 {
+    const SmoothItem item = io.at(blockIdx.x);
+    const double* __restrict__ pairs = item.pairs;
+    const int n_new = item.n_new;
+    TrajState* s = item.s;
+    double* __restrict__ mats = item.mats;
+    int32_t* n_emitted = item.n_emitted;
+    int64_t* first_frame = item.first_frame;
     // the ring (and Kalman outputs) live in LDS during the call; the per-pair parameter
     // conversions run in parallel, only the 4 running sums are sequential (one thread each)
     __shared__ double ring[VS_TRAJ_RING][4];
@@ -172,6 +206,30 @@ __global__ __launch_bounds__(256) void smooth_kernel(const double* __restrict__ 
     }
 }
 
+SmoothArgs smooth_args(const vs_smooth_params& p)
+{
+    SmoothArgs a;
+    a.mode = p.mode;
+    a.radius = p.radius;
+    a.ratio = p.kalman_ratio;
+    a.crop = p.crop;
+    a.cx = p.cx;
+    a.cy = p.cy;
+    return a;
+}
+
+int check_smooth(const vs_smooth_params& p)
+{
+    if (p.mode < VS_SMOOTH_CENTERED || p.mode > VS_SMOOTH_KALMAN)
+        return vs::set_error(VS_ERR_INVALID, "vs_smooth_trajectory: bad mode");
+    if (p.mode != VS_SMOOTH_KALMAN && (p.radius < 0 || 2 * p.radius + 2 > VS_TRAJ_RING))
+        return vs::set_error(VS_ERR_UNSUPPORTED, "vs_smooth_trajectory: radius must be 0..%d", (VS_TRAJ_RING - 2) / 2);
+    if (p.mode == VS_SMOOTH_KALMAN && !(p.kalman_ratio > 0.0))
+        return vs::set_error(VS_ERR_INVALID, "vs_smooth_trajectory: kalman_ratio must be > 0");
+    if (!(p.crop >= 0.0 && p.crop < 0.5)) return vs::set_error(VS_ERR_INVALID, "vs_smooth_trajectory: crop in [0, 0.5)");
+    return VS_OK;
+}
+
 }  // namespace
 
 extern "C" size_t vs_traj_state_bytes(void) { return sizeof(TrajState); }
@@ -191,22 +249,24 @@ extern "C" int vs_smooth_trajectory(const double* pair_params, int32_t n_new, in
     if (!p || !state) return vs::set_error(VS_ERR_INVALID, "vs_smooth_trajectory: null argument");
     if (n_new < 0 || mats_capacity < 0 || (n_new > 0 && !pair_params) || (mats_capacity > 0 && !mats))
         return vs::set_error(VS_ERR_INVALID, "vs_smooth_trajectory: bad counts");
-    if (p->mode < VS_SMOOTH_CENTERED || p->mode > VS_SMOOTH_KALMAN)
-        return vs::set_error(VS_ERR_INVALID, "vs_smooth_trajectory: bad mode");
-    if (p->mode != VS_SMOOTH_KALMAN && (p->radius < 0 || 2 * p->radius + 2 > VS_TRAJ_RING))
-        return vs::set_error(VS_ERR_UNSUPPORTED, "vs_smooth_trajectory: radius must be 0..%d", (VS_TRAJ_RING - 2) / 2);
-    if (p->mode == VS_SMOOTH_KALMAN && !(p->kalman_ratio > 0.0))
-        return vs::set_error(VS_ERR_INVALID, "vs_smooth_trajectory: kalman_ratio must be > 0");
-    if (!(p->crop >= 0.0 && p->crop < 0.5)) return vs::set_error(VS_ERR_INVALID, "vs_smooth_trajectory: crop in [0, 0.5)");
-    SmoothArgs a;
-    a.mode = p->mode;
-    a.radius = p->radius;
-    a.ratio = p->kalman_ratio;
-    a.crop = p->crop;
-    a.cx = p->cx;
-    a.cy = p->cy;
-    smooth_kernel<<<1, 256, 0, vs::as_stream(stream)>>>(pair_params, n_new, end_of_stream, a,
-                                                        static_cast<TrajState*>(state), mats, mats_capacity,
-                                                        n_emitted, first_frame);
+    const int e = check_smooth(*p);
+    if (e) return e;
+    const Single io{SmoothItem{pair_params, n_new, static_cast<TrajState*>(state), mats, n_emitted, first_frame}};
+    smooth_kernel<<<1, 256, 0, vs::as_stream(stream)>>>(io, end_of_stream, smooth_args(*p), mats_capacity);
     return vs::check_launch("vs_smooth_trajectory");
 }
+
+namespace vs {
+
+// the smoother's step of every item of a batched step: the pair j - 1 (j > 0) appended, the frames it
+// completes emitted to the stream's mats
+int step_smooth(const StepView& v, int n, const vs_smooth_params& p, hipStream_t s)
+{
+    if (n <= 0) return VS_OK;
+    const int e = check_smooth(p);
+    if (e) return e;
+    smooth_kernel<<<n, 256, 0, s>>>(Step{v}, 0, smooth_args(p), v.lag + 2);
+    return check_launch("vs_batch_push(smooth)");
+}
+
+}  // namespace vs

@@ -93,4 +93,70 @@ inline LevelDesc level_desc(const vs_pyramid& p)
     return d;
 }
 
+// ------------------------------------------------------------------------------------------------
+// Batched per-frame step (vs_batch_*): one launch per stage covers the current frame of every stream
+// of a batch. Each attached stream has a device descriptor (its vs_stream buffers, the parameters that
+// may differ between the streams of a batch, and a device-side frame counter); a step's items name
+// descriptor slots. Every stage reads an item's frame index from its descriptor, so a step's launches
+// are the same from one frame to the next (a captured step can be replayed).
+struct StepStream {
+    const uint8_t* ring;        // the stream's frames: frame j at ring + (j % ring_len) * plane
+    uint8_t* pyr;               // two pyramids: frame j's at pyr + (j & 1) * pyr_bytes
+    float* pts;                 // [2][capacity][2]: the points tracked from frame j at [j & 1]
+    uint8_t* alive;             // [2][capacity]
+    float* dst;                 // [capacity][2]
+    uint8_t* status;            // [capacity]
+    float* fb_err;              // [capacity]
+    int32_t* n_valid;           // [1]
+    int32_t* count;             // [1]
+    vs_fit_state* fit_state;
+    double* pair_params;        // [1][4]
+    double* affine6;            // [1][6]
+    vs_fit_info* info;          // [1]
+    uint8_t* inliers;           // [capacity]
+    void* traj_state;
+    double* mats;               // [lag + 2][6]
+    int32_t* n_emitted;
+    int64_t* first_frame;
+    uint8_t* out;               // [out_slots][plane]
+    int64_t next_frame;         // the frame the next step processes (advanced on the device)
+    int32_t ring_len;
+    int32_t out_slots;
+    int32_t max_corners;
+    int32_t pad;
+    uint64_t seed;
+    int64_t stream_id;
+};
+
+// One step's view, passed by value to its kernels: item i is the stream of descriptor slot[i].
+struct StepView {
+    StepStream* desc;
+    const int32_t* slot;        // device, [n]
+    int64_t plane;              // frame bytes (pitch = width)
+    int64_t pyr_bytes;
+    int32_t capacity;           // point slots of every stream of the batch
+    int32_t lag;                // the smoother's lag (frames)
+    int32_t redetect_every;
+    int32_t min_valid;
+
+    __device__ __forceinline__ StepStream& s(int i) const { return desc[slot[i]]; }
+    __device__ __forceinline__ int64_t j(int i) const { return desc[slot[i]].next_frame; }
+    __device__ __forceinline__ const uint8_t* frame(int i, int64_t k) const
+    {
+        const StepStream& d = desc[slot[i]];
+        return d.ring + (k % d.ring_len) * plane;
+    }
+    __device__ __forceinline__ uint8_t* cur_pyr(int i) const { return s(i).pyr + (j(i) & 1) * pyr_bytes; }
+    __device__ __forceinline__ uint8_t* prev_pyr(int i) const { return s(i).pyr + ((j(i) + 1) & 1) * pyr_bytes; }
+};
+
+// Stage launchers of the batched step (each defined next to its kernels); items [0, n) of the view.
+int step_pyramid(const StepView& v, int n, const vs_pyramid& L, bool vec_ok, hipStream_t s);
+int step_track(const StepView& v, int n, const vs_pyramid& L, const vs_lk_params& p, hipStream_t s);
+size_t step_fit_workspace(int n, int capacity);
+int step_fit(const StepView& v, int n, const vs_fit_params& p, uint8_t* ws, hipStream_t s);
+int step_smooth(const StepView& v, int n, const vs_smooth_params& p, hipStream_t s);
+int step_warp(const StepView& v, int n, int W, int H, int border, bool vec_ok, hipStream_t s);
+int step_detect(const StepView& v, int n, int W, int H, const vs_detect_params& p, uint8_t* ws, hipStream_t s);
+
 }  // namespace vs

@@ -56,12 +56,43 @@ __device__ __forceinline__ Box corner_box(float f00, float f01, float c0, float 
     return b;
 }
 
+// item i of a strided call: src + i * src_stride, matrix mats + i * mat_stride, dst + i * dst_stride
+struct Strided {
+    const uint8_t* src;
+    int64_t src_stride;
+    const double* mats;
+    int64_t mat_stride;
+    uint8_t* dst;
+    int64_t dst_stride;
+    __device__ __forceinline__ bool at(int i, const uint8_t*& s, const double*& M, uint8_t*& d) const
+    {
+        s = src + i * src_stride;
+        M = mats + i * mat_stride;
+        d = dst + i * dst_stride;
+        return true;
+    }
+};
+
+// item i of a batched step: the frame e = j - lag it emits (none while j < lag) under the matrix the
+// smoother's step just wrote to mats[0], into output slot e % out_slots
+struct Step {
+    vs::StepView v;
+    __device__ __forceinline__ bool at(int i, const uint8_t*& s, const double*& M, uint8_t*& d) const
+    {
+        const vs::StepStream& q = v.s(i);
+        const int64_t e = q.next_frame - v.lag;
+        if (e < 0) return false;
+        s = v.frame(i, e);
+        M = q.mats;
+        d = q.out + (e % q.out_slots) * v.plane;
+        return true;
+    }
+};
+
 // 5 workgroups per CU: the LDS tile (96 rows of 288 bytes) allows no more
-__global__ __launch_bounds__(256, 5) void warp_kernel(const uint8_t* __restrict__ src, int64_t src_stride, int W, int H,
-                                                      int src_pitch, const double* __restrict__ mats, int64_t mat_stride,
-                                                      uint8_t* __restrict__ dst, int64_t dst_stride, int dst_pitch,
-                                                      int border, int tiles_x, int tiles_y, int vec_ok, int n_items,
-                                                      int by_xcd)
+template <class IO>
+__global__ __launch_bounds__(256, 5) void warp_kernel(IO io, int W, int H, int src_pitch, int dst_pitch, int border,
+                                                      int tiles_x, int tiles_y, int vec_ok, int n_items, int by_xcd)
 {
     __shared__ __attribute__((aligned(16))) uint8_t tin[MAXR * LW];
     // the tiles of one frame run on one XCD, so the halo rows of vertically adjacent tiles are
@@ -72,17 +103,19 @@ __global__ __launch_bounds__(256, 5) void warp_kernel(const uint8_t* __restrict_
     const int ox = tx * TW, oy = ty * TH;
     const int x4 = ox + (threadIdx.x & 63) * 4;
     const int ybase = oy + (threadIdx.x >> 6) * RPT;
-    const double* M = mats + item * mat_stride;
+    const uint8_t* s;
+    const double* M;
+    uint8_t* dst;
+    if (!io.at(item, s, M, dst)) return;
     const double rdet = 1.0 / (M[0] * M[4] - M[1] * M[3]);
     const double i00 = M[4] * rdet, i01 = -M[1] * rdet, i10 = -M[3] * rdet, i11 = M[0] * rdet;
     const double i02 = -(i00 * M[2] + i01 * M[5]);
     const double i12 = -(i10 * M[2] + i11 * M[5]);
     const float f00 = (float)i00, f01 = (float)i01;
     const float f10 = (float)i10, f11 = (float)i11;
-    const uint8_t* s = src + item * src_stride;
     const int nx = W - x4 < 4 ? W - x4 : 4;      // <= 0 for threads past the right edge
     const int ny = H - ybase < RPT ? H - ybase : RPT;
-    uint8_t* drow = dst + item * dst_stride + (int64_t)ybase * dst_pitch + x4;
+    uint8_t* drow = dst + (int64_t)ybase * dst_pitch + x4;
     const bool word_store = nx == 4 && (reinterpret_cast<uintptr_t>(drow) & 3) == 0 && (dst_pitch & 3) == 0;
     const int xe = (ox + TW < W ? ox + TW : W) - 1, ye = (oy + TH < H ? oy + TH : H) - 1;
 
@@ -233,8 +266,24 @@ extern "C" int vs_warp_frame(const uint8_t* src, int64_t src_stride, int32_t wid
     // 16-byte staging loads need 16-byte aligned rows in every item
     const int vec_ok = (src_pitch % 16 == 0) && (reinterpret_cast<uintptr_t>(src) % 16 == 0) &&
                        (n == 1 || src_stride % 16 == 0);
-    warp_kernel<<<(unsigned)nblk, 256, 0, vs::as_stream(stream)>>>(src, src_stride, width, height, src_pitch, mats,
-                                                                   mat_stride, dst, dst_stride, dst_pitch, border,
+    const Strided io{src, src_stride, mats, mat_stride, dst, dst_stride};
+    warp_kernel<<<(unsigned)nblk, 256, 0, vs::as_stream(stream)>>>(io, width, height, src_pitch, dst_pitch, border,
                                                                    tiles_x, tiles_y, vec_ok, n, by_xcd);
     return vs::check_launch("vs_warp_frame");
 }
+
+namespace vs {
+
+// the warp of the frame each item of a batched step emits (items emitting nothing return at once)
+int step_warp(const StepView& v, int n, int W, int H, int border, bool vec_ok, hipStream_t s)
+{
+    if (n <= 0) return VS_OK;
+    const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
+    const bool by_xcd = n >= xcd_min_items(XCD_WARP);
+    const int64_t nblk = xcd_grid(n, tiles_x * tiles_y, by_xcd);
+    if (nblk > 0x7fffffff) return set_error(VS_ERR_INVALID, "vs_batch_push: warp grid too large");
+    warp_kernel<<<(unsigned)nblk, 256, 0, s>>>(Step{v}, W, H, W, W, border, tiles_x, tiles_y, vec_ok ? 1 : 0, n, by_xcd);
+    return check_launch("vs_batch_push(warp)");
+}
+
+}  // namespace vs

@@ -189,6 +189,18 @@ class SequenceStabilizer:
         }
 
 
+def stream_struct(width: int, height: int, P: StabParams, layout, capacity: int, out_slots: int) -> V.vs_stream:
+    """A vs_stream with the geometry and parameters of a stream (no buffers)."""
+    s = V.vs_stream()
+    s.width, s.height, s.layout = width, height, layout
+    s.detect, s.lk = _detect_params(P, width, height), _lk_params(P)
+    s.fit, s.smooth = _fit_params(P, width, height), _smooth_params(P, width, height)
+    s.capacity, s.redetect_every, s.min_valid, s.border = capacity, P.redetect_every, P.min_valid, P.border
+    s.out_slots = out_slots
+    s.photo_steps = max(P.photometric_steps, 0)
+    return s
+
+
 class Stabilizer:
     """Plain per-frame streaming path. ``push`` enqueues all work for one frame on the current
     stream through one native call (``vs_stream_push``) and returns the indices and output views of
@@ -197,12 +209,18 @@ class Stabilizer:
     that serves the next pair is enqueued after the emitted frames' warps; a ``ready`` event given
     to ``push`` is recorded between the two, when the call's outputs are written."""
 
-    def __init__(self, width: int, height: int, P: StabParams, device="cuda", out_slots: int | None = None):
+    def __init__(self, width: int, height: int, P: StabParams, device="cuda", out_slots: int | None = None,
+                 capacity: int | None = None, ring=None):
+        """capacity: point slots (default P.max_corners). ring: only for a stream advanced by a
+        ``StreamBatch``: the number of frames of a device frame ring to allocate (frame j goes to
+        ring[j % len]), or a uint8 device tensor [k, H, W] that already holds the stream's frames
+        (frame j at [j % k], e.g. a resident sequence). Batch members need no workspaces of their own."""
         self.W, self.H, self.P = width, height, P
         self.dev = torch.device(device)
         dev = self.dev
         self.layout = V.vs_pyramid_layout(width, height, width, P.levels)
-        self.cap = cap = P.max_corners
+        self.cap = cap = capacity or P.max_corners
+        self.batched = ring is not None
         self.pyr = _bytes(2 * self.layout.bytes, dev)
         self.pts = torch.zeros((2, cap, 2), dtype=torch.float32, device=dev)
         self.alive = torch.zeros((2, cap), dtype=torch.uint8, device=dev)
@@ -211,10 +229,10 @@ class Stabilizer:
         self.fb_err = torch.zeros(cap, dtype=torch.float32, device=dev)
         self.n_valid = torch.zeros(1, dtype=torch.int32, device=dev)
         self.count = torch.zeros(1, dtype=torch.int32, device=dev)
-        self.det_ws_bytes = V.vs_detect_workspace(width, height, 1)
-        self.det_ws = _bytes(self.det_ws_bytes, dev)
-        self.fit_ws_bytes = V.vs_fit_workspace(1, cap)
-        self.fit_ws = _bytes(self.fit_ws_bytes, dev)
+        self.det_ws_bytes = 0 if self.batched else V.vs_detect_workspace(width, height, 1)
+        self.det_ws = None if self.batched else _bytes(self.det_ws_bytes, dev)
+        self.fit_ws_bytes = 0 if self.batched else V.vs_fit_workspace(1, cap)
+        self.fit_ws = None if self.batched else _bytes(self.fit_ws_bytes, dev)
         self.fit_state = _bytes(V.FIT_STATE_BYTES, dev)
         self.pair_params = torch.zeros((1, 4), dtype=torch.float64, device=dev)
         self.info = _bytes(V.FIT_INFO_BYTES, dev)
@@ -228,23 +246,25 @@ class Stabilizer:
         self.first = torch.zeros(1, dtype=torch.int64, device=dev)
         self.out_slots = out_slots or (self.lag + 2)
         self.out = torch.empty((self.out_slots, height, width), dtype=torch.uint8, device=dev)
-        self.refine_pair = _PhotoRefiner(P, width, height, 1, dev)
-        s = self._s = V.vs_stream()
-        s.width, s.height, s.layout = width, height, self.layout
-        s.detect, s.lk = _detect_params(P, width, height), _lk_params(P)
-        s.fit, s.smooth = _fit_params(P, width, height), _smooth_params(P, width, height)
-        s.capacity, s.redetect_every, s.min_valid, s.border = cap, P.redetect_every, P.min_valid, P.border
-        s.out_slots = self.out_slots
-        s.photo_steps, s.photo_omega = max(P.photometric_steps, 0), self.refine_pair.omega
+        self.refine_pair = None if self.batched else _PhotoRefiner(P, width, height, 1, dev)
+        if isinstance(ring, int):
+            ring = torch.empty((max(ring, self.lag + 2), height, width), dtype=torch.uint8, device=dev)
+        self.ring = ring
+        s = self._s = stream_struct(width, height, P, self.layout, cap, self.out_slots)
         for name in ("pyr", "pts", "alive", "dst", "status", "fb_err", "n_valid", "count", "fit_state", "pair_params",
                      "affine6", "info", "inliers", "traj_state", "mats", "n_emitted", "out"):
             setattr(s, name, getattr(self, name).data_ptr())
-        s.detect_ws, s.detect_ws_bytes = self.det_ws.data_ptr(), self.det_ws_bytes
-        s.fit_ws, s.fit_ws_bytes = self.fit_ws.data_ptr(), self.fit_ws_bytes
         s.first_frame = self.first.data_ptr()
-        rp = self.refine_pair
-        s.photo_loss, s.photo_accepted = rp.loss.data_ptr(), rp.accepted.data_ptr()
-        s.photo_ws, s.photo_ws_bytes = rp.ws.data_ptr(), rp.ws_bytes
+        if self.batched:
+            assert ring.is_cuda and ring.dtype == torch.uint8 and ring.is_contiguous() and ring.shape[1:] == (height, width)
+            s.ring, s.ring_len = ring.data_ptr(), ring.shape[0]
+        else:
+            s.detect_ws, s.detect_ws_bytes = self.det_ws.data_ptr(), self.det_ws_bytes
+            s.fit_ws, s.fit_ws_bytes = self.fit_ws.data_ptr(), self.fit_ws_bytes
+            rp = self.refine_pair
+            s.photo_omega = rp.omega
+            s.photo_loss, s.photo_accepted = rp.loss.data_ptr(), rp.accepted.data_ptr()
+            s.photo_ws, s.photo_ws_bytes = rp.ws.data_ptr(), rp.ws_bytes
         self.reset()
 
     def reset(self):
@@ -279,3 +299,71 @@ class Stabilizer:
         out = [(e, self.out[e % self.out_slots]) for e in range(first, first + n)]
         self.frames.clear()
         return out
+
+
+class StreamBatch:
+    """Streams of one class (same frame size, capacity and parameters except the corner budget, seed
+    and stream id) advanced together, one frame per stream per ``push``, with one launch per stage for
+    all of them (vs_batch_push). Members are ``Stabilizer`` objects built with ``ring`` set and this
+    batch's capacity; their outputs equal those of the same streams pushed alone, bit for bit."""
+
+    def __init__(self, width: int, height: int, P: StabParams, capacity: int, max_streams: int,
+                 detect_chunk: int = 8, device="cuda"):
+        self.W, self.H, self.P, self.cap = width, height, P, capacity
+        self.dev = torch.device(device)
+        self.layout = V.vs_pyramid_layout(width, height, width, P.levels)
+        lag = P.radius if P.smooth_mode == V.VS_SMOOTH_CENTERED else 0
+        self.proto = stream_struct(width, height, P, self.layout, capacity, lag + 2)
+        self.max_streams = max_streams
+        self.detect_chunk = min(detect_chunk, max_streams)
+        self.ws_bytes = V.vs_batch_workspace(self.proto, max_streams, self.detect_chunk)
+        self.ws = _bytes(self.ws_bytes, self.dev)
+        self.b = V.vs_batch()
+        V.vs_batch_init(self.b, self.proto, max_streams, self.detect_chunk, self.ws, self.ws_bytes)
+        self.members: dict = {}
+
+    def free_slot(self) -> int | None:
+        for i in range(self.max_streams):
+            if i not in self.members:
+                return i
+        return None
+
+    def member(self, P: StabParams, out_slots: int | None = None, ring=None) -> Stabilizer:
+        """A new stream of this class (corner budget, seed and stream id from P), not yet attached."""
+        if ring is None:
+            ring = (P.radius if P.smooth_mode == V.VS_SMOOTH_CENTERED else 0) + 2
+        return Stabilizer(self.W, self.H, P, device=self.dev, out_slots=out_slots, capacity=self.cap, ring=ring)
+
+    def attach(self, st: Stabilizer, slot: int | None = None) -> int:
+        slot = self.free_slot() if slot is None else slot
+        assert slot is not None, "batch full"
+        V.vs_batch_attach(self.b, slot, st._s)
+        st.j = 0
+        self.members[slot] = st
+        return slot
+
+    def detach(self, slot: int) -> Stabilizer:
+        V.vs_batch_detach(self.b, slot)
+        return self.members.pop(slot)
+
+    def push(self, slots: list, ready: torch.cuda.Event | None = None) -> dict:
+        """One frame of every listed stream (frame j of a stream must be in its ring at j % len).
+        Returns {slot: [(frame index, output view), ...]} of the frames emitted."""
+        handle = 0
+        if ready is not None:
+            if not ready.cuda_event:
+                ready.record()
+            handle = ready.cuda_event
+        self.b.ready_event = handle
+        first, cnt = V.vs_batch_push(self.b, list(slots))
+        out = {}
+        for sl, f, c in zip(slots, first, cnt):
+            st = self.members[sl]
+            st.j += 1
+            out[sl] = [(e, st.out[e % st.out_slots]) for e in range(f, f + c)]
+        return out
+
+    def note_replayed(self, slots: list, steps: int):
+        V.vs_batch_note_replayed(self.b, list(slots), steps)
+        for sl in slots:
+            self.members[sl].j += steps

@@ -90,8 +90,18 @@ class vs_stream(C.Structure):
                 ("affine6", C.c_void_p), ("info", C.c_void_p), ("inliers", C.c_void_p), ("traj_state", C.c_void_p),
                 ("mats", C.c_void_p), ("n_emitted", C.c_void_p), ("first_frame", C.c_void_p),
                 ("photo_loss", C.c_void_p), ("photo_accepted", C.c_void_p), ("photo_ws", C.c_void_p),
-                ("photo_ws_bytes", C.c_size_t), ("out", C.c_void_p), ("ready_event", C.c_void_p), ("next_frame", C.c_int64),
+                ("photo_ws_bytes", C.c_size_t), ("out", C.c_void_p), ("ready_event", C.c_void_p), ("ring", C.c_void_p),
+                ("ring_len", C.c_int32), ("ring_pad", C.c_int32), ("next_frame", C.c_int64),
                 ("emitted", C.c_int64), ("frames", C.c_void_p * VS_STREAM_MAX_FRAMES)]
+
+
+VS_BATCH_MAX_STREAMS = 256
+
+
+class vs_batch(C.Structure):
+    _fields_ = [("proto", vs_stream), ("max_streams", C.c_int32), ("detect_chunk", C.c_int32),
+                ("workspace", C.c_void_p), ("ws_bytes", C.c_size_t), ("ready_event", C.c_void_p),
+                ("attached", C.c_void_p * VS_BATCH_MAX_STREAMS)]
 
 
 FIT_INFO_BYTES = C.sizeof(vs_fit_info)
@@ -138,6 +148,13 @@ _SIGS = {
     "vs_stream_reset": (C.c_int, [C.POINTER(vs_stream), _P]),
     "vs_stream_push": (C.c_int, [C.POINTER(vs_stream), _P, C.POINTER(C.c_int64), C.POINTER(C.c_int32), _P]),
     "vs_stream_flush": (C.c_int, [C.POINTER(vs_stream), C.POINTER(C.c_int64), C.POINTER(C.c_int32), _P]),
+    "vs_batch_workspace": (C.c_size_t, [C.POINTER(vs_stream), C.c_int32, C.c_int32]),
+    "vs_batch_init": (C.c_int, [C.POINTER(vs_batch), C.POINTER(vs_stream), C.c_int32, C.c_int32, _P, C.c_size_t]),
+    "vs_batch_attach": (C.c_int, [C.POINTER(vs_batch), C.c_int32, C.POINTER(vs_stream), _P]),
+    "vs_batch_detach": (C.c_int, [C.POINTER(vs_batch), C.c_int32]),
+    "vs_batch_push": (C.c_int, [C.POINTER(vs_batch), C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                C.POINTER(C.c_int32), _P]),
+    "vs_batch_note_replayed": (C.c_int, [C.POINTER(vs_batch), C.c_int32, C.POINTER(C.c_int32), C.c_int32]),
     "vs_set_tuning": (C.c_int, [C.POINTER(vs_tuning)]),
     "vs_get_tuning": (C.c_int, [C.POINTER(vs_tuning)]),
     "vs_last_error": (C.c_char_p, []),
@@ -215,6 +232,39 @@ def vs_stream_flush(s: vs_stream, stream=None) -> tuple[int, int]:
     first, n = C.c_int64(0), C.c_int32(0)
     _check(load().vs_stream_flush(C.byref(s), C.byref(first), C.byref(n), _stream(stream)), "vs_stream_flush")
     return first.value, n.value
+
+
+def vs_batch_workspace(proto: vs_stream, max_streams: int, detect_chunk: int) -> int:
+    return int(load().vs_batch_workspace(C.byref(proto), max_streams, detect_chunk))
+
+
+def vs_batch_init(b: vs_batch, proto: vs_stream, max_streams: int, detect_chunk: int, workspace, ws_bytes: int):
+    _check(load().vs_batch_init(C.byref(b), C.byref(proto), max_streams, detect_chunk, _ptr(workspace), ws_bytes),
+           "vs_batch_init")
+
+
+def vs_batch_attach(b: vs_batch, slot: int, s: vs_stream, stream=None):
+    _check(load().vs_batch_attach(C.byref(b), slot, C.byref(s), _stream(stream)), "vs_batch_attach")
+
+
+def vs_batch_detach(b: vs_batch, slot: int):
+    _check(load().vs_batch_detach(C.byref(b), slot), "vs_batch_detach")
+
+
+def vs_batch_push(b: vs_batch, slots, stream=None) -> tuple[list, list]:
+    """Returns (first emitted frame index, number emitted) per listed slot."""
+    n = len(slots)
+    sl = (C.c_int32 * max(n, 1))(*slots)
+    first = (C.c_int64 * max(n, 1))()
+    cnt = (C.c_int32 * max(n, 1))()
+    _check(load().vs_batch_push(C.byref(b), n, sl, first, cnt, _stream(stream)), "vs_batch_push")
+    return list(first[:n]), list(cnt[:n])
+
+
+def vs_batch_note_replayed(b: vs_batch, slots, steps: int):
+    n = len(slots)
+    sl = (C.c_int32 * max(n, 1))(*slots)
+    _check(load().vs_batch_note_replayed(C.byref(b), n, sl, steps), "vs_batch_note_replayed")
 
 
 def vs_set_tuning(t: "vs_tuning | None"):
