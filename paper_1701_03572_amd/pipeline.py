@@ -301,6 +301,24 @@ class Stabilizer:
         return out
 
 
+def _r512(n: int) -> int:
+    return (max(int(n), 1) + 511) // 512 * 512
+
+
+def member_bytes(width: int, height: int, P: StabParams, capacity: int, ring_frames: int, out_slots: int) -> int:
+    """Device bytes of a batch member (a ``Stabilizer`` built with a ring of ``ring_frames`` frames),
+    computed from the sizes of its buffers (each rounded to the allocator's 512-byte granule), so a
+    server can reserve them before allocating anything."""
+    layout = V.vs_pyramid_layout(width, height, width, P.levels)
+    lag = P.radius if P.smooth_mode == V.VS_SMOOTH_CENTERED else 0
+    cap = capacity
+    plane = width * height
+    sizes = [2 * layout.bytes, 16 * cap, 2 * cap, 8 * cap, cap, 4 * cap, 4, 4, V.FIT_STATE_BYTES, 32,
+             V.FIT_INFO_BYTES, cap, 48, V.vs_traj_state_bytes(), (lag + 2) * 48, 4, 8, out_slots * plane,
+             max(ring_frames, lag + 2) * plane]
+    return sum(_r512(b) for b in sizes)
+
+
 class StreamBatch:
     """Streams of one class (same frame size, capacity and parameters except the corner budget, seed
     and stream id) advanced together, one frame per stream per ``push``, with one launch per stage for
@@ -321,6 +339,14 @@ class StreamBatch:
         self.b = V.vs_batch()
         V.vs_batch_init(self.b, self.proto, max_streams, self.detect_chunk, self.ws, self.ws_bytes)
         self.members: dict = {}
+
+    @staticmethod
+    def workspace_bytes(width: int, height: int, P: StabParams, capacity: int, max_streams: int,
+                        detect_chunk: int = 8) -> int:
+        layout = V.vs_pyramid_layout(width, height, width, P.levels)
+        lag = P.radius if P.smooth_mode == V.VS_SMOOTH_CENTERED else 0
+        proto = stream_struct(width, height, P, layout, capacity, lag + 2)
+        return _r512(V.vs_batch_workspace(proto, max_streams, min(detect_chunk, max_streams)))
 
     def free_slot(self) -> int | None:
         for i in range(self.max_streams):

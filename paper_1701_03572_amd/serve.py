@@ -1,112 +1,228 @@
-"""Serving loop: independent streams arriving over time, each stabilized frame by frame on the GPU.
+"""Serving loop with continuous batching: independent streams arriving and leaving over time, the
+frames of all admitted streams processed together in ticks (the real-time version of Section 6,
+across streams).
 
-Each admitted stream owns device-resident state (a streaming Stabilizer: pyramid ping-pong, point
-records, fit and trajectory state, output slots) plus a small device ring for its incoming frames;
-its frames arrive in host memory (pinned) and are copied to the ring on the stream's HIP stream, so
-the measured latency includes the host-to-device copy. Streams are spread round-robin over a small
-pool of HIP streams (default priority), so the mostly single-workgroup launches of different
-streams run concurrently instead of queueing behind each other. Admission reserves each stream's device memory
-against an HBM budget (measured when its state is built); a stream that does not fit waits in a FIFO
-queue until memory is released. Streams never share state, so a stream's outputs do not depend on
-what else is being served (tested: alone vs in a mix).
+Streams are grouped into classes (same frame size and parameters except the corner budget, seed and
+stream id); each class is one ``StreamBatch`` on its own HIP stream (default priority), so the
+classes of a tick overlap on the GPU. A tick takes the next buffered frame of every admitted stream
+that has one, copies it from pinned host memory into the stream's device frame ring and runs one
+``vs_batch_push`` per class: one launch per stage for all of the class's frames. Streams join and
+leave between ticks, so requests that arrive while others are on the GPU are picked up by the next
+tick.
 
-``simulate`` replays a workload in virtual time: paced (frames are submitted at their arrival times,
-per-frame latency = completion of the frame's stabilized output on the GPU timeline minus its
-arrival) or saturated (every frame submitted as fast as possible, for capacity).
+Admission reserves a stream's device memory against an HBM budget from the exact sizes of its
+buffers, before anything is allocated (plus the class's batch workspace when the class is new); a
+stream that does not fit, or that would exceed the concurrency cap, waits in a FIFO queue with its
+arriving frames buffered on the host, and is admitted, with all its frames, when a finished stream
+releases memory. Each stream keeps its pyramids, points, fit state and trajectory on the device.
+Streams share no state, so a stream's outputs are the same alone and in a mix (tested bit for bit).
+
+``simulate`` replays a workload in virtual time: paced (frames submitted at their arrival times,
+per-frame latency = completion of the tick that stabilized it minus its arrival; the host-to-device
+copy is inside it) or saturated (all frames available at once, for capacity).
 """
 from __future__ import annotations
 
 import collections
 import dataclasses
+import math
 import time
 
 import numpy as np
 import torch
 
-from .params import SMOOTH_CAUSAL, StabParams
-from .pipeline import Stabilizer
+from .params import SMOOTH_CAUSAL, SMOOTH_CENTERED, StabParams
+from .pipeline import StreamBatch, member_bytes
 
 
 @dataclasses.dataclass
-class _Stream:
+class _Member:
     sid: int
-    stab: Stabilizer
-    ring: torch.Tensor
+    key: tuple
+    P: StabParams
+    width: int
+    height: int
     reserved: int
+    pending: collections.deque = dataclasses.field(default_factory=collections.deque)   # (j, host frame)
+    received: int = 0
+    closing: bool = False
+    slot: int = -1
+    stab: object = None
+
+
+@dataclasses.dataclass
+class _Class:
+    batch: StreamBatch
     queue: torch.cuda.Stream
-    pushed: int = 0
+    reserved: int
+    members: dict = dataclasses.field(default_factory=dict)    # slot -> _Member
+
+
+def class_key(width: int, height: int, P: StabParams) -> tuple:
+    """Streams whose keys are equal can share a batch: everything but the corner budget, the RANSAC
+    seed and the stream id."""
+    return (width, height, P.replace(max_corners=0, seed=0, stream_id=0))
 
 
 class StreamServer:
-    def __init__(self, hbm_budget: int, device="cuda", queues: int = 4):
+    def __init__(self, hbm_budget: int, device="cuda", max_concurrent: int = 128, capacity: int = 3000,
+                 detect_chunk: int = 8, ring_frames: int = 2):
         self.budget = int(hbm_budget)
         self.used = 0
         self.dev = torch.device(device)
-        self.streams: dict = {}
-        self.waiting: collections.deque = collections.deque()
-        self.rejected = 0
-        self.queues = [torch.cuda.Stream(device=self.dev) for _ in range(max(1, queues))]
-        self._next_queue = 0
+        self.max_concurrent = max_concurrent
+        self.capacity = capacity
+        self.detect_chunk = detect_chunk
+        self.ring_frames = ring_frames
+        self.classes: dict = {}
+        self.streams: dict = {}             # sid -> admitted _Member
+        self.waiting: collections.deque = collections.deque()   # queued _Member
+        self.ticks = 0
+        self.items = 0
 
-    def _build(self, sid, width, height, P: StabParams) -> _Stream:
-        q = self.queues[self._next_queue % len(self.queues)]
-        self._next_queue += 1
-        # the new state is initialised on the stream's own queue, after what the current stream
-        # has enqueued so far
-        q.wait_stream(torch.cuda.current_stream(self.dev))
-        before = torch.cuda.memory_allocated(self.dev)
-        with torch.cuda.stream(q):
-            stab = Stabilizer(width, height, P, device=self.dev)
-            ring = torch.empty((stab.lag + 2, height, width), dtype=torch.uint8, device=self.dev)
-        reserved = torch.cuda.memory_allocated(self.dev) - before
-        return _Stream(sid, stab, ring, reserved, q)
+    # ---- admission ------------------------------------------------------------------------------
+    def _lag(self, P: StabParams) -> int:
+        return P.radius if P.smooth_mode == SMOOTH_CENTERED else 0
+
+    def _member_bytes(self, m: _Member) -> int:
+        lag = self._lag(m.P)
+        return member_bytes(m.width, m.height, m.P, self.capacity, max(self.ring_frames, lag + 2), lag + 2)
+
+    def _class_bytes(self, m: _Member) -> int:
+        if m.key in self.classes:
+            return 0
+        sb_proto = StreamBatch.workspace_bytes(m.width, m.height, m.P, self.capacity, self.max_concurrent,
+                                               self.detect_chunk)
+        return sb_proto
+
+    def _fits(self, m: _Member) -> bool:
+        return (len(self.streams) < self.max_concurrent and
+                self.used + self._member_bytes(m) + self._class_bytes(m) <= self.budget)
+
+    def _admit(self, m: _Member):
+        cb = self._class_bytes(m)
+        if cb:
+            q = torch.cuda.Stream(device=self.dev)
+            with torch.cuda.stream(q):
+                sb = StreamBatch(m.width, m.height, m.P.replace(max_corners=min(m.P.max_corners, self.capacity)),
+                                 self.capacity, self.max_concurrent, self.detect_chunk, device=self.dev)
+            self.classes[m.key] = _Class(sb, q, cb)
+            self.used += cb
+        cls = self.classes[m.key]
+        m.reserved = self._member_bytes(m)
+        self.used += m.reserved
+        lag = self._lag(m.P)
+        # the member's buffers are allocated on the class's queue, which is the only stream using them
+        with torch.cuda.stream(cls.queue):
+            m.stab = cls.batch.member(m.P, ring=max(self.ring_frames, lag + 2))
+            m.slot = cls.batch.attach(m.stab)
+        cls.members[m.slot] = m
+        self.streams[m.sid] = m
 
     def open(self, sid, width: int, height: int, P: StabParams) -> bool:
-        """Admit a stream if its state fits the budget; otherwise queue it. Returns True if admitted."""
-        st = self._build(sid, width, height, P)
-        if self.used + st.reserved > self.budget:
-            del st
-            self.waiting.append((sid, width, height, P))
-            return False
-        self.used += st.reserved
-        self.streams[sid] = st
-        return True
+        """Admit a stream if its state fits the budget and the concurrency cap (checked before
+        allocating); otherwise queue it. Returns True if admitted now."""
+        assert P.max_corners <= self.capacity and P.photometric_steps == 0
+        m = _Member(sid, class_key(width, height, P), P, width, height, 0)
+        if not self.waiting and self._fits(m):
+            self._admit(m)
+            return True
+        self.waiting.append(m)
+        return False
 
-    def submit(self, sid, frame_host: torch.Tensor, ready: torch.cuda.Event | None = None) -> list:
-        """Copy one arriving frame (host, uint8 [H, W]) to the device and enqueue its processing.
-        Returns (frame index, output view) for the frames this push emits; ``ready`` (optional) is
-        recorded on the stream's queue once they are written."""
-        st = self.streams[sid]
-        with torch.cuda.stream(st.queue):
-            slot = st.ring[st.pushed % st.ring.shape[0]]
-            slot.copy_(frame_host, non_blocking=True)
-            st.pushed += 1
-            return st.stab.push(slot, ready=ready)
+    def _find(self, sid) -> _Member:
+        if sid in self.streams:
+            return self.streams[sid]
+        for m in self.waiting:
+            if m.sid == sid:
+                return m
+        raise KeyError(sid)
 
-    def close(self, sid) -> list:
-        """End a stream: emit what is left, release its memory and admit queued streams that now fit."""
-        st = self.streams.pop(sid)
-        with torch.cuda.stream(st.queue):
-            out = st.stab.flush()
-        self.used -= st.reserved
-        admitted = []
-        while self.waiting:
-            wsid, w, h, P = self.waiting[0]
-            probe = self._build(wsid, w, h, P)
-            if self.used + probe.reserved > self.budget:
-                break
-            self.waiting.popleft()
-            self.used += probe.reserved
-            self.streams[wsid] = probe
-            admitted.append(wsid)
-        self.last_admitted = admitted
+    def submit(self, sid, frame_host: torch.Tensor):
+        """Buffer one arriving frame (host uint8 [H, W], pinned, unchanged until processed)."""
+        m = self._find(sid)
+        assert not m.closing
+        m.pending.append((m.received, frame_host))
+        m.received += 1
+
+    def close(self, sid):
+        """No more frames: the stream ends once its buffered frames are processed."""
+        self._find(sid).closing = True
+
+    def has_work(self) -> bool:
+        """Some admitted stream has a buffered frame or is closing (a tick would do something)."""
+        return any(m.pending or m.closing for m in self.streams.values())
+
+    # ---- ticks ----------------------------------------------------------------------------------
+    def tick(self, timing: bool = False, on_emit=None) -> list:
+        """One frame of every admitted stream that has one buffered, one batched push per class.
+        Returns [(sid, frame index, event)] of the frames emitted; the event is recorded on the class's
+        queue after the warps. ``on_emit(sid, frame index, output view)``, when given, is called for
+        each with the class's queue current (work it enqueues there is ordered after the warp that
+        wrote the view and before the view's memory is reused)."""
+        out = []
+        for cls in self.classes.values():
+            items = [m for m in cls.members.values() if m.pending]
+            if not items:
+                continue
+            ev = torch.cuda.Event(enable_timing=timing)
+            with torch.cuda.stream(cls.queue):
+                for m in items:
+                    j, frame = m.pending.popleft()
+                    ring = m.stab.ring
+                    ring[j % ring.shape[0]].copy_(frame, non_blocking=True)
+                res = cls.batch.push([m.slot for m in items], ready=ev)
+                for m in items:
+                    for e, view in res[m.slot]:
+                        out.append((m.sid, e, ev))
+                        if on_emit is not None:
+                            on_emit(m.sid, e, view)
+            self.ticks += 1
+            self.items += len(items)
+        out += self._finish(timing, on_emit)
+        return out
+
+    def _finish(self, timing: bool = False, on_emit=None) -> list:
+        """Ends the closed streams whose frames are all processed, releases their memory and admits
+        queued streams that now fit."""
+        out = []
+        for m in [m for m in self.streams.values() if m.closing and not m.pending]:
+            cls = self.classes[m.key]
+            with torch.cuda.stream(cls.queue):
+                st = cls.batch.detach(m.slot)
+                em = st.flush()
+                if em:
+                    ev = torch.cuda.Event(enable_timing=timing)
+                    ev.record()
+                    for e, view in em:
+                        out.append((m.sid, e, ev))
+                        if on_emit is not None:
+                            on_emit(m.sid, e, view)
+            del cls.members[m.slot]
+            del self.streams[m.sid]
+            self.used -= m.reserved
+            m.stab = None
+            if not cls.members:
+                del self.classes[m.key]
+                self.used -= cls.reserved
+        while self.waiting and self._fits(self.waiting[0]):
+            self._admit(self.waiting.popleft())
+        return out
+
+    def drain(self, on_emit=None) -> list:
+        """Ticks until every admitted stream is idle (closed ones finished, queued ones admitted)."""
+        out = []
+        while self.has_work():
+            out += self.tick(on_emit=on_emit)
+        if self.waiting and not self.streams:
+            raise RuntimeError("a queued stream can never be admitted within the budget")
         return out
 
 
 @dataclasses.dataclass(frozen=True)
 class ServedStream:
     sid: int
-    arrival: float          # s (virtual time)
+    arrival: float          # s (virtual time) of its first replayed frame
     n_frames: int
     fps: float
     width: int
@@ -117,12 +233,15 @@ class ServedStream:
 
 
 def poisson_workload(duration_s: float, rate: float, lifetime_s: tuple, fps: float, classes: list, k_range: tuple,
-                     seed: int, max_concurrent: int = 128) -> list:
-    """Seeded stream arrivals: Poisson(rate) over [0, duration), lifetimes U[lifetime_s], resolution
-    drawn from ``classes`` [(width, height, levels, clip index)], corner budget U[k_range]; the causal
-    smoother (no lag). Streams beyond ``max_concurrent`` overlapping ones are dropped."""
+                     seed: int, max_concurrent: int = 128, warm_start_s: float = 0.0) -> list:
+    """Seeded stream arrivals: Poisson(rate) over [-warm_start_s, duration), lifetimes U[lifetime_s],
+    resolution drawn from ``classes`` [(width, height, levels, clip index)], corner budget U[k_range];
+    the causal smoother (no lag). Streams beyond ``max_concurrent`` overlapping ones are dropped.
+    With a warm start, streams that arrived before 0 enter the replay at 0 with their remaining frames,
+    so the replay starts near the steady-state concurrency (rate x mean lifetime). Frames arriving at
+    or after ``duration_s`` are cut, so a paced replay lasts ``duration_s``."""
     rng = np.random.default_rng(seed)
-    t, out, sid = 0.0, [], 0
+    t, out, sid = -warm_start_s, [], 0
     while True:
         t += rng.exponential(1.0 / rate)
         if t >= duration_s:
@@ -130,67 +249,97 @@ def poisson_workload(duration_s: float, rate: float, lifetime_s: tuple, fps: flo
         life = rng.uniform(*lifetime_s)
         w, h, levels, clip = classes[int(rng.integers(0, len(classes)))]
         k = int(rng.integers(k_range[0], k_range[1] + 1))
-        active = sum(1 for s in out if s.arrival <= t < s.arrival + s.n_frames / s.fps)
+        offset = int(rng.integers(0, 1000))
+        n = max(2, int(life * fps))
+        active = sum(1 for s in out if s.arrival <= max(t, 0.0) < s.arrival + s.n_frames / s.fps)
         if active >= max_concurrent:
             continue
-        P = StabParams(levels=levels, max_corners=k, smooth_mode=SMOOTH_CAUSAL, stream_id=sid)
-        out.append(ServedStream(sid, t, max(2, int(life * fps)), fps, w, h, P, clip, int(rng.integers(0, 1000))))
+        P = StabParams(levels=levels, max_corners=k, smooth_mode=SMOOTH_CAUSAL, stream_id=sid, seed=1709 + sid)
+        skip = int(math.ceil(-t * fps)) if t < 0 else 0   # frames played before the replay starts
+        arr = t + skip / fps
+        n = min(n - skip, int(math.ceil((duration_s - arr) * fps)))
+        if n < 2:
+            continue
+        out.append(ServedStream(sid, arr, n, fps, w, h, P, clip, offset + skip))
         sid += 1
     return out
 
 
-def simulate(server: StreamServer, workload: list, pools: list, paced: bool) -> dict:
+def simulate(server: StreamServer, workload: list, pools: list, paced: bool, max_inflight: int = 2,
+             on_emit=None) -> dict:
     """Replay ``workload`` (ServedStream list) against ``server``. ``pools[clip]`` is a pinned host
-    uint8 tensor [m, H, W] each stream plays cyclically from its offset. Returns per-frame latencies
-    (paced) and throughput."""
-    events = []             # (time, kind, stream, frame index)
+    uint8 tensor [m, H, W] each stream plays cyclically from its offset. Ticks are issued whenever
+    frames are buffered and fewer than ``max_inflight`` ticks are still running on the GPU, so the
+    batch of a tick is whatever arrived while the previous ones ran. ``on_emit`` is passed to
+    ``StreamServer.tick``. Returns per-frame latencies (paced) and throughput."""
+    events = []             # (time, order, kind, stream, frame index): kind 0 = frame, 1 = end of stream
     for s in workload:
         for j in range(s.n_frames):
-            events.append((s.arrival + j / s.fps, 0 if j < s.n_frames - 1 else 1, s, j))
-    events.sort(key=lambda e: (e[0], e[2].sid, e[3]))
-    done = []               # (arrival s, cuda event)
-    start = torch.cuda.Event(enable_timing=True)
+            events.append((s.arrival + j / s.fps, 0, s, j))
+        events.append((s.arrival + (s.n_frames - 1) / s.fps, 1, s, s.n_frames))
+    events.sort(key=lambda e: (e[0], e[2].sid, e[1], e[3]))
+    arrival = {}
+    done = []               # (arrival s, event)
+    inflight = collections.deque()
+    for q in [c.queue for c in server.classes.values()]:
+        q.synchronize()
     torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     start.record()
-    admitted_at = {}
+    i = 0
     n_out = 0
-    for t, kind, s, j in events:
-        if paced:
-            lag = t - (time.perf_counter() - t0)
-            if lag > 0:
-                time.sleep(lag)
-        if j == 0:
-            if not server.open(s.sid, s.width, s.height, s.params):
-                continue
-            admitted_at[s.sid] = t
-        if s.sid not in server.streams:
-            continue                                  # still queued: its frames are dropped until admitted
-        pool = pools[s.clip]
-        frame = pool[(s.offset + j) % pool.shape[0]]
-        queue = server.streams[s.sid].queue
-        ev = torch.cuda.Event(enable_timing=True)
-        emitted = server.submit(s.sid, frame, ready=ev)   # recorded on the queue after the push's warps
-        if kind == 1:
-            emitted += server.close(s.sid)
-            ev = torch.cuda.Event(enable_timing=True)
-            ev.record(queue)                          # after the flush's warps too
-        if emitted:
-            done.append((t, ev, len(emitted)))
+    max_conc = 0
+    while True:
+        now = (time.perf_counter() - t0) if paced else math.inf
+        while i < len(events) and events[i][0] <= now:
+            t, kind, s, j = events[i]
+            i += 1
+            if kind == 0:
+                if j == 0:
+                    server.open(s.sid, s.width, s.height, s.params)
+                pool = pools[s.clip]
+                server.submit(s.sid, pool[(s.offset + j) % pool.shape[0]])
+                arrival[(s.sid, j)] = t
+            else:
+                server.close(s.sid)
+        while inflight and all(e.query() for e in inflight[0]):
+            inflight.popleft()
+        if server.has_work() and len(inflight) < max_inflight:
+            max_conc = max(max_conc, len(server.streams))
+            emitted = server.tick(timing=True, on_emit=on_emit)
+            evs = []
+            for sid, e, ev in emitted:
+                done.append((arrival[(sid, e)], ev))
+                if not evs or evs[-1] is not ev:
+                    evs.append(ev)
             n_out += len(emitted)
-    for q in server.queues:
-        torch.cuda.current_stream().wait_stream(q)
+            if evs:
+                inflight.append(evs)
+            continue
+        if i >= len(events) and not server.has_work():
+            if server.waiting:
+                raise RuntimeError("a queued stream can never be admitted within the budget")
+            break
+        if inflight and (not paced or i >= len(events) or server.has_work()):
+            inflight[0][-1].synchronize()
+        elif paced and i < len(events):
+            lag = events[i][0] - (time.perf_counter() - t0)
+            if lag > 0:
+                time.sleep(min(lag, 0.002))
+    torch.cuda.synchronize()            # every queue, also those of classes that have ended
     end = torch.cuda.Event(enable_timing=True)
     end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_total_ms = start.elapsed_time(end)
-    res = {"frames_out": n_out, "wall_s": wall, "gpu_s": gpu_total_ms / 1e3,
+    res = {"frames_out": n_out, "frames_in": len(arrival), "wall_s": wall, "gpu_s": gpu_total_ms / 1e3,
            "frames_per_s": n_out / max(gpu_total_ms / 1e3, 1e-9), "latency_ms_p50": None, "latency_ms_p99": None,
-           "streams": len(workload), "admitted": len(admitted_at), "queued_or_rejected": len(workload) - len(admitted_at)}
+           "streams": len(workload), "ticks": server.ticks, "mean_items_per_push": server.items / max(server.ticks, 1),
+           "max_concurrent": max_conc}
     if paced and done:
         # completion on the GPU timeline (relative to the start event, recorded at t0) minus arrival
-        lat = np.array([start.elapsed_time(ev) / 1e3 - t for t, ev, _ in done])
+        lat = np.array([start.elapsed_time(ev) / 1e3 - t for t, ev in done])
         res["latency_ms_p50"] = float(np.percentile(lat, 50) * 1e3)
         res["latency_ms_p99"] = float(np.percentile(lat, 99) * 1e3)
     return res
