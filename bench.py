@@ -182,7 +182,6 @@ def run_batched(n_streams: int, n_frames: int, steps: int, warmup: int, cpu_fram
     ms = MultiStabilizer(specs)
     for i, f in enumerate(frames):
         ms.load(i, f)
-    del frames
     total = ms.frames_total()
 
     def timed(fn, k):
@@ -210,9 +209,55 @@ def run_batched(n_streams: int, n_frames: int, steps: int, warmup: int, cpu_fram
         (n_streams, total, eager_ms, res["frames_per_s_eager"], graph_ms, res["frames_per_s_graph"]))
     del ms
     torch.cuda.empty_cache()
+    res["frame_step"] = run_frame_steps(specs, frames)
+    del frames
+    torch.cuda.empty_cache()
     if cpu_frames > 0:
         res["cpu_baseline"] = batched_cpu_baseline(n_streams, n_frames, cpu_frames)
         log("batched oracle: %.2f frames/s on %d threads" % (res["cpu_baseline"]["value"], res["cpu_baseline"]["cores"]))
+    return res
+
+
+def run_frame_steps(specs: list, frames: list) -> dict:
+    """The same streams advanced frame by frame: each step is the next frame of all of them, one
+    vs_batch_push per resolution class; timed eagerly and as replays of one captured step (one
+    replay per frame step). Median of 3 passes over all frames."""
+    import numpy as np
+    import torch
+    from paper_1701_03572_amd.batch import FrameStepBatch
+
+    fb = FrameStepBatch(specs, frames, detect_chunk=16, keep_outputs=False)
+    n = max(s.n_frames for s in specs)
+    total = fb.frames_total()
+
+    def timed(fn):
+        runs = []
+        for _ in range(3):
+            fb.reset()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            runs.append(a.elapsed_time(b))
+        return float(np.median(runs))
+
+    fb.reset()
+    fb.run()                                   # warm-up pass
+    eager_ms = timed(fb.run)
+    fb.reset()
+    fb.capture_step()
+    fb.replay_steps(n)                         # warm-up pass of the graph
+    graph_ms = timed(lambda: fb.replay_steps(n))
+    res = {"what": "per-frame steps: each step the next frame of all %d streams, one batched launch set per class "
+                   "(%d classes)" % (len(specs), len(fb.classes)),
+           "steps": n, "ms_eager": round(eager_ms, 3), "frames_per_s_eager": round(total / (eager_ms / 1e3), 1),
+           "ms_per_step_eager": round(eager_ms / n, 4), "ms_graph": round(graph_ms, 3),
+           "frames_per_s_graph": round(total / (graph_ms / 1e3), 1), "ms_per_step_graph": round(graph_ms / n, 4)}
+    log("frame-step batch: %d steps of %d streams: eager %.2f ms (%.0f frames/s), graph replays %.2f ms (%.0f frames/s)"
+        % (n, len(specs), eager_ms, res["frames_per_s_eager"], graph_ms, res["frames_per_s_graph"]))
+    del fb
     return res
 
 

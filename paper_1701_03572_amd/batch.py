@@ -203,3 +203,107 @@ class MultiStabilizer:
         info = V.fit_info_to_dicts(c.info[off * V.FIT_INFO_BYTES:(off + npairs) * V.FIT_INFO_BYTES]) if npairs else []
         return {"pair_params": c.pair_params[off:off + npairs].cpu().numpy(), "info": info,
                 "mats": c.mats[off:off + nf].cpu().numpy(), "n_valid": c.n_valid[off:off + npairs].cpu().numpy()}
+
+
+class FrameStepBatch:
+    """The same kind of workload advanced frame by frame (the real-time version of Section 6 across
+    streams): each step processes the next frame of every stream, one ``vs_batch_push`` per class
+    (``pipeline.StreamBatch``): one launch per stage for the current frames of all of the class's
+    streams. Every stream's frames stay resident (its frame ring is its whole sequence). Since a
+    step's launches depend only on which streams it lists, one step over all streams (all of one
+    length) can be captured and replayed once per frame (``capture_step`` / ``replay_steps``).
+    Every stream's outputs equal those of the stream processed alone (and those of
+    ``MultiStabilizer``), bit for bit."""
+
+    def __init__(self, specs: list, frames: list, detect_chunk: int = 16, keep_outputs: bool = True,
+                 device="cuda"):
+        from .pipeline import StreamBatch
+        from .serve import class_key as serve_key
+        self.specs = list(specs)
+        self.dev = torch.device(device)
+        groups: dict = {}
+        for i, spec in enumerate(self.specs):
+            groups.setdefault(serve_key(spec.width, spec.height, spec.params), []).append(i)
+        self.classes = []                       # (StreamBatch, [(stream index, slot)])
+        self.members = {}
+        for idx in groups.values():
+            s0 = self.specs[idx[0]]
+            cap = max(self.specs[i].params.max_corners for i in idx)
+            sb = StreamBatch(s0.width, s0.height, s0.params.replace(max_corners=cap), cap, len(idx),
+                             min(detect_chunk, len(idx)), device=self.dev)
+            slots = []
+            for i in idx:
+                spec = self.specs[i]
+                fr = frames[i]
+                assert fr.shape == (spec.n_frames, spec.height, spec.width) and fr.is_contiguous()
+                st = sb.member(spec.params, out_slots=spec.n_frames if keep_outputs else None, ring=fr)
+                slots.append((i, sb.attach(st)))
+                self.members[i] = st
+            self.classes.append((sb, slots))
+        self.queues = [torch.cuda.Stream(device=self.dev) for _ in self.classes]
+        self.graph = None
+        self._capture_advanced = False
+        self.t = 0
+
+    def _push_all(self, lists: list):
+        """One push per class on the class's queue, forked from and joined to the current stream."""
+        cur = torch.cuda.current_stream(self.dev)
+        used = []
+        for (sb, _), q, act in zip(self.classes, self.queues, lists):
+            if not act:
+                continue
+            q.wait_stream(cur)
+            with torch.cuda.stream(q):
+                sb.push(act)
+            used.append(q)
+        for q in used:
+            cur.wait_stream(q)
+
+    def reset(self):
+        """Every stream back to frame 0 (re-attached at its slot, which resets it)."""
+        for sb, slots in self.classes:
+            for i, sl in slots:
+                st = sb.detach(sl)
+                sb.attach(st, sl)
+        self.t = 0
+        self._capture_advanced = False
+
+    def _active(self, slots) -> list:
+        return [sl for i, sl in slots if self.t < self.specs[i].n_frames]
+
+    def step(self):
+        self._push_all([self._active(slots) for _, slots in self.classes])
+        self.t += 1
+
+    def run(self):
+        """Every frame of every stream, step by step (eager)."""
+        n = max(s.n_frames for s in self.specs)
+        while self.t < n:
+            self.step()
+
+    def capture_step(self):
+        """Capture one step over all streams (they must share one length) into a HIP graph. The
+        capture advances the host progress by one step, the replays do the device work."""
+        assert len({s.n_frames for s in self.specs}) == 1, "graph steps need streams of one length"
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self._push_all([[sl for _, sl in slots] for _, slots in self.classes])
+        self.graph = g
+        self._capture_advanced = True
+        return g
+
+    def replay_steps(self, k: int):
+        """k replays of the captured step: the next k frames of every stream."""
+        for _ in range(k):
+            self.graph.replay()
+        adv = k - 1 if self._capture_advanced else k     # the capture already advanced the host once
+        self._capture_advanced = False
+        for sb, slots in self.classes:
+            sb.note_replayed([sl for _, sl in slots], adv)
+        self.t += k
+
+    def frames_total(self) -> int:
+        return sum(s.n_frames for s in self.specs)
+
+    def output(self, i: int) -> torch.Tensor:
+        return self.members[i].out

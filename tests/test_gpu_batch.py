@@ -84,3 +84,36 @@ def test_graph_replays_reproduce_eager_results():
             np.testing.assert_array_equal(got["pair_params"], eager[i][0]["pair_params"])
             np.testing.assert_array_equal(got["mats"], eager[i][0]["mats"])
             assert torch.equal(ms.output(i), eager[i][1]), (rep, i)
+
+
+def test_frame_step_batch_equals_sequence_batch_eager_and_replayed():
+    """The per-frame-step batch (each step: the next frame of every stream, one launch set per class)
+    gives every stream the outputs of the whole-sequence batch, bit for bit; so do replays of one
+    captured step, and a second pass after a reset."""
+    from paper_1701_03572_amd.batch import FrameStepBatch
+    specs, frames = mixed(6, 12, base_seed=1707)
+    ms = MultiStabilizer(specs)
+    for i, f in enumerate(frames):
+        ms.load(i, f)
+    ms.run()
+    torch.cuda.synchronize()
+    ref = [ms.output(i).clone() for i in range(len(specs))]
+    fb = FrameStepBatch(specs, frames, detect_chunk=2)
+    assert len(fb.classes) >= 2
+    fb.run()
+    torch.cuda.synchronize()
+    for i in range(len(specs)):
+        assert torch.equal(fb.output(i), ref[i]), i
+    fb.reset()
+    for i in range(len(specs)):
+        fb.output(i).zero_()
+    fb.capture_step()
+    fb.replay_steps(5)
+    torch.cuda.synchronize()
+    _ = sum(float(fb.output(i).float().mean()) for i in range(len(specs)))   # eager work between replays
+    fb.replay_steps(7)
+    torch.cuda.synchronize()
+    for i in range(len(specs)):
+        st = fb.members[i]
+        assert st._s.next_frame == 12 and st._s.emitted == 12
+        assert torch.equal(fb.output(i), ref[i]), i
