@@ -278,6 +278,38 @@ __device__ __forceinline__ void row_terms(uint32_t p0, uint32_t p1, uint32_t p2,
 // one unaligned 32-bit load per row; otherwise four edge-clamped byte loads. Rows are interpolated
 // horizontally first; V(r) = lerp(H(r), H(r+1), b) gives I = V(k+1) and Dy = V(k+2) - V(k), and Dx
 // interpolates the rows' D vertically. With WEIGHTED, rows k >= nrows get Dx = Dy = 0.
+// I, Ix, Iy of one lane from rows held as words at sp (row r at sp + 8 r, the lane's 4 bytes at byte
+// shift sh of two aligned words), with the shared fraction (a, b); see window_samples.
+template <int RMAX, bool WEIGHTED>
+__device__ __forceinline__ void staged_terms(const uint32_t* sp, unsigned sh, float a, float b, int nrows,
+                                             float (&I)[RMAX], float (&Ix)[RMAX], float (&Iy)[RMAX])
+{
+    float H[RMAX + 3], D[RMAX + 3];   // D is used for rows 1 .. RMAX + 1 only
+#pragma unroll
+    for (int r = 0; r < RMAX + 3; ++r) {
+        const uint32_t w = lds_word(sp + 8 * r, sh);
+        const uint32_t p0 = w & 0xff, p1 = (w >> 8) & 0xff, p2 = (w >> 16) & 0xff, p3 = w >> 24;
+        if (r == 0 || r == RMAX + 2)
+            row_terms<false>(p0, p1, p2, p3, a, H[r], D[r]);
+        else
+            row_terms<true>(p0, p1, p2, p3, a, H[r], D[r]);
+    }
+    float V[RMAX + 2];
+#pragma unroll
+    for (int r = 0; r < RMAX + 2; ++r) V[r] = lerp(H[r], H[r + 1], b);
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) {
+        I[k] = V[k + 1];
+        Ix[k] = lerp(D[k + 1], D[k + 2], b);
+        Iy[k] = V[k + 2] - V[k];
+        if constexpr (WEIGHTED) {
+            const float wgt = k < nrows ? 1.0f : 0.0f;
+            Ix[k] *= wgt;
+            Iy[k] *= wgt;
+        }
+    }
+}
+
 template <int RMAX, bool FAST, bool WEIGHTED>
 __device__ __forceinline__ void window_samples(const Img& A, int ix, int iy, int bx, int by, int lane_off, float a,
                                                float b, int nrows, bool active, uint32_t* stage, float (&I)[RMAX],
@@ -344,6 +376,50 @@ __device__ __forceinline__ void window_samples(const Img& A, int ix, int iy, int
     }
 }
 
+// The set-up's two blocks when both lie inside their levels and a lane holds at most 7 rows: the
+// previous-frame window block (24 rows) and the first iterate's next-frame block (22 rows) are loaded
+// together, so the two global-memory latencies overlap, staged in two areas of the wave's LDS and read
+// as in window_samples and load_next_block (same arithmetic, same results).
+template <int RMAX, bool WEIGHTED>
+__device__ __forceinline__ void setup_staged(const Img& A, const Img& B, int bx, int by, int nbx, int nby,
+                                             int lane_off, float a, float b, int nrows, bool active, float* red,
+                                             float (&I)[RMAX], float (&Ix)[RMAX], float (&Iy)[RMAX],
+                                             float (&qa)[RMAX + 1], float (&qb)[RMAX + 1])
+{
+    static_assert(RMAX <= 7, "staged blocks hold 7 rows per lane at most");
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x & 63;
+    const int r = lane >> 1, h = lane & 1;
+    uint32_t* sprev = reinterpret_cast<uint32_t*>(red);
+    uint32_t* snext = sprev + 8 * STAGE_ROWS;
+    static_assert(8 * (2 * STAGE_ROWS - 2) <= RED_FLOATS, "both blocks fit the reduction area");
+    const int pc0 = bx & ~3, nc0 = nbx & ~3;
+    u32x4 vp = {0u, 0u, 0u, 0u}, vn = {0u, 0u, 0u, 0u};
+    if (r < STAGE_ROWS)
+        vp = __builtin_amdgcn_raw_buffer_load_b128(A.rs, (int)__umul24((unsigned)(by + r), (unsigned)A.pitch) + pc0 + 16 * h,
+                                                   0, 0);
+    if (r < STAGE_ROWS - 2)
+        vn = __builtin_amdgcn_raw_buffer_load_b128(B.rs, (int)__umul24((unsigned)(nby + r), (unsigned)B.pitch) + nc0 + 16 * h,
+                                                   0, 0);
+    if (r < STAGE_ROWS) *reinterpret_cast<u32x4*>(sprev + 8 * r + 4 * h) = vp;
+    if (r < STAGE_ROWS - 2) *reinterpret_cast<u32x4*>(snext + 8 * r + 4 * h) = vn;
+    wave_lds_sync();
+    // lanes outside the window read the zeroed area
+    const uint32_t* zero = reinterpret_cast<const uint32_t*>(red + RED_FLOATS);
+    const int op = lane_off + (bx - pc0), on = lane_off + (nbx - nc0);
+    staged_terms<RMAX, WEIGHTED>(active ? sprev + (op >> 2) : zero, active ? (unsigned)(op & 3) : 0u, a, b, nrows, I, Ix,
+                                 Iy);
+    const uint32_t* np = active ? snext + (on >> 2) : zero;
+    const unsigned nsh = active ? (unsigned)(on & 3) : 0u;
+#pragma unroll
+    for (int k = 0; k <= RMAX; ++k) {
+        const uint32_t w = lds_word(np + 8 * k, nsh);
+        qa[k] = (float)(w & 0xff);
+        qb[k] = (float)((w >> 8) & 0xff);
+    }
+    wave_lds_sync();   // the area is written again by the next staging or reduction
+}
+
 template <int RMAX>
 __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* fb, const uint8_t* pb,
                           const vs::LevelDesc& d, const LKConst& c, float ux, float uy, float& vx, float& vy,
@@ -375,23 +451,36 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
         // window's block starting at (fx - h - 1, fy - h - 1)
         const bool a_in = wave_all(!active || (ix - 1 >= 0 && ix + 2 <= A.w - 1 && iy - 1 >= 0 && iy + RMAX + 1 <= A.h - 1));
         const int bx = (int)fx - c.hw - 1, by = (int)fy - c.hw - 1;
+        // the first iterate's next-frame block is read with the set-up, so its residual sums share the
+        // set-up's reduction: 3 tensor sums + 2 sums of I times the gradient + 8 residual sums in one
+        const int jx0 = (int)floorf(cx + gx), jy0 = (int)floorf(cy + gy);
         float I[RMAX], Ix[RMAX], Iy[RMAX];
-        if (c.full) {
-            if (a_in)
-                window_samples<RMAX, true, false>(A, ix, iy, bx, by, lane_off, a, b, nrows, active, stage, I, Ix, Iy);
-            else
-                window_samples<RMAX, false, false>(A, ix, iy, bx, by, lane_off, a, b, nrows, active, stage, I, Ix, Iy);
-        } else {
-            if (a_in)
-                window_samples<RMAX, true, true>(A, ix, iy, bx, by, lane_off, a, b, nrows, active, stage, I, Ix, Iy);
-            else
-                window_samples<RMAX, false, true>(A, ix, iy, bx, by, lane_off, a, b, nrows, active, stage, I, Ix, Iy);
-        }
-        // the first iterate's next-frame block is read here, so its residual sums share the set-up's
-        // reduction: 3 tensor sums + 2 sums of I times the gradient + 8 residual sums in one reduction
         float qa[RMAX + 1], qb[RMAX + 1];
-        {
-            const int jx0 = (int)floorf(cx + gx), jy0 = (int)floorf(cy + gy);
+        bool both_staged = false;
+        if constexpr (RMAX <= 7) {
+            const int x0 = jx0 + qx, y0 = jy0 + qy0;
+            both_staged = a_in && wave_all(!active || (x0 >= 0 && x0 + 1 <= B.w - 1 && y0 >= 0 && y0 + RMAX <= B.h - 1));
+            if (both_staged) {
+                if (c.full)
+                    setup_staged<RMAX, false>(A, B, bx, by, jx0 - c.hw, jy0 - c.hw, lane_off, a, b, nrows, active, red,
+                                              I, Ix, Iy, qa, qb);
+                else
+                    setup_staged<RMAX, true>(A, B, bx, by, jx0 - c.hw, jy0 - c.hw, lane_off, a, b, nrows, active, red,
+                                             I, Ix, Iy, qa, qb);
+            }
+        }
+        if (!both_staged) {
+            if (c.full) {
+                if (a_in)
+                    window_samples<RMAX, true, false>(A, ix, iy, bx, by, lane_off, a, b, nrows, active, stage, I, Ix, Iy);
+                else
+                    window_samples<RMAX, false, false>(A, ix, iy, bx, by, lane_off, a, b, nrows, active, stage, I, Ix, Iy);
+            } else {
+                if (a_in)
+                    window_samples<RMAX, true, true>(A, ix, iy, bx, by, lane_off, a, b, nrows, active, stage, I, Ix, Iy);
+                else
+                    window_samples<RMAX, false, true>(A, ix, iy, bx, by, lane_off, a, b, nrows, active, stage, I, Ix, Iy);
+            }
             load_next_block<RMAX>(B, jx0 + qx, jy0 + qy0, jx0 - c.hw, jy0 - c.hw, lane_off, active, stage, qa, qb);
         }
         float v[16];
