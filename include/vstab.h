@@ -465,18 +465,27 @@ int vs_batch_note_replayed(vs_batch* b, int32_t n, const int32_t* slots, int32_t
 
 /* ---------------------------------------------------------------------------------------------
  * tuning -- launch-shape choices that change speed only, never a result bit (the choices only
- * reorder independent workgroups or group independent waves). Process-wide; a call reads the
- * values current when it is made, so settings may change between calls from any thread.
+ * reorder independent workgroups, group independent waves, or split independent work differently).
+ * Process-wide; a call reads the values current when it is made, so settings may change between
+ * calls from any thread.
  *   xcd_min_items_{pyramid,lk,warp}: batches of at least this many items keep each item's
  *     workgroups on one XCD (one L2); 0 selects the default (8); 1 always, 65536 never.
  *   lk_points_per_group: points (one wave each) per tracking workgroup, 1, 2 or 4; 0: default (1).
+ *   detect_segment_rows: output rows per wave segment of the corner response, 12..240; 0: by batch
+ *     size (12 for at most 8 frames, else 60). Survivors are sorted afterwards, so the split is free.
+ *   fit_groups_in_flight: hypothesis workgroups of a fit launch are spread until about this many are
+ *     in flight (at most 32 per pair), 64..16384; 0: default (2048). The best hypothesis is the most
+ *     inliers, then the smallest index, whatever the split.
  * vs_set_tuning(NULL) restores the defaults. Values out of range: VS_ERR_INVALID, nothing changed.
- * vs_get_tuning reports the values in force (defaults resolved). Both are host-only. */
+ * vs_get_tuning reports the values in force (defaults resolved; detect_segment_rows 0 = by batch
+ * size). Both are host-only. */
 typedef struct {
     int32_t xcd_min_items_pyramid;
     int32_t xcd_min_items_lk;
     int32_t xcd_min_items_warp;
     int32_t lk_points_per_group;
+    int32_t detect_segment_rows;
+    int32_t fit_groups_in_flight;
 } vs_tuning;
 
 int vs_set_tuning(const vs_tuning* t);

@@ -27,6 +27,7 @@ int check_launch(const char* what)
 // launch tuning: speed-only choices, read by each call when it launches
 static std::atomic<int> g_xcd_pyr{VS_XCD_MIN_ITEMS}, g_xcd_lk{VS_XCD_MIN_ITEMS}, g_xcd_warp{VS_XCD_MIN_ITEMS};
 static std::atomic<int> g_lk_ppg{1};
+static std::atomic<int> g_det_rows{0}, g_fit_groups{2048};
 
 int xcd_min_items(int kernel)
 {
@@ -39,11 +40,19 @@ int xcd_min_items(int kernel)
 
 int lk_points_per_group() { return g_lk_ppg.load(std::memory_order_relaxed); }
 
+int detect_segment_rows(int n_items, int few_rows, int many_rows)
+{
+    const int r = g_det_rows.load(std::memory_order_relaxed);
+    return r ? r : (n_items <= 8 ? few_rows : many_rows);
+}
+
+int fit_groups_in_flight() { return g_fit_groups.load(std::memory_order_relaxed); }
+
 }  // namespace vs
 
 extern "C" int vs_set_tuning(const vs_tuning* t)
 {
-    vs_tuning v{0, 0, 0, 0};
+    vs_tuning v{0, 0, 0, 0, 0, 0};
     if (t) v = *t;
     const int xs[3] = {v.xcd_min_items_pyramid, v.xcd_min_items_lk, v.xcd_min_items_warp};
     for (int x : xs)
@@ -51,10 +60,16 @@ extern "C" int vs_set_tuning(const vs_tuning* t)
     if (!(v.lk_points_per_group == 0 || v.lk_points_per_group == 1 || v.lk_points_per_group == 2 ||
           v.lk_points_per_group == 4))
         return vs::set_error(VS_ERR_INVALID, "vs_set_tuning: lk_points_per_group must be 0, 1, 2 or 4");
+    if (!(v.detect_segment_rows == 0 || (v.detect_segment_rows >= 12 && v.detect_segment_rows <= 240)))
+        return vs::set_error(VS_ERR_INVALID, "vs_set_tuning: detect_segment_rows must be 0 or 12..240");
+    if (!(v.fit_groups_in_flight == 0 || (v.fit_groups_in_flight >= 64 && v.fit_groups_in_flight <= 16384)))
+        return vs::set_error(VS_ERR_INVALID, "vs_set_tuning: fit_groups_in_flight must be 0 or 64..16384");
     vs::g_xcd_pyr.store(xs[0] ? xs[0] : VS_XCD_MIN_ITEMS);
     vs::g_xcd_lk.store(xs[1] ? xs[1] : VS_XCD_MIN_ITEMS);
     vs::g_xcd_warp.store(xs[2] ? xs[2] : VS_XCD_MIN_ITEMS);
     vs::g_lk_ppg.store(v.lk_points_per_group ? v.lk_points_per_group : 1);
+    vs::g_det_rows.store(v.detect_segment_rows);
+    vs::g_fit_groups.store(v.fit_groups_in_flight ? v.fit_groups_in_flight : 2048);
     return VS_OK;
 }
 
@@ -65,6 +80,8 @@ extern "C" int vs_get_tuning(vs_tuning* t)
     t->xcd_min_items_lk = vs::g_xcd_lk.load();
     t->xcd_min_items_warp = vs::g_xcd_warp.load();
     t->lk_points_per_group = vs::g_lk_ppg.load();
+    t->detect_segment_rows = vs::g_det_rows.load();
+    t->fit_groups_in_flight = vs::g_fit_groups.load();
     return VS_OK;
 }
 

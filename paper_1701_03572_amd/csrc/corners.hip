@@ -808,7 +808,7 @@ int launch_detect(const IO& io, int n, int width, int height, int pitch, const v
     const int rw = width - 2 * p.roi_mx, rh = height - 2 * p.roi_my;
     // each output row belongs to one wave's segment and the survivors are sorted afterwards, so the
     // segment height only trades per-wave warm-up rows against waves per frame
-    const int sr = n <= 8 ? SR_FEW : SR;
+    const int sr = vs::detect_segment_rows(n, SR_FEW, SR);   // >= SR_FEW, which sizes the survivor list
     const int strips = (rw + SW - 1) / SW, segs = (rh + sr - 1) / sr;
     const int64_t nwaves = (int64_t)n * strips * segs;
     corner_response_kernel<<<(unsigned)((nwaves + 3) / 4), 256, 0, s>>>(io, width, height, pitch, p.roi_mx, p.roi_my, n,

@@ -910,9 +910,11 @@ int launch_fit(const char* who, const float* src, const float* dst, const uint8_
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (he != hipSuccess) return vs::set_error(VS_ERR_HIP, "%s: %s", who, hipGetErrorString(he));
     }
-    // spread each pair's hypotheses over workgroups until about 2048 are in flight (up to MAX_SPLIT
-    // per pair): the scoring loops are chains of dependent FP64 operations, hidden only by other waves
-    const int split = a.iters > 0 ? std::min(std::max((2048 + n - 1) / n, 1), MAX_SPLIT) : 1;
+    // spread each pair's hypotheses over workgroups until about fit_groups_in_flight (2048 by default)
+    // are in flight (up to MAX_SPLIT per pair): the scoring loops are chains of dependent FP64
+    // operations, hidden only by other waves
+    const int target = vs::fit_groups_in_flight();
+    const int split = a.iters > 0 ? std::min(std::max((target + n - 1) / n, 1), MAX_SPLIT) : 1;
     const Strided io{src, dst, valid, capacity, pair_index0, params, affine6, info, inliers};
     fit_hyp_kernel<<<n * split, NT, lds, s>>>(io, capacity, a, split, w8);
     int e = vs::check_launch(who);
@@ -940,7 +942,8 @@ int launch_fit_step(const vs::StepView& v, int n, const FitArgs& a, uint8_t* w8,
         if (he != hipSuccess) return vs::set_error(VS_ERR_HIP, "%s: %s", who, hipGetErrorString(he));
     }
     const Step io{v};
-    const int split = a.iters > 0 ? std::min(std::max((2048 + n - 1) / n, 1), MAX_SPLIT) : 1;
+    const int target = vs::fit_groups_in_flight();
+    const int split = a.iters > 0 ? std::min(std::max((target + n - 1) / n, 1), MAX_SPLIT) : 1;
     fit_hyp_kernel<<<n * split, NT, lds, s>>>(io, capacity, a, split, w8);
     int e = vs::check_launch(who);
     if (e) return e;

@@ -24,6 +24,10 @@ int check_launch(const char* what);
 enum { XCD_PYRAMID = 0, XCD_LK = 1, XCD_WARP = 2 };
 int xcd_min_items(int kernel);
 int lk_points_per_group();
+// rows per corner-response wave segment for a batch of n_items (few_rows / many_rows by default)
+int detect_segment_rows(int n_items, int few_rows, int many_rows);
+// hypothesis workgroups of a fit launch in flight
+int fit_groups_in_flight();
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 

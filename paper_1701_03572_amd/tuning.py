@@ -1,8 +1,8 @@
 """Launch-shape autotuner.
 
 The library's speed-only launch choices (``vs_set_tuning``: per-XCD mapping thresholds of the
-pyramid, tracking and warp launches, and points per tracking workgroup) never change a result
-bit. ``autotune`` times the candidates of each kernel family on a batch of the caller's class and
+pyramid, tracking and warp launches, points per tracking workgroup, the corner response's wave
+segment height and the fit's hypothesis workgroups in flight) never change a result bit. ``autotune`` times the candidates of each kernel family on a batch of the caller's class and
 keeps the fastest; the choice is cached in a JSON file keyed by GPU architecture, resolution class
 and corner-budget class, and ``apply`` installs a cached choice before a run.
 """
@@ -20,6 +20,8 @@ RES_CLASSES = [(320, 240), (640, 480), (1280, 720), (1920, 1080), (3840, 2160)]
 K_CLASSES = [256, 1024, 4096]
 XCD_CANDIDATES = [1, 8, 65536]        # always, from 8 items (the default), never
 LK_PPG_CANDIDATES = [1, 2, 4]
+DET_ROWS_CANDIDATES = [0, 12, 30, 60, 120]   # 0: by batch size (the default)
+FIT_GROUPS_CANDIDATES = [512, 1024, 2048, 4096, 8192]
 MARGIN = 0.015                        # a candidate replaces the default only if this much faster
 
 
@@ -29,13 +31,16 @@ class Tuning:
     xcd_lk: int = 8
     xcd_warp: int = 8
     lk_ppg: int = 1
+    det_rows: int = 0
+    fit_groups: int = 2048
 
     def to_c(self) -> V.vs_tuning:
-        return V.vs_tuning(self.xcd_pyramid, self.xcd_lk, self.xcd_warp, self.lk_ppg)
+        return V.vs_tuning(self.xcd_pyramid, self.xcd_lk, self.xcd_warp, self.lk_ppg, self.det_rows, self.fit_groups)
 
     @staticmethod
     def from_c(t: V.vs_tuning) -> "Tuning":
-        return Tuning(t.xcd_min_items_pyramid, t.xcd_min_items_lk, t.xcd_min_items_warp, t.lk_points_per_group)
+        return Tuning(t.xcd_min_items_pyramid, t.xcd_min_items_lk, t.xcd_min_items_warp, t.lk_points_per_group,
+                      t.detect_segment_rows, t.fit_groups_in_flight)
 
 
 def set_tuning(t: Tuning | None):
@@ -192,8 +197,34 @@ def autotune(frames: torch.Tensor, k: int, levels: int, win_half: int = 10, reps
     timings["warp"] = _compare({str(x): dataclasses.replace(base, xcd_pyramid=best_pyr, xcd_lk=xl, lk_ppg=gl, xcd_warp=x)
                                 for x in XCD_CANDIDATES}, step or warp_fn, reps, rounds)
     best_warp = int(_pick(timings["warp"], str(base.xcd_warp)))
+    cur = Tuning(best_pyr, xl, best_warp, gl)
 
-    t = Tuning(best_pyr, xl, best_warp, gl)
+    # corner response: wave segment height
+    det_fn = lambda: V.vs_detect_corners(frames, 5 * fs, w, h, w, seg, 5, None, 0, dp, k, xy, None, cnt, al, ws, wsb)
+    timings["detect"] = _compare({str(r): dataclasses.replace(cur, det_rows=r) for r in DET_ROWS_CANDIDATES},
+                                 step or det_fn, reps, rounds)
+    cur = dataclasses.replace(cur, det_rows=int(_pick(timings["detect"], str(base.det_rows))))
+
+    # fit: hypothesis workgroups in flight, on the pairs tracked above
+    set_tuning(cur)
+    lk_fn()
+    fp = V.vs_fit_params(V.VS_HYBRID, 128, 1.0, 1, 0, 10, 20, cx, cy)
+    fstate = torch.zeros(V.FIT_STATE_BYTES, dtype=torch.uint8, device=frames.device)
+    prm = torch.zeros((seg, 4), dtype=torch.float64, device=frames.device)
+    info = torch.zeros(seg * V.FIT_INFO_BYTES, dtype=torch.uint8, device=frames.device)
+    fwsb = V.vs_fit_workspace(seg, k)
+    fws = torch.empty(fwsb, dtype=torch.uint8, device=frames.device)
+    # the tracked pairs sit at every 5th record: their points as consecutive items
+    src5, dst5, st5 = (t[0::5][:seg].contiguous() for t in (xy, dst, st))
+
+    def fit_fn():
+        V.vs_fit_state_init(fstate)
+        V.vs_fit_similarity(src5, dst5, st5, k, seg, fp, 0, fstate, prm, info, None, fws, fwsb)
+    timings["fit"] = _compare({str(g): dataclasses.replace(cur, fit_groups=g) for g in FIT_GROUPS_CANDIDATES},
+                              step or fit_fn, reps, rounds)
+    cur = dataclasses.replace(cur, fit_groups=int(_pick(timings["fit"], str(base.fit_groups))))
+
+    t = cur
     set_tuning(t)
     if save:
         store(cache_key(device_arch(frames.device.index or 0), w, h, k), t, timings,

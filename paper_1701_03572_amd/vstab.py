@@ -29,7 +29,8 @@ class VsError(RuntimeError):
 
 class vs_tuning(C.Structure):
     _fields_ = [("xcd_min_items_pyramid", C.c_int32), ("xcd_min_items_lk", C.c_int32),
-                ("xcd_min_items_warp", C.c_int32), ("lk_points_per_group", C.c_int32)]
+                ("xcd_min_items_warp", C.c_int32), ("lk_points_per_group", C.c_int32),
+                ("detect_segment_rows", C.c_int32), ("fit_groups_in_flight", C.c_int32)]
 
 
 class vs_pyramid(C.Structure):

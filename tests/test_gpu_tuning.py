@@ -1,7 +1,8 @@
 """Launch tuning never changes a result: pyramids, corners, tracks (positions, statuses, round-trip
-errors, valid counts, work counters) and warps are bit-identical under every per-XCD mapping choice
-and 1, 2 or 4 points per tracking workgroup (a capacity that is not a multiple of the group size
-included). The autotuner times the candidates, installs the fastest and caches it."""
+errors, valid counts, work counters), warps and fits (parameters, 2x3 models, records, inlier flags,
+dwell state) are bit-identical under every per-XCD mapping choice, 1, 2 or 4 points per tracking
+workgroup (a capacity that is not a multiple of the group size included), any corner-response
+segment height and any number of fit workgroups in flight. The autotuner times the candidates, installs the fastest and caches it."""
 import numpy as np
 import pytest
 import torch
@@ -51,12 +52,25 @@ def run_all(frames, K=501, L=4):
     mats = torch.stack([a, -b, cx - a * cx + b * cy + 2.5, b, a, cy - b * cx - a * cy - 1.25], 1).contiguous()
     out = torch.empty_like(frames)
     V.vs_warp_frame(frames, fs, w, h, w, mats, 6, out, fs, w, n, 0)
+    # the fit of the tracked pairs (every 5th record) as consecutive items
+    src5, dst5, st5 = (t[0::5][:seg].contiguous() for t in (xy, dst, st))
+    fp = V.vs_fit_params(V.VS_HYBRID3, 128, 1.0, 5, 1, 10, 2, cx, cy)
+    fstate = torch.zeros(V.FIT_STATE_BYTES, dtype=torch.uint8, device="cuda")
+    V.vs_fit_state_init(fstate)
+    prm = torch.zeros((seg, 4), dtype=torch.float64, device="cuda")
+    m6 = torch.zeros((seg, 6), dtype=torch.float64, device="cuda")
+    info = torch.zeros(seg * V.FIT_INFO_BYTES, dtype=torch.uint8, device="cuda")
+    inl = torch.zeros((seg, K), dtype=torch.uint8, device="cuda")
+    fwsb = V.vs_fit_workspace(seg, K)
+    fws = torch.empty(fwsb, dtype=torch.uint8, device="cuda")
+    V.vs_fit_motion(src5, dst5, st5, K, seg, fp, 0, fstate, prm, m6, info, inl, fws, fwsb)
     torch.cuda.synchronize()
-    return [t.cpu().numpy() for t in (pyr, xy, cnt, dst, st, fe, nv, wk, out)]
+    return [t.cpu().numpy() for t in (pyr, xy, cnt, dst, st, fe, nv, wk, out, prm, m6, info, inl, fstate)]
 
 
 @pytest.mark.parametrize("t", [T.Tuning(1, 1, 1, 1), T.Tuning(65536, 65536, 65536, 2), T.Tuning(8, 8, 8, 4),
-                               T.Tuning(1, 65536, 8, 4)])
+                               T.Tuning(1, 65536, 8, 4), T.Tuning(det_rows=12, fit_groups=64),
+                               T.Tuning(det_rows=240, fit_groups=16384), T.Tuning(det_rows=37, fit_groups=100)])
 def test_results_do_not_depend_on_the_tuning(t):
     frames = dev(synth.make_sequence("vga", n_frames=46).frames)      # 9 items: above and below the thresholds
     ref = run_all(frames)
@@ -74,6 +88,6 @@ def test_autotune_installs_and_caches(tmp_path):
     t, timings = T.autotune(frames, 300, 4, reps=2, path=path)
     say("autotuned", t, {k: min(v.values()) for k, v in timings.items()})
     assert T.get_tuning() == t
-    assert set(timings) == {"pyramid", "lk", "warp"} and len(timings["lk"]) == 9
+    assert set(timings) == {"pyramid", "lk", "warp", "detect", "fit"} and len(timings["lk"]) == 9
     T.set_tuning(None)
     assert T.apply(640, 480, 300, path) == t and T.get_tuning() == t

@@ -19,12 +19,16 @@ def test_defaults_and_round_trip():
     t = T.Tuning(1, 65536, 3, 4)
     T.set_tuning(t)
     assert T.get_tuning() == t
-    T.set_tuning(T.Tuning(0, 0, 0, 0))          # zeros select the defaults
-    assert T.get_tuning() == T.Tuning(8, 8, 8, 1)
+    T.set_tuning(T.Tuning(0, 0, 0, 0, 0, 0))    # zeros select the defaults
+    assert T.get_tuning() == T.Tuning(8, 8, 8, 1, 0, 2048)
+    t = T.Tuning(det_rows=30, fit_groups=512)
+    T.set_tuning(t)
+    assert T.get_tuning() == t
 
 
 @pytest.mark.parametrize("bad", [T.Tuning(-1, 8, 8, 1), T.Tuning(8, 65537, 8, 1), T.Tuning(8, 8, 8, 3),
-                                 T.Tuning(8, 8, 8, 8)])
+                                 T.Tuning(8, 8, 8, 8), T.Tuning(det_rows=11), T.Tuning(det_rows=241),
+                                 T.Tuning(fit_groups=63), T.Tuning(fit_groups=16385)])
 def test_rejected_settings_change_nothing(bad):
     T.set_tuning(T.Tuning(1, 1, 1, 2))
     with pytest.raises(V.VsError):
