@@ -378,8 +378,9 @@ __device__ __forceinline__ void window_samples(const Img& A, int ix, int iy, int
 
 // The set-up's two blocks when both lie inside their levels and a lane holds at most 7 rows: the
 // previous-frame window block (24 rows) and the first iterate's next-frame block (22 rows) are loaded
-// together, so the two global-memory latencies overlap, staged in two areas of the wave's LDS and read
-// as in window_samples and load_next_block (same arithmetic, same results).
+// together, so the two global-memory latencies overlap, and staged in two areas of the wave's LDS;
+// the previous-frame block's arithmetic runs while the next-frame block is still arriving. Both are
+// read as in window_samples and load_next_block (same arithmetic, same results).
 template <int RMAX, bool WEIGHTED>
 __device__ __forceinline__ void setup_staged(const Img& A, const Img& B, int bx, int by, int nbx, int nby,
                                              int lane_off, float a, float b, int nrows, bool active, float* red,
@@ -401,14 +402,16 @@ __device__ __forceinline__ void setup_staged(const Img& A, const Img& B, int bx,
     if (r < STAGE_ROWS - 2)
         vn = __builtin_amdgcn_raw_buffer_load_b128(B.rs, (int)__umul24((unsigned)(nby + r), (unsigned)B.pitch) + nc0 + 16 * h,
                                                    0, 0);
+    // the previous-frame block first: its arithmetic overlaps the next-frame block's load
     if (r < STAGE_ROWS) *reinterpret_cast<u32x4*>(sprev + 8 * r + 4 * h) = vp;
-    if (r < STAGE_ROWS - 2) *reinterpret_cast<u32x4*>(snext + 8 * r + 4 * h) = vn;
     wave_lds_sync();
     // lanes outside the window read the zeroed area
     const uint32_t* zero = reinterpret_cast<const uint32_t*>(red + RED_FLOATS);
     const int op = lane_off + (bx - pc0), on = lane_off + (nbx - nc0);
     staged_terms<RMAX, WEIGHTED>(active ? sprev + (op >> 2) : zero, active ? (unsigned)(op & 3) : 0u, a, b, nrows, I, Ix,
                                  Iy);
+    if (r < STAGE_ROWS - 2) *reinterpret_cast<u32x4*>(snext + 8 * r + 4 * h) = vn;
+    wave_lds_sync();
     const uint32_t* np = active ? snext + (on >> 2) : zero;
     const unsigned nsh = active ? (unsigned)(on & 3) : 0u;
 #pragma unroll
