@@ -272,6 +272,16 @@ class Stabilizer:
         self.j = 0
         self.frames = {}           # frames pushed and not yet emitted (held alive for the device)
 
+    def rebind(self, P: StabParams):
+        """Reuse these buffers for a stream that differs only in its corner budget, RANSAC seed and
+        stream id (same geometry, capacity and other parameters); call before it is (re)started."""
+        assert P.replace(max_corners=0, seed=0, stream_id=0) == self.P.replace(max_corners=0, seed=0, stream_id=0)
+        assert P.max_corners <= self.cap
+        self.P = P
+        self._s.detect.max_corners = P.max_corners
+        self._s.fit.seed = P.seed
+        self._s.fit.stream_id = P.stream_id
+
     def _collect(self, first: int, n: int) -> list:
         out = [(e, self.out[e % self.out_slots]) for e in range(first, first + n)]
         keep = min(first + n, self.j - 1)

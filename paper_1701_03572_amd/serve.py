@@ -15,6 +15,9 @@ buffers, before anything is allocated (plus the class's batch workspace when the
 stream that does not fit, or that would exceed the concurrency cap, waits in a FIFO queue with its
 arriving frames buffered on the host, and is admitted, with all its frames, when a finished stream
 releases memory. Each stream keeps its pyramids, points, fit state and trajectory on the device.
+The buffers of a finished stream stay with its class (still counted against the budget) and are
+reused by the next stream of that class, so admissions in steady state allocate nothing; pooled
+buffers are released when a new stream needs their memory.
 Streams share no state, so a stream's outputs are the same alone and in a mix (tested bit for bit).
 
 ``simulate`` replays a workload in virtual time: paced (frames submitted at their arrival times,
@@ -25,6 +28,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import gc
 import math
 import time
 
@@ -56,6 +60,7 @@ class _Class:
     queue: torch.cuda.Stream
     reserved: int
     members: dict = dataclasses.field(default_factory=dict)    # slot -> _Member
+    pool: list = dataclasses.field(default_factory=list)       # (Stabilizer, reserved bytes) of finished streams
 
 
 def class_key(width: int, height: int, P: StabParams) -> tuple:
@@ -95,11 +100,47 @@ class StreamServer:
                                                self.detect_chunk)
         return sb_proto
 
-    def _fits(self, m: _Member) -> bool:
-        return (len(self.streams) < self.max_concurrent and
-                self.used + self._member_bytes(m) + self._class_bytes(m) <= self.budget)
+    def _pooled(self, m: _Member) -> bool:
+        cls = self.classes.get(m.key)
+        return cls is not None and bool(cls.pool)
 
-    def _admit(self, m: _Member):
+    def _fits(self, m: _Member) -> bool:
+        if len(self.streams) >= self.max_concurrent:
+            return False
+        if self._pooled(m):
+            return True                      # reuses a pooled stream's buffers (already counted)
+        need = self._member_bytes(m) + self._class_bytes(m)
+        if self.used + need <= self.budget:
+            return True
+        # release pooled buffers of other classes, and empty classes, until it fits
+        for key, cls in list(self.classes.items()):
+            while cls.pool and self.used + need > self.budget:
+                _, b = cls.pool.pop()
+                self.used -= b
+            if not cls.members and not cls.pool and key != m.key:
+                del self.classes[key]
+                self.used -= cls.reserved
+                need = self._member_bytes(m) + self._class_bytes(m)
+        return self.used + need <= self.budget
+
+    def prepare(self, width: int, height: int, P: StabParams, streams: int = 0) -> bool:
+        """Creates the class of (width, height, P) ahead of its first stream, with ``streams`` pooled
+        members, so that first admissions allocate nothing. Returns False if it does not fit."""
+        m = _Member(-1, class_key(width, height, P), P, width, height, 0)
+        need = self._class_bytes(m) + streams * self._member_bytes(m)
+        if self.used + need > self.budget:
+            return False
+        self._ensure_class(m)
+        cls = self.classes[m.key]
+        lag = self._lag(P)
+        with torch.cuda.stream(cls.queue):
+            for _ in range(streams):
+                b = self._member_bytes(m)
+                cls.pool.append((cls.batch.member(P, ring=max(self.ring_frames, lag + 2)), b))
+                self.used += b
+        return True
+
+    def _ensure_class(self, m: _Member):
         cb = self._class_bytes(m)
         if cb:
             q = torch.cuda.Stream(device=self.dev)
@@ -108,13 +149,20 @@ class StreamServer:
                                  self.capacity, self.max_concurrent, self.detect_chunk, device=self.dev)
             self.classes[m.key] = _Class(sb, q, cb)
             self.used += cb
+
+    def _admit(self, m: _Member):
+        self._ensure_class(m)
         cls = self.classes[m.key]
-        m.reserved = self._member_bytes(m)
-        self.used += m.reserved
         lag = self._lag(m.P)
-        # the member's buffers are allocated on the class's queue, which is the only stream using them
+        # the member's buffers live on the class's queue, which is the only stream using them
         with torch.cuda.stream(cls.queue):
-            m.stab = cls.batch.member(m.P, ring=max(self.ring_frames, lag + 2))
+            if cls.pool:
+                m.stab, m.reserved = cls.pool.pop()
+                m.stab.rebind(m.P)
+            else:
+                m.reserved = self._member_bytes(m)
+                self.used += m.reserved
+                m.stab = cls.batch.member(m.P, ring=max(self.ring_frames, lag + 2))
             m.slot = cls.batch.attach(m.stab)
         cls.members[m.slot] = m
         self.streams[m.sid] = m
@@ -183,8 +231,8 @@ class StreamServer:
         return out
 
     def _finish(self, timing: bool = False, on_emit=None) -> list:
-        """Ends the closed streams whose frames are all processed, releases their memory and admits
-        queued streams that now fit."""
+        """Ends the closed streams whose frames are all processed (their buffers go to the class's
+        pool) and admits queued streams that now fit."""
         out = []
         for m in [m for m in self.streams.values() if m.closing and not m.pending]:
             cls = self.classes[m.key]
@@ -200,11 +248,8 @@ class StreamServer:
                             on_emit(m.sid, e, view)
             del cls.members[m.slot]
             del self.streams[m.sid]
-            self.used -= m.reserved
+            cls.pool.append((st, m.reserved))     # kept for the class's next stream, still reserved
             m.stab = None
-            if not cls.members:
-                del self.classes[m.key]
-                self.used -= cls.reserved
         while self.waiting and self._fits(self.waiting[0]):
             self._admit(self.waiting.popleft())
         return out
@@ -217,6 +262,16 @@ class StreamServer:
         if self.waiting and not self.streams:
             raise RuntimeError("a queued stream can never be admitted within the budget")
         return out
+
+    def release_idle(self):
+        """Frees pooled buffers and classes without streams (their memory leaves the budget)."""
+        for key, cls in list(self.classes.items()):
+            while cls.pool:
+                _, b = cls.pool.pop()
+                self.used -= b
+            if not cls.members:
+                del self.classes[key]
+                self.used -= cls.reserved
 
 
 @dataclasses.dataclass(frozen=True)
@@ -266,24 +321,37 @@ def poisson_workload(duration_s: float, rate: float, lifetime_s: tuple, fps: flo
 
 
 def simulate(server: StreamServer, workload: list, pools: list, paced: bool, max_inflight: int = 2,
-             on_emit=None) -> dict:
+             on_emit=None, measure_from: float = 0.0, keep_latencies: bool = False) -> dict:
     """Replay ``workload`` (ServedStream list) against ``server``. ``pools[clip]`` is a pinned host
     uint8 tensor [m, H, W] each stream plays cyclically from its offset. Ticks are issued whenever
     frames are buffered and fewer than ``max_inflight`` ticks are still running on the GPU, so the
     batch of a tick is whatever arrived while the previous ones ran. ``on_emit`` is passed to
-    ``StreamServer.tick``. Returns per-frame latencies (paced) and throughput."""
+    ``StreamServer.tick``. Returns per-frame latencies (paced; of the frames arriving at or after
+    ``measure_from`` s, so a warm-up period can be left out) and throughput."""
     events = []             # (time, order, kind, stream, frame index): kind 0 = frame, 1 = end of stream
     for s in workload:
         for j in range(s.n_frames):
             events.append((s.arrival + j / s.fps, 0, s, j))
         events.append((s.arrival + (s.n_frames - 1) / s.fps, 1, s, s.n_frames))
     events.sort(key=lambda e: (e[0], e[2].sid, e[1], e[3]))
-    arrival = {}
-    done = []               # (arrival s, event)
-    inflight = collections.deque()
     for q in [c.queue for c in server.classes.values()]:
         q.synchronize()
     torch.cuda.synchronize()
+    # the replay loop creates many short-lived objects: the cyclic garbage collector is paused during
+    # it, as a serving loop would pause it, so its pauses do not land in the measured latencies
+    gc_was_enabled = gc.isenabled()
+    gc.disable()
+    try:
+        return _replay(server, events, pools, paced, max_inflight, on_emit, measure_from, keep_latencies)
+    finally:
+        if gc_was_enabled:
+            gc.enable()
+
+
+def _replay(server, events, pools, paced, max_inflight, on_emit, measure_from, keep_latencies) -> dict:
+    arrival = {}
+    done = []               # (arrival s, event)
+    inflight = collections.deque()
     start = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     start.record()
@@ -335,11 +403,17 @@ def simulate(server: StreamServer, workload: list, pools: list, paced: bool, max
     gpu_total_ms = start.elapsed_time(end)
     res = {"frames_out": n_out, "frames_in": len(arrival), "wall_s": wall, "gpu_s": gpu_total_ms / 1e3,
            "frames_per_s": n_out / max(gpu_total_ms / 1e3, 1e-9), "latency_ms_p50": None, "latency_ms_p99": None,
-           "streams": len(workload), "ticks": server.ticks, "mean_items_per_push": server.items / max(server.ticks, 1),
+           "streams": len({e[2].sid for e in events}), "ticks": server.ticks, "mean_items_per_push": server.items / max(server.ticks, 1),
            "max_concurrent": max_conc}
     if paced and done:
         # completion on the GPU timeline (relative to the start event, recorded at t0) minus arrival
+        arr = np.array([t for t, ev in done])
         lat = np.array([start.elapsed_time(ev) / 1e3 - t for t, ev in done])
-        res["latency_ms_p50"] = float(np.percentile(lat, 50) * 1e3)
-        res["latency_ms_p99"] = float(np.percentile(lat, 99) * 1e3)
+        sel = lat[arr >= measure_from]
+        res["latency_ms_p50"] = float(np.percentile(sel, 50) * 1e3)
+        res["latency_ms_p99"] = float(np.percentile(sel, 99) * 1e3)
+        res["latency_frames"] = int(sel.size)
+        if keep_latencies:
+            res["arrivals_s"] = arr
+            res["latencies_s"] = lat
     return res

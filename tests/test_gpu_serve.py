@@ -8,7 +8,8 @@ admitted streams of a class are processed together in ticks.
   everywhere (the oracle tracks in binary64; the per-stage parity of the same kernels is tested
   elsewhere).
 * Admission checks the HBM budget before allocating; streams that do not fit wait with their frames
-  buffered, every frame of every stream is emitted, and the reserved memory returns to 0.
+  buffered, every frame of every stream is emitted, finished streams' buffers are reused by later
+  streams of their class, and the reserved memory returns to 0 once idle buffers are released.
 * A short paced replay of Poisson arrivals reports latencies and throughput.
 """
 import numpy as np
@@ -114,6 +115,8 @@ def test_admission_by_budget_buffers_frames_and_releases_memory():
     assert torch.cuda.memory_allocated() - before <= probe.used    # the reservation covers what was allocated
     probe.close(0)
     probe.drain()
+    assert probe.used > 0 and len(probe.classes[next(iter(probe.classes))].pool) == 1   # buffers pooled
+    probe.release_idle()
     assert probe.used == 0 and not probe.classes
     budget = cls_bytes + int(2.5 * one)                              # room for two streams at a time
     clips = [host_clip("tiny", 6 + k, 70 + k) for k in range(4)]
@@ -131,7 +134,10 @@ def test_admission_by_budget_buffers_frames_and_releases_memory():
         server.tick(on_emit=on_emit)
         assert server.used <= server.budget and len(server.streams) <= 2
     torch.cuda.synchronize()
-    assert server.used == 0 and not server.streams and not server.waiting
+    assert not server.streams and not server.waiting
+    assert server.used == cls_bytes + 2 * one          # two streams' buffers pooled, reused by the later two
+    server.release_idle()
+    assert server.used == 0 and not server.classes
     for k, c in enumerate(clips):
         assert sorted(e for s, e in outs if s == k) == list(range(c.shape[0]))
     with pytest.raises(RuntimeError):
@@ -155,3 +161,18 @@ def test_paced_poisson_replay():
     say(sat)
     assert sat["frames_out"] == res["frames_out"] and sat["frames_per_s"] > 0 and sat["latency_ms_p99"] is None
     assert sat["mean_items_per_push"] > 1
+
+
+def test_prepared_classes_and_pooled_buffers_give_the_same_outputs():
+    """A stream served on reused (pooled) buffers of an earlier stream equals the stream served on
+    fresh buffers, bit for bit."""
+    a = host_clip("tiny", 9, 81)
+    b = host_clip("tiny", 7, 82)
+    PA = StabParams(levels=3, max_corners=200, smooth_mode=SMOOTH_CAUSAL, stream_id=1, seed=5)
+    PB = StabParams(levels=3, max_corners=120, smooth_mode=SMOOTH_CAUSAL, stream_id=2, seed=6)
+    fresh = serve(StreamServer(8 * GB, capacity=200), [(2, b, PB, 0)])
+    server = StreamServer(8 * GB, capacity=200)
+    assert server.prepare(320, 240, PA, streams=1)
+    reused = serve(server, [(1, a, PA, 0), (2, b, PB, 9)])      # b starts after a ended: a's buffers
+    for e in range(7):
+        np.testing.assert_array_equal(fresh[(2, e)], reused[(2, e)])
