@@ -1,28 +1,28 @@
 // detect_corners: Shi-Tomasi response + 3x3 NMS over the ROI, then the ordered greedy top-K.
 //
 // Kernel 1 (corner_response): each wave walks down a 240-column strip of the ROI, 60 output rows at a
-// time; lane i owns 4 columns. Per pixel row it forms, in registers, the Sobel terms (byte dot
-// products), the tensor products and their 3x3 box sums (exact int32), an FP32 estimate of the score
-// with a bounded relative error, and a separable 3x3 max of the estimates; neighbouring lanes' edge
-// columns arrive by DPP wave shifts. A pixel whose neighbours' estimates are all below its own by
-// more than the error band survives; one whose neighbours are above by more than the band is
-// dropped; a pixel inside the band survives flagged. Survivors are appended (one atomic per wave and
-// row) as their exact box-summed tensor (A, B, C) and pixel index.
+// time; lane i owns 4 columns. Per pixel row it forms, in registers, the Sobel terms, the tensor
+// products and their 3x3 box sums (all integers below 2^24, so exact in FP32), an FP32 estimate of
+// the score with a bounded relative error, and a separable 3x3 max of the estimates; neighbouring
+// lanes' edge columns arrive by DPP wave shifts. A pixel whose neighbours' estimates are all below
+// its own by more than the error band survives; one whose neighbours are above by more than the band
+// is dropped; a pixel inside the band survives flagged. Survivors queue in the wave's LDS as their
+// exact box-summed tensor (A, B, C) and pixel index. Every 64 queued survivors, one per lane, get
+// their exact binary64 score 2 det / (tr + sqrt(disc)); a flagged one is compared exactly against its
+// in-ROI neighbours, recomputed from the image. The survivors that remain queue again in LDS as
+// (score bits, index) and are appended to the item's candidate lists 256 at a time with one atomic;
+// the wave's largest score is folded into the item's maximum with one integer atomic max on the
+// score's bit pattern (non-negative doubles order like their bits). The candidates are exactly the
+// set of 3x3 maxima of the exact scores; nothing but them reaches global memory.
 //
-// Kernel 2 (corner_keys): one thread per appended survivor computes the exact binary64 score
-// 2 det / (tr + sqrt(disc)) from exact det/tr/disc; a flagged survivor is compared exactly against
-// its in-ROI neighbours, recomputed from the image. Survivors that remain are written, compacted, to
-// the item's candidate list, and the item's maximum score is folded in with an integer atomic max on
-// the score's bit pattern (non-negative doubles order like their bits). The result is exactly the
-// set of 3x3 maxima of the exact scores.
-//
-// Kernel 3 (corner_select): one 1024-thread workgroup per item. Candidates below
+// Kernel 2 (corner_select): one 1024-thread workgroup per item. Candidates below
 // quality * max are dropped. The order is (score desc, y asc, x asc), i.e. the composite key
 // V = (bits(score) - bits(threshold)) * 2^32 + (2^32 - 1 - y * W - x) taken descending. Batches of
-// the next ~2048 keys are cut out by a most-significant-digit radix select (11-bit digits),
-// bitonic-sorted in LDS and fed to the greedy minimum-distance test 64 at a time: all 16 waves
-// test a group against the accepted set, then one wave resolves conflicts inside the group in
-// order. The result equals the sequential greedy over the full sorted list.
+// the next ~2048 keys are cut out by a most-significant-digit radix select (11-bit digits; the
+// passes over the score bits read only the scores), bitonic-sorted in LDS and fed to the greedy
+// minimum-distance test 64 at a time: all 16 waves test a group against the accepted set, then one
+// wave resolves conflicts inside the group in order. The result equals the sequential greedy over
+// the full sorted list.
 #include "vs_common.hpp"
 
 namespace {
@@ -31,8 +31,8 @@ typedef unsigned __int128 u128;
 
 struct CandHeader {
     uint32_t count;        // candidates (exact 3x3 maxima) in the key/index lists
-    uint32_t raw_count;    // survivor-list entries reserved by the response kernel (unused ones are marked)
-    uint64_t lmax_bits;
+    uint32_t unused;
+    uint64_t lmax_bits;    // bit pattern of the largest candidate score (0: none yet)
 };
 
 constexpr int64_t HDR = 256;
@@ -44,23 +44,26 @@ constexpr int CAP = 4096;       // LDS batch capacity of the selection
 constexpr int BATCH = 2048;     // keys requested per batch
 constexpr int DIGIT = 11;
 constexpr int NBIN = 1 << DIGIT;
-// Each response wave reserves its survivor-list entries RAW_CHUNK at a time (one atomic per chunk
-// rather than one per row on the frame's single counter, whose atomics serialise in L2); entries
-// of a chunk it does not fill are marked RAW_UNUSED.
-constexpr uint32_t RAW_CHUNK = 256;   // >= 4 columns x 64 lanes, so one row's survivors always fit
-constexpr uint32_t RAW_UNUSED = 0xFFFFFFFFu;
+// LDS queues of one response wave. Survivors are scored 64 at a time, so fewer than 64 wait after a
+// row's scoring and one row adds at most 4 x 62; kept candidates are appended KFLUSH at a time, so
+// fewer than KFLUSH wait before a chunk adds at most 64.
+constexpr int QCAP = 320;
+constexpr int KFLUSH = 256;
+constexpr int KCAP = KFLUSH + 64;
+static_assert(63 + 4 * 62 <= QCAP && KFLUSH - 1 + 64 <= KCAP, "queue capacities");
 
-// response waves of one item at most (the smaller segment height, strips over the whole width)
-__host__ __device__ inline int64_t max_waves(int w, int h) { return (int64_t)(w / SW + 2) * (h / SR_FEW + 2); }
+struct WaveQueues {
+    uint4 surv[QCAP];        // A, B, C (bits of exact floats), pixel index | flag << 31
+    uint64_t key[KCAP];      // bits of the exact score
+    uint32_t idx[KCAP];
+};
+constexpr int RESP_WAVES = 4;   // waves per response workgroup
 
-// per item: header | keys (8 B each) | indices (4 B) | survivors (16 B: A, B, C, index | flag << 31);
-// the key and index lists have room for one entry per pixel, the survivor list also for one
-// partly filled chunk per response wave
-__host__ __device__ inline int64_t raw_entries(int w, int h) { return (int64_t)w * h + max_waves(w, h) * RAW_CHUNK; }
+// per item: header | keys (8 B each) | indices (4 B), each list with room for one entry per pixel
 __host__ __device__ inline int64_t per_item_bytes(int w, int h)
 {
     const int64_t c = (int64_t)w * h;
-    return (HDR + 8 * c + 4 * c + 16 * raw_entries(w, h) + 255) & ~(int64_t)255;
+    return (HDR + 12 * c + 255) & ~(int64_t)255;
 }
 
 __device__ __forceinline__ CandHeader* hdr_of(uint8_t* ws, int64_t item_bytes, int item)
@@ -74,10 +77,6 @@ __device__ __forceinline__ uint64_t* keys_of(uint8_t* ws, int64_t item_bytes, in
 __device__ __forceinline__ uint32_t* idx_of(uint8_t* ws, int64_t item_bytes, int item, int w, int h)
 {
     return reinterpret_cast<uint32_t*>(ws + item * item_bytes + HDR + 8 * (int64_t)w * h);
-}
-__device__ __forceinline__ uint4* raw_of(uint8_t* ws, int64_t item_bytes, int item, int w, int h)
-{
-    return reinterpret_cast<uint4*>(ws + item * item_bytes + HDR + 12 * (int64_t)w * h);
 }
 
 // Item addressing of a strided call: item i reads frames + i * frame_stride and owns the records
@@ -140,16 +139,16 @@ __global__ void detect_init_kernel(uint8_t* ws, int64_t item_bytes, int n, IO io
     if (i >= n || io.off(i)) return;
     CandHeader* h = hdr_of(ws, item_bytes, i);
     h->count = 0;
-    h->raw_count = 0;
     h->lmax_bits = 0;
 }
 
-// Exact binary64 score 2 det / (tr + sqrt(disc)) of the box-summed tensor. With |A|, |B|, |C| < 2^24
-// every product and sum below is an integer below 2^53, so det, tr and disc are exact and equal
-// to their 64-bit integer values; sqrt, add and divide are single correctly rounded operations.
-__device__ __forceinline__ double exact_key(int32_t A, int32_t B, int32_t C)
+
+// Exact binary64 score 2 det / (tr + sqrt(disc)) of the box-summed tensor (integers, passed as
+// doubles). With |A|, |B|, |C| < 2^24 every product and sum below is an integer below 2^53, so det,
+// tr and disc are exact and equal to their 64-bit integer values; sqrt, add and divide are single
+// correctly rounded operations.
+__device__ __forceinline__ double exact_key(double a, double b, double c)
 {
-    const double a = (double)A, b = (double)B, c = (double)C;
     const double det = a * c - b * b;
     const double tr = a + c;
     const double dm = a - c;
@@ -164,9 +163,8 @@ __device__ __forceinline__ double exact_key(int32_t A, int32_t B, int32_t C)
 // fused rounding over non-negative terms (A - C is exact); with the sum A + C, the square root and
 // the reciprocal (each within one ulp) and the final product the relative error stays below 10u
 // (6e-7).
-__device__ __forceinline__ float approx_key(int32_t A, int32_t B, int32_t C)
+__device__ __forceinline__ float approx_key(float a, float b, float c)
 {
-    const float a = (float)A, b = (float)B, c = (float)C;
     const float w = b * b;
     const float e = fmaf(-b, b, w);        // w - b^2, exactly
     const float det = fmaf(a, c, -w) + e;
@@ -213,29 +211,87 @@ __device__ __forceinline__ float dpp_f(float v)
 
 // Register state of one lane's 4 columns, indexed by pixel-row step modulo 3 (horizontal Sobel terms,
 // horizontal box sums of the products, 3x3 maxima of the estimates) or modulo 2 (box sums, estimates,
-// side maxima). All indices are compile-time constants after unrolling.
+// side maxima). All indices are compile-time constants after unrolling. Every tensor value is an
+// integer below 2^24 in magnitude held exactly in FP32.
 struct RespState {
-    int dx[3][4], sy[3][4];
-    int ha[3][4], hb[3][4], hc[3][4];
-    int sa[2][4], sb[2][4], sc[2][4];
+    float dx[3][4], sy[3][4];
+    float ha[3][4], hb[3][4], hc[3][4];
+    float sa[2][4], sb[2][4], sc[2][4];
     float sv[2][4], hm[3][4], sd[2][4];
-    uint32_t cbase, cfill;   // the wave's current survivor chunk (wave-uniform) and its fill
+    int qn, kn;          // queued survivors and queued kept candidates (wave-uniform)
+    uint64_t kmax;       // the lane's largest kept score bits
 };
-
-// marks entries [from, to) of the survivor list unused (the whole wave writes them)
-__device__ __forceinline__ void mark_unused(uint4* raw, uint32_t from, uint32_t to, int lane)
-{
-    for (uint32_t i = from + lane; i < to; i += 64) raw[i] = make_uint4(0u, 0u, 0u, RAW_UNUSED);
-}
 
 struct RespCtx {
     int lane, xb, oy, oy_end;
     int rx0, rx1, ry0, ry1;
     int out_lo, out_hi;          // output columns of this strip
-    int W;
-    uint32_t* raw_count;
-    uint4* raw;
+    int W, pitch;
+    const uint8_t* img;
+    uint32_t* count;             // the item's candidate count
+    uint64_t* keys;              // the item's candidate lists (room for one entry per pixel)
+    uint32_t* idx;
+    WaveQueues* q;               // this wave's LDS queues
 };
+
+// Appends the queued kept candidates to the item's lists (one atomic) and empties the queue.
+__device__ __forceinline__ void flush_kept(RespState& st, const RespCtx& cx)
+{
+    vs::wave_lds_sync();
+    uint32_t b = 0;
+    if (cx.lane == 0) b = atomicAdd(cx.count, (uint32_t)st.kn);
+    const uint32_t base = (uint32_t)__builtin_amdgcn_readfirstlane((int)b);
+    for (int i = cx.lane; i < st.kn; i += 64) {
+        cx.keys[base + i] = cx.q->key[i];
+        cx.idx[base + i] = cx.q->idx[i];
+    }
+    st.kn = 0;
+    vs::wave_lds_sync();
+}
+
+// whether an in-ROI neighbour of (x, y) has an exact score above `key` (the exact NMS of a flagged
+// survivor; the neighbours' tensors are recomputed from the image)
+__device__ bool beaten_by_neighbour(const RespCtx& cx, int x, int y, double key)
+{
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int nx = x + dx, ny = y + dy;
+            if ((dx == 0 && dy == 0) || nx < cx.rx0 || nx >= cx.rx1 || ny < cx.ry0 || ny >= cx.ry1) continue;
+            int32_t A, B, C;
+            tensor_from_image(cx.img, cx.pitch, nx, ny, A, B, C);
+            if (exact_key((double)A, (double)B, (double)C) > key) return true;
+        }
+    return false;
+}
+
+// Exact scores of the queued survivors [h, h + cnt), cnt <= 64, one per lane; those that remain
+// queue as kept candidates, written out once KFLUSH are queued.
+__device__ __forceinline__ void score_chunk(RespState& st, const RespCtx& cx, int h, int cnt)
+{
+    vs::wave_lds_sync();
+    bool keep = false;
+    uint64_t kb = 0;
+    uint32_t ix = 0;
+    if (cx.lane < cnt) {
+        const uint4 r = cx.q->surv[h + cx.lane];
+        ix = r.w & 0x7FFFFFFFu;
+        const double key = exact_key((double)__uint_as_float(r.x), (double)__uint_as_float(r.y),
+                                     (double)__uint_as_float(r.z));
+        keep = key > 0.0;
+        if (keep && (r.w >> 31))
+            keep = !beaten_by_neighbour(cx, (int)(ix % (uint32_t)cx.W), (int)(ix / (uint32_t)cx.W), key);
+        kb = (uint64_t)__double_as_longlong(key);
+    }
+    const uint64_t bal = __ballot(keep);
+    if (keep) {
+        const int pos = st.kn + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        cx.q->key[pos] = kb;
+        cx.q->idx[pos] = ix;
+        if (kb > st.kmax) st.kmax = kb;
+    }
+    st.kn += __popcll(bal);
+    if (st.kn >= KFLUSH) flush_kept(st, cx);
+}
 
 // One pixel-row step. T is the step number modulo SUP; GRAD/BOX/NMS switch the pipeline stages on.
 // Pixel row yp = oy - 3 + t; gradients for row yp - 1; box sums and estimates for row yp - 2; NMS
@@ -246,50 +302,53 @@ __device__ __forceinline__ void resp_step(RespState& st, uint32_t P, int t, cons
     constexpr int i3 = T % 3, m3 = (T + 2) % 3, mm3 = (T + 1) % 3;   // t, t-1, t-2 (mod 3)
     constexpr int i2 = T % 2, m2 = (T + 1) % 2;                       // t, t-1 (mod 2)
     const uint32_t L = (uint32_t)dpp_i<DPP_SHR>((int)P), R = (uint32_t)dpp_i<DPP_SHL>((int)P);
+    const float p0 = (float)(P & 0xffu), p1 = (float)((P >> 8) & 0xffu), p2 = (float)((P >> 16) & 0xffu);
+    const float p3 = (float)(P >> 24), pl = (float)(L >> 24), pr = (float)(R & 0xffu);
     // horizontal Sobel terms: (1,2,1) smoothing and central difference
-    st.sy[i3][0] = (int)__builtin_amdgcn_udot4(L, 0x01000000u, __builtin_amdgcn_udot4(P, 0x00000102u, 0, false), false);
-    st.sy[i3][1] = (int)__builtin_amdgcn_udot4(P, 0x00010201u, 0, false);
-    st.sy[i3][2] = (int)__builtin_amdgcn_udot4(P, 0x01020100u, 0, false);
-    st.sy[i3][3] = (int)__builtin_amdgcn_udot4(R, 0x00000001u, __builtin_amdgcn_udot4(P, 0x02010000u, 0, false), false);
-    const int b0 = (int)(P & 0xff), b1 = (int)((P >> 8) & 0xff), b2 = (int)((P >> 16) & 0xff), b3 = (int)(P >> 24);
-    st.dx[i3][0] = b1 - (int)(L >> 24);
-    st.dx[i3][1] = b2 - b0;
-    st.dx[i3][2] = b3 - b1;
-    st.dx[i3][3] = (int)(R & 0xff) - b2;
+    st.sy[i3][0] = fmaf(2.0f, p0, pl) + p1;
+    st.sy[i3][1] = fmaf(2.0f, p1, p0) + p2;
+    st.sy[i3][2] = fmaf(2.0f, p2, p1) + p3;
+    st.sy[i3][3] = fmaf(2.0f, p3, p2) + pr;
+    st.dx[i3][0] = p1 - pl;
+    st.dx[i3][1] = p2 - p0;
+    st.dx[i3][2] = p3 - p1;
+    st.dx[i3][3] = pr - p2;
     if constexpr (GRAD) {
-        int A[4], B[4], C[4];
+        float A[4], B[4], C[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const int gx = st.dx[mm3][c] + 2 * st.dx[m3][c] + st.dx[i3][c];
-            const int gy = st.sy[i3][c] - st.sy[mm3][c];
-            A[c] = __mul24(gx, gx);
-            B[c] = __mul24(gx, gy);
-            C[c] = __mul24(gy, gy);
+            const float gx = fmaf(2.0f, st.dx[m3][c], st.dx[mm3][c]) + st.dx[i3][c];
+            const float gy = st.sy[i3][c] - st.sy[mm3][c];
+            A[c] = gx * gx;
+            B[c] = gx * gy;
+            C[c] = gy * gy;
         }
-        const int al = dpp_i<DPP_SHR>(A[3]), ar = dpp_i<DPP_SHL>(A[0]);
-        const int bl = dpp_i<DPP_SHR>(B[3]), br = dpp_i<DPP_SHL>(B[0]);
-        const int cl = dpp_i<DPP_SHR>(C[3]), cr = dpp_i<DPP_SHL>(C[0]);
-        st.ha[i3][0] = al + A[0] + A[1];
-        st.hb[i3][0] = bl + B[0] + B[1];
-        st.hc[i3][0] = cl + C[0] + C[1];
-#pragma unroll
-        for (int c = 1; c < 3; ++c) {
-            st.ha[i3][c] = A[c - 1] + A[c] + A[c + 1];
-            st.hb[i3][c] = B[c - 1] + B[c] + B[c + 1];
-            st.hc[i3][c] = C[c - 1] + C[c] + C[c + 1];
-        }
-        st.ha[i3][3] = A[2] + A[3] + ar;
-        st.hb[i3][3] = B[2] + B[3] + br;
-        st.hc[i3][3] = C[2] + C[3] + cr;
+        const float al = dpp_f<DPP_SHR>(A[3]), ar = dpp_f<DPP_SHL>(A[0]);
+        const float bl = dpp_f<DPP_SHR>(B[3]), br = dpp_f<DPP_SHL>(B[0]);
+        const float cl = dpp_f<DPP_SHR>(C[3]), cr = dpp_f<DPP_SHL>(C[0]);
+        // 3-column sums; the middle pair is shared by columns 1 and 2 (integers: any order is exact)
+        const float a12 = A[1] + A[2], b12 = B[1] + B[2], c12 = C[1] + C[2];
+        st.ha[i3][0] = (al + A[0]) + A[1];
+        st.hb[i3][0] = (bl + B[0]) + B[1];
+        st.hc[i3][0] = (cl + C[0]) + C[1];
+        st.ha[i3][1] = A[0] + a12;
+        st.hb[i3][1] = B[0] + b12;
+        st.hc[i3][1] = C[0] + c12;
+        st.ha[i3][2] = a12 + A[3];
+        st.hb[i3][2] = b12 + B[3];
+        st.hc[i3][2] = c12 + C[3];
+        st.ha[i3][3] = (A[2] + A[3]) + ar;
+        st.hb[i3][3] = (B[2] + B[3]) + br;
+        st.hc[i3][3] = (C[2] + C[3]) + cr;
     }
     if constexpr (BOX) {
         const int yb = cx.oy - 5 + t;
         const bool row_in = yb >= cx.ry0 && yb < cx.ry1;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            st.sa[i2][c] = st.ha[mm3][c] + st.ha[m3][c] + st.ha[i3][c];
-            st.sb[i2][c] = st.hb[mm3][c] + st.hb[m3][c] + st.hb[i3][c];
-            st.sc[i2][c] = st.hc[mm3][c] + st.hc[m3][c] + st.hc[i3][c];
+            st.sa[i2][c] = (st.ha[mm3][c] + st.ha[m3][c]) + st.ha[i3][c];
+            st.sb[i2][c] = (st.hb[mm3][c] + st.hb[m3][c]) + st.hb[i3][c];
+            st.sc[i2][c] = (st.hc[mm3][c] + st.hc[m3][c]) + st.hc[i3][c];
             const int x = cx.xb + c;
             const bool in = row_in && x >= cx.rx0 && x < cx.rx1;
             st.sv[i2][c] = in ? approx_key(st.sa[i2][c], st.sb[i2][c], st.sc[i2][c]) : -1.0f;   // -1: ignored
@@ -319,43 +378,51 @@ __device__ __forceinline__ void resp_step(RespState& st, uint32_t P, int t, cons
             flag[c] = !(nmax < v * (1.0f - KEY_BAND));
         }
         uint64_t bal[4];
-        uint32_t tot = 0;
+        int tot = 0;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             bal[c] = __ballot(surv[c]);
-            tot += (uint32_t)__popcll(bal[c]);
+            tot += __popcll(bal[c]);
         }
         if (tot) {
-            if (st.cfill + tot > RAW_CHUNK) {
-                // the current chunk is full: mark its rest unused and reserve the next one
-                if (st.cbase != RAW_UNUSED) mark_unused(cx.raw, st.cbase + st.cfill, st.cbase + RAW_CHUNK, cx.lane);
-                uint32_t b = 0;
-                if (cx.lane == 0) b = atomicAdd(cx.raw_count, RAW_CHUNK);
-                st.cbase = (uint32_t)__builtin_amdgcn_readfirstlane((int)b);
-                st.cfill = 0;
-            }
-            uint32_t base = st.cbase + st.cfill;
-            st.cfill += tot;
+            // queue the row's survivors behind the waiting ones (fewer than 64 wait: capacity QCAP)
+            int base = st.qn;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const uint32_t lo = (uint32_t)bal[c], hi = (uint32_t)(bal[c] >> 32);
-                const uint32_t pos = base + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+                const int pos = base + (int)__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
                 if (surv[c]) {
                     const uint32_t ix = (uint32_t)(yn * cx.W + cx.xb + c) | (flag[c] ? 0x80000000u : 0u);
-                    cx.raw[pos] = make_uint4((uint32_t)st.sa[m2][c], (uint32_t)st.sb[m2][c], (uint32_t)st.sc[m2][c], ix);
+                    cx.q->surv[pos] = make_uint4(__float_as_uint(st.sa[m2][c]), __float_as_uint(st.sb[m2][c]),
+                                                 __float_as_uint(st.sc[m2][c]), ix);
                 }
-                base += (uint32_t)__popcll(bal[c]);
+                base += __popcll(bal[c]);
+            }
+            st.qn = base;
+            if (st.qn >= 64) {
+                int h = 0;
+                do {
+                    score_chunk(st, cx, h, 64);
+                    h += 64;
+                } while (st.qn - h >= 64);
+                // move the rest (fewer than 64 entries, disjoint from their new place as h >= 64) to the front
+                const int rest = st.qn - h;
+                vs::wave_lds_sync();
+                if (cx.lane < rest) cx.q->surv[cx.lane] = cx.q->surv[h + cx.lane];
+                vs::wave_lds_sync();
+                st.qn = rest;
             }
         }
     }
 }
 
 template <class IO>
-__global__ __launch_bounds__(256) void corner_response_kernel(IO io, int W, int H, int pitch, int mx, int my, int n_items,
-                                                              int strips, int segs, int sr, uint8_t* ws,
-                                                              int64_t item_bytes)
+__global__ __launch_bounds__(64 * RESP_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void corner_response_kernel(IO io, int W, int H, int pitch, int mx, int my,
+                                                                          int n_items, int strips, int segs, int sr,
+                                                                          uint8_t* ws, int64_t item_bytes)
 {
-    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);   // one independent wave per (item, strip, segment)
+    __shared__ WaveQueues s_q[RESP_WAVES];
+    const int gw = blockIdx.x * RESP_WAVES + (threadIdx.x >> 6);   // one independent wave per (item, strip, segment)
     const int per_item = strips * segs;
     const int item = gw / per_item;
     if (item >= n_items) return;
@@ -366,26 +433,32 @@ __global__ __launch_bounds__(256) void corner_response_kernel(IO io, int W, int 
     RespCtx cx;
     cx.lane = threadIdx.x & 63;
     cx.W = W;
+    cx.pitch = pitch;
     cx.rx0 = mx; cx.rx1 = W - mx; cx.ry0 = my; cx.ry1 = H - my;
     cx.out_lo = mx + SW * strip;
     cx.out_hi = min(cx.out_lo + SW, cx.rx1);
     cx.xb = ((cx.out_lo - 4) & ~3) + 4 * cx.lane;   // lanes 1..62 cover [out_lo, out_lo + SW)
     cx.oy = my + sr * seg;
     cx.oy_end = min(cx.oy + sr, cx.ry1);
-    cx.raw_count = &hdr_of(ws, item_bytes, item)->raw_count;
-    cx.raw = raw_of(ws, item_bytes, item, W, H);   // room for raw_entries(W, H) entries
+    cx.img = io.img(item);
+    CandHeader* hd = hdr_of(ws, item_bytes, item);
+    cx.count = &hd->count;
+    cx.keys = keys_of(ws, item_bytes, item);
+    cx.idx = idx_of(ws, item_bytes, item, W, H);
+    cx.q = &s_q[threadIdx.x >> 6];
 
     // pixel rows are read through a buffer descriptor: rows or columns past the image read as 0 and
     // only feed estimates outside the ROI, which the NMS ignores
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<uint8_t*>(io.img(item)), (short)0, pitch * H, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(cx.img), (short)0,
+                                                                        pitch * H, 0x00020000);
     auto load_row = [&](int yp) -> uint32_t {
         return __builtin_amdgcn_raw_buffer_load_b32(rs, yp * pitch + cx.xb, 0, 0);
     };
 
     RespState st;
-    st.cbase = RAW_UNUSED;
-    st.cfill = RAW_CHUNK;                       // no chunk yet: the first survivors reserve one
+    st.qn = 0;
+    st.kn = 0;
+    st.kmax = 0;
     const int nsteps = (cx.oy_end - cx.oy) + 6;
     const int nsup = (nsteps + SUP - 1) / SUP;
     uint32_t P[SUP];
@@ -416,82 +489,16 @@ __global__ __launch_bounds__(256) void corner_response_kernel(IO io, int W, int 
         resp_step<4, true, true, true>(st, P[4], t0 + 4, cx);
         resp_step<5, true, true, true>(st, P[5], t0 + 5, cx);
     }
-    if (st.cbase != RAW_UNUSED) mark_unused(cx.raw, st.cbase + st.cfill, st.cbase + RAW_CHUNK, cx.lane);
-}
-
-// Exact scores of the survivors; flagged ones get the exact NMS against their in-ROI neighbours.
-template <class IO>
-__global__ __launch_bounds__(256) void corner_keys_kernel(IO io, int W, int H, int pitch, int mx, int my, uint8_t* ws,
-                                                          int64_t item_bytes)
-{
-    const int item = blockIdx.y;
-    if (io.off(item)) return;
-    CandHeader* hd = hdr_of(ws, item_bytes, item);
-    const uint32_t nraw = hd->raw_count;
-    const uint4* raw = raw_of(ws, item_bytes, item, W, H);
-    uint64_t* keys = keys_of(ws, item_bytes, item);
-    uint32_t* idx = idx_of(ws, item_bytes, item, W, H);
-    const uint8_t* img = io.img(item);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int rx0 = mx, rx1 = W - mx, ry0 = my, ry1 = H - my;
-    __shared__ uint32_t s_wcnt[4], s_base;
-    __shared__ uint64_t s_wmax[4];
-    uint64_t mx_bits = 0;
-    for (uint32_t b0 = blockIdx.x * 256u; b0 < nraw; b0 += gridDim.x * 256u) {
-        const uint32_t i = b0 + threadIdx.x;
-        bool keep = false;
-        uint64_t kb = 0;
-        uint32_t ix = 0;
-        const uint4 r = i < nraw ? raw[i] : make_uint4(0u, 0u, 0u, RAW_UNUSED);
-        if (r.w != RAW_UNUSED) {
-            ix = r.w & 0x7FFFFFFFu;
-            const double key = exact_key((int32_t)r.x, (int32_t)r.y, (int32_t)r.z);
-            keep = key > 0.0;
-            if (keep && (r.w >> 31)) {
-                const int x = (int)(ix % (uint32_t)W), y = (int)(ix / (uint32_t)W);
-                for (int dy = -1; dy <= 1 && keep; ++dy)
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        const int nx = x + dx, ny = y + dy;
-                        if ((dx == 0 && dy == 0) || nx < rx0 || nx >= rx1 || ny < ry0 || ny >= ry1) continue;
-                        int32_t A, B, C;
-                        tensor_from_image(img, pitch, nx, ny, A, B, C);
-                        if (exact_key(A, B, C) > key) { keep = false; break; }
-                    }
-            }
-            kb = (uint64_t)__double_as_longlong(key);
-        }
-        // one atomic per workgroup and iteration places the workgroup's kept candidates
-        const uint64_t bal = __ballot(keep);
-        if (lane == 0) s_wcnt[wv] = (uint32_t)__popcll(bal);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const uint32_t tot = (s_wcnt[0] + s_wcnt[1]) + (s_wcnt[2] + s_wcnt[3]);
-            s_base = tot ? atomicAdd(&hd->count, tot) : 0u;
-        }
-        __syncthreads();
-        uint32_t pos = s_base;
-        for (int w = 0; w < wv; ++w) pos += s_wcnt[w];
-        pos += __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-        if (keep) {
-            keys[pos] = kb;
-            idx[pos] = ix;
-            if (kb > mx_bits) mx_bits = kb;
-        }
-        __syncthreads();
-    }
-    // the largest kept key: one atomic per workgroup
+    // the last survivors and kept candidates, then the wave's largest score (one atomic per wave)
+    if (st.qn > 0) score_chunk(st, cx, 0, st.qn);
+    if (st.kn > 0) flush_kept(st, cx);
+    uint64_t m = st.kmax;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
-        const uint64_t t = __shfl_xor(mx_bits, o, 64);
-        mx_bits = t > mx_bits ? t : mx_bits;
+        const uint64_t t = __shfl_xor(m, o, 64);
+        m = t > m ? t : m;
     }
-    if (lane == 0) s_wmax[wv] = mx_bits;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t m = s_wmax[0];
-        for (int w = 1; w < 4; ++w) m = s_wmax[w] > m ? s_wmax[w] : m;
-        if (m) atomicMax((unsigned long long*)&hd->lmax_bits, (unsigned long long)m);
-    }
+    if (cx.lane == 0 && m) atomicMax((unsigned long long*)&hd->lmax_bits, (unsigned long long)m);
 }
 
 // composite key: larger is earlier in the selection order
@@ -505,25 +512,152 @@ __device__ __forceinline__ bool before(uint64_t ka, uint32_t ia, uint64_t kb, ui
     return ka > kb || (ka == kb && ia < ib);
 }
 
-// Calls f(key, index) for every candidate of the list, thread tid taking i = tid, tid + 1024, ...
-// Eight loads per thread are issued before any is used, so a pass is not a chain of dependent
-// global-memory latencies.
+// Whether two corners are closer than the minimum distance (d2 = its square). For frames whose
+// sides are at most 32768 (D24) every coordinate difference fits 24-bit multiplies and the sum of
+// squares stays below 2^31, so 32-bit arithmetic decides it exactly (d2 clamped to 2^32 - 1 leaves
+// every decision unchanged); larger frames use 64-bit arithmetic.
+template <bool D24>
+__device__ __forceinline__ bool too_close(int ax, int ay, int bx, int by, uint32_t d2_32, int64_t d2)
+{
+    if constexpr (D24) {
+        const int dx = ax - bx, dy = ay - by;
+        return (uint32_t)__mul24(dy, dy) + (uint32_t)__mul24(dx, dx) < d2_32;
+    } else {
+        const int64_t dx = ax - bx, dy = ay - by;
+        return dx * dx + dy * dy < d2;
+    }
+}
+constexpr int D24_MAX_SIDE = 32768;
+
+// One greedy group, first phase (every wave): member `lane` of the group at g0 (if lane < gn) is
+// tested against the na accepted corners -- wave wv takes corners 4 wv .. 4 wv + 3, then 128 further
+// on, ..., with two 16-byte reads of the same addresses by every lane per 4 corners -- and against
+// the group's members 4 wv .. 4 wv + 3 that come before it. A conflict with an accepted corner sets
+// s_conf[lane]; too-close earlier members set their bits in s_mask[lane].
+template <bool D24>
+__device__ __forceinline__ void greedy_test(const int2* bxy, const int2* acc_xy, int g0, int gn, int na, int lane,
+                                            int wv, uint32_t d2_32, int64_t d2, uint32_t* s_conf, uint64_t* s_mask)
+{
+    if (lane >= gn) return;
+    const int2 c = bxy[g0 + lane];
+    bool conf = false;
+    for (int j = 4 * wv; j < na && !conf; j += 2 * 64) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int jb = j + 64 * u;
+            const int4 q0 = *reinterpret_cast<const int4*>(&acc_xy[jb]);
+            const int4 q1 = *reinterpret_cast<const int4*>(&acc_xy[jb + 2]);
+            const int qx[4] = {q0.x, q0.z, q1.x, q1.z}, qy[4] = {q0.y, q0.w, q1.y, q1.w};
+            // every test is evaluated (bitwise, not short-circuit), so no branch splits the reads
+#pragma unroll
+            for (int v = 0; v < 4; ++v) conf |= (jb + v < na) & too_close<D24>(c.x, c.y, qx[v], qy[v], d2_32, d2);
+        }
+    }
+    if (conf) s_conf[lane] = 1;
+    uint64_t bits = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int j = 4 * wv + b;
+        const int2 o = bxy[g0 + j];        // j < 64 <= CAP - g0: inside the batch array
+        bits |= (uint64_t)((j < lane) & too_close<D24>(c.x, c.y, o.x, o.y, d2_32, d2)) << j;
+    }
+    if (bits) atomicOr((unsigned long long*)&s_mask[lane], (unsigned long long)bits);
+}
+
+// Sorts the batch bkey/bidx[0, 1024 R) earliest first (bitonic network). Thread t holds elements
+// w 64 R + h 64 + l (wave w, lane l, h < R) in registers: compare-exchanges with partners in the same
+// lane or across lanes of the wave run in registers (the latter by shuffles); only the strides
+// reaching another wave go through LDS, with two barriers each. Called by all 1024 threads.
+template <int R>
+__device__ void sort_batch(uint64_t* bkey, uint32_t* bidx, int tid)
+{
+    constexpr int S = 1024 * R;
+    const int lane = tid & 63, wv = tid >> 6;
+    uint64_t k[R];
+    uint32_t x[R];
+#pragma unroll
+    for (int h = 0; h < R; ++h) {
+        k[h] = bkey[wv * 64 * R + h * 64 + lane];
+        x[h] = bidx[wv * 64 * R + h * 64 + lane];
+    }
+    for (int kk = 2; kk <= S; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            if (j >= 64 * R) {
+                // partner in another wave
+                __syncthreads();
+#pragma unroll
+                for (int h = 0; h < R; ++h) {
+                    bkey[wv * 64 * R + h * 64 + lane] = k[h];
+                    bidx[wv * 64 * R + h * 64 + lane] = x[h];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int h = 0; h < R; ++h) {
+                    const int e = wv * 64 * R + h * 64 + lane;
+                    const uint64_t pk = bkey[e ^ j];
+                    const uint32_t px = bidx[e ^ j];
+                    const bool keep_earlier = ((e & j) == 0) == ((e & kk) == 0);
+                    if (keep_earlier != before(k[h], x[h], pk, px)) { k[h] = pk; x[h] = px; }
+                }
+            } else if (j >= 64) {
+                // partner in the same lane: register h ^ (j / 64); the lower one is h
+                const int hj = j >> 6;
+#pragma unroll
+                for (int h = 0; h < R; ++h) {
+                    int h2 = -1;
+                    if constexpr (R >= 2) { if (hj == 1 && (h & 1) == 0) h2 = h + 1; }
+                    if constexpr (R >= 4) { if (hj == 2 && (h & 2) == 0) h2 = h + 2; }
+                    if (h2 < 0) continue;
+#pragma unroll
+                    for (int g = 1; g < R; ++g) {
+                        if (g != h2) continue;
+                        const int e = wv * 64 * R + h * 64 + lane;
+                        const bool up = (e & kk) == 0;
+                        // up: h keeps the earlier, g the later; otherwise the reverse
+                        if (up != before(k[h], x[h], k[g], x[g])) {
+                            const uint64_t tk = k[h]; k[h] = k[g]; k[g] = tk;
+                            const uint32_t tx = x[h]; x[h] = x[g]; x[g] = tx;
+                        }
+                    }
+                }
+            } else {
+                // partner lane ^ j of the same register
+#pragma unroll
+                for (int h = 0; h < R; ++h) {
+                    const int e = wv * 64 * R + h * 64 + lane;
+                    const uint64_t pk = __shfl_xor(k[h], j, 64);
+                    const uint32_t px = (uint32_t)__shfl_xor((int)x[h], j, 64);
+                    const bool keep_earlier = ((e & j) == 0) == ((e & kk) == 0);
+                    if (keep_earlier != before(k[h], x[h], pk, px)) { k[h] = pk; x[h] = px; }
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < R; ++h) {
+        bkey[wv * 64 * R + h * 64 + lane] = k[h];
+        bidx[wv * 64 * R + h * 64 + lane] = x[h];
+    }
+    __syncthreads();
+}
+
+// Calls f(key, i) for every candidate i of the list, thread tid taking i = tid, tid + 1024, ...
+// Eight key loads per thread are issued before any is used, so a pass is not a chain of dependent
+// global-memory latencies. The pixel indices are read by f only where it needs them.
 template <typename F>
-__device__ __forceinline__ void for_each_key(const uint64_t* keys, const uint32_t* idx, uint32_t N, int tid, F f)
+__device__ __forceinline__ void for_each_key(const uint64_t* keys, uint32_t N, int tid, F f)
 {
     constexpr int UNR = 8;
     for (uint32_t i0 = tid; i0 < N; i0 += 1024 * UNR) {
+        // the loads are issued unconditionally (indices past the list read its last entry, i0 < N)
+        // so that no branch separates them
         uint64_t kb[UNR];
-        uint32_t ix[UNR];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const uint32_t i = i0 + 1024u * u;
-            kb[u] = i < N ? keys[i] : 0;
-            ix[u] = i < N ? idx[i] : 0;
-        }
+        for (int u = 0; u < UNR; ++u) kb[u] = keys[min(i0 + 1024u * u, N - 1)];
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
-            if (i0 + 1024u * u < N) f(kb[u], ix[u]);
+            if (i0 + 1024u * u < N) f(kb[u], i0 + 1024u * u);
     }
 }
 
@@ -540,11 +674,11 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
     __shared__ uint64_t bkey[CAP];
     __shared__ uint32_t bidx[CAP];
     __shared__ uint32_t hist[NBIN];
-    __shared__ int32_t acc_x[VS_MAX_CORNERS];
-    __shared__ int32_t acc_y[VS_MAX_CORNERS];
+    // accepted corners (x, y); the scan below reads 4 at a time, up to 2 x 64 + 3 entries past the last
+    __shared__ __attribute__((aligned(16))) int2 acc_xy[VS_MAX_CORNERS + 2 * 64 + 4];
+    __shared__ __attribute__((aligned(16))) int2 bxy[CAP];   // (x, y) of the sorted batch
     __shared__ uint32_t s_conf[64];
-    __shared__ __attribute__((aligned(16))) uint8_t s_mbits[64 * 16];
-    __shared__ int32_t s_cx[64], s_cy[64];
+    __shared__ uint64_t s_mask[64];
     __shared__ int s_nacc, s_bcount, s_digit, s_done;
     __shared__ uint32_t s_need, s_above, s_sel_in_bin;
 
@@ -558,6 +692,7 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
     const double thr = __dmul_rn(quality, lmax);
     const uint64_t base = (uint64_t)__double_as_longlong(thr);
     const int64_t d2 = (int64_t)min_dist * min_dist;
+    const uint32_t d2_32 = d2 < 0xFFFFFFFFll ? (uint32_t)d2 : 0xFFFFFFFFu;
 
     if (tid == 0) { s_nacc = 0; s_done = !(lmax > 0.0) || K <= 0; }
     __syncthreads();
@@ -587,21 +722,38 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
                 shift -= db;
                 for (int b = tid; b < NBIN; b += 1024) hist[b] = 0;
                 __syncthreads();
-                for_each_key(keys, idx, N, tid, [&](uint64_t kb, uint32_t ix) {
-                    bool in = kb >= base;
-                    u128 v = 0;
-                    if (in) {
-                        v = comp(kb, ix, base);
-                        in = (unbounded || v < U) && !(pshift < 128 && (v >> pshift) != prefix);
-                    }
-                    // most keys fall into a few low bins: the lanes sharing the first active lane's bin
-                    // add in one atomic, the others one each
-                    const uint32_t b = in ? ((uint32_t)(v >> shift) & ((1u << db) - 1u)) : 0xFFFFFFFFu;
+                // most keys fall into a few low bins: the lanes sharing the first active lane's bin
+                // add in one atomic, the others one each
+                auto add_bin = [&](bool in, uint32_t b) {
                     const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)b);
                     const uint64_t same = __ballot(in && b == b0);
                     if (same && lane == (int)__builtin_ctzll(same)) atomicAdd(&hist[b0], (uint32_t)__popcll(same));
                     if (in && b != b0) atomicAdd(&hist[b], 1u);
-                });
+                };
+                const uint32_t dmask = (1u << db) - 1u;
+                if (unbounded && shift >= 32) {
+                    // the digit and the prefix lie in the score bits: 64-bit arithmetic on them
+                    const int ps = pshift - 32, ds = shift - 32;   // ps <= 63: the span has at most 63 bits
+                    const uint64_t pre = (uint64_t)prefix;
+                    for_each_key(keys, N, tid, [&](uint64_t kb, uint32_t) {
+                        const uint64_t vk = kb - base;
+                        const bool in = kb >= base && (vk >> ps) == pre;
+                        add_bin(in, in ? (uint32_t)(vk >> ds) & dmask : 0xFFFFFFFFu);
+                    });
+                } else {
+                    for_each_key(keys, N, tid, [&](uint64_t kb, uint32_t i) {
+                        bool in = kb >= base;
+                        u128 v = 0;
+                        if (in) {
+                            // the index (the composite key's low 32 bits) matters only when this digit
+                            // reaches into it or the score bits tie with the bound U's
+                            const bool need_ix = shift < 32 || (!unbounded && kb - base == (uint64_t)(U >> 32));
+                            v = comp(kb, need_ix ? idx[i] : 0u, base);
+                            in = (unbounded || v < U) && !(pshift < 128 && (v >> pshift) != prefix);
+                        }
+                        add_bin(in, in ? ((uint32_t)(v >> shift) & dmask) : 0xFFFFFFFFu);
+                    });
+                }
                 __syncthreads();
                 // suffix sums from the top digit (Hillis-Steele in place over NBIN bins)
                 for (int o = 1; o < NBIN; o <<= 1) {
@@ -647,109 +799,85 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
         }
         if (none_left) break;
 
-        // ---- 2) gather [T, U) into LDS
+        // ---- 2) gather [T, U) into LDS: the score bits decide, except where they tie with T's or U's
+        // and the bound's index bits are not zero; then the key's index is read. Each gathered key
+        // records its list position, replaced by its pixel index once the pass is over (one round of
+        // loads instead of a load latency inside the pass).
         if (tid == 0) s_bcount = 0;
         __syncthreads();
-        for_each_key(keys, idx, N, tid, [&](uint64_t kb, uint32_t ix) {
-            bool take = kb >= base;
-            if (take) {
-                const u128 v = comp(kb, ix, base);
-                take = !(v < T || (!unbounded && v >= U));
-            }
-            // one atomic per wave for the wave's selected keys
-            const uint64_t m = __ballot(take);
-            if (!m) return;
-            int first = 0;
-            if (lane == (int)__builtin_ctzll(m)) first = atomicAdd(&s_bcount, __popcll(m));
-            first = __shfl(first, (int)__builtin_ctzll(m), 64);
-            const int slot = first + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            if (take && slot < CAP) {  // always true by construction of T; keeps LDS writes in range
-                bkey[slot] = kb;
-                bidx[slot] = ix;
-            }
-        });
+        {
+            const uint64_t Tk = (uint64_t)(T >> 32), Uk = (uint64_t)(U >> 32);
+            const uint32_t Tlo = (uint32_t)T, Ulo = (uint32_t)U;
+            for_each_key(keys, N, tid, [&](uint64_t kb, uint32_t i) {
+                bool take = kb >= base;
+                if (take) {
+                    const uint64_t vk = kb - base;
+                    take = vk >= Tk && (unbounded || vk < Uk);
+                    const bool need_ix = (vk == Tk && Tlo != 0u) || (!unbounded && vk == Uk && Ulo != 0u);
+                    if (need_ix) {
+                        const u128 v = comp(kb, idx[i], base);
+                        take = !(v < T || (!unbounded && v >= U));
+                    }
+                }
+                // one atomic per wave for the wave's selected keys
+                const uint64_t m = __ballot(take);
+                if (!m) return;
+                int first = 0;
+                if (lane == (int)__builtin_ctzll(m)) first = atomicAdd(&s_bcount, __popcll(m));
+                first = __shfl(first, (int)__builtin_ctzll(m), 64);
+                const int slot = first + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                if (take && slot < CAP) {  // always true by construction of T; keeps LDS writes in range
+                    bkey[slot] = kb;
+                    bidx[slot] = i;
+                }
+            });
+        }
+        __syncthreads();
+        for (int s2 = tid; s2 < min((int)s_bcount, CAP); s2 += 1024) bidx[s2] = idx[bidx[s2]];
         __syncthreads();
         const int bc = s_bcount < CAP ? s_bcount : CAP;
-        int p2 = 1;
-        while (p2 < bc) p2 <<= 1;
-        for (int i = bc + tid; i < p2; i += 1024) { bkey[i] = 0; bidx[i] = 0xFFFFFFFFu; }
+        // the batch is padded with entries that order last to the sorting size 1024, 2048 or 4096
+        const int ssize = bc <= 1024 ? 1024 : (bc <= 2048 ? 2048 : 4096);
+        for (int i = bc + tid; i < ssize; i += 1024) { bkey[i] = 0; bidx[i] = 0xFFFFFFFFu; }
         __syncthreads();
 
         // ---- 3) bitonic sort, earliest first
-        for (int k = 2; k <= p2; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int i = tid; i < p2; i += 1024) {
-                    const int l = i ^ j;
-                    if (l > i) {
-                        const bool up = (i & k) == 0;
-                        const uint64_t ka = bkey[i], kb2 = bkey[l];
-                        const uint32_t ia = bidx[i], ib = bidx[l];
-                        const bool swap = up ? before(kb2, ib, ka, ia) : before(ka, ia, kb2, ib);
-                        if (swap) { bkey[i] = kb2; bkey[l] = ka; bidx[i] = ib; bidx[l] = ia; }
-                    }
-                }
-                __syncthreads();
-            }
-        }
+        if (ssize == 1024)
+            sort_batch<1>(bkey, bidx, tid);
+        else if (ssize == 2048)
+            sort_batch<2>(bkey, bidx, tid);
+        else
+            sort_batch<4>(bkey, bidx, tid);
 
-        // ---- 4) greedy acceptance, 64 candidates at a time. Wave 0 stages a group's coordinates. All
-        // waves then test the group against the corners accepted so far and fill the group's 64 x 64
-        // matrix of too-close earlier members. Wave 0 accepts the members clear of both at once and
-        // walks only the contested ones in order; then it stages the next group. Two barriers a group.
+        // ---- 4) greedy acceptance, 64 candidates at a time. The batch's coordinates are formed in
+        // parallel first. Per group, all waves test the members against the corners accepted so far
+        // and mark, per member, the earlier members of the group that are too close (one bit each).
+        // Wave 0 then accepts the members clear of both at once and walks only the contested ones in
+        // order. Two barriers a group.
+        for (int i = tid; i < bc; i += 1024) {
+            const uint32_t ix = bidx[i];
+            bxy[i] = make_int2((int32_t)(ix % (uint32_t)W), (int32_t)(ix / (uint32_t)W));
+        }
         if (tid < 64) {
             s_conf[tid] = 0;
-            if (tid < bc) {
-                const uint32_t ix = bidx[tid];
-                s_cx[tid] = (int32_t)(ix % (uint32_t)W);
-                s_cy[tid] = (int32_t)(ix / (uint32_t)W);
-            }
+            s_mask[tid] = 0;
         }
         __syncthreads();
         for (int g0 = 0; g0 < bc; g0 += 64) {
             const int na = s_nacc;
             if (na >= K) break;
             const int gn = min(64, bc - g0);                  // members in this group
-            if (lane < gn) {
-                const int cx = s_cx[lane], cy = s_cy[lane];
-                bool conf = false;
-                // wave wv checks accepted corners wv, wv + 16, ...; four independent reads per step
-                for (int j = wv; j < na && !conf; j += 64) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int jj = j + 16 * u;
-                        if (jj < na) {
-                            const int64_t dx = cx - acc_x[jj], dy = cy - acc_y[jj];
-                            conf = conf || dx * dx + dy * dy < d2;
-                        }
-                    }
-                }
-                if (conf) s_conf[lane] = 1;
-                // members 4 wv .. 4 wv + 3 of the group that come before this lane and are too close
-                uint32_t bits = 0;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int j = 4 * wv + b;
-                    if (j < lane) {
-                        const int64_t dx = cx - s_cx[j], dy = cy - s_cy[j];
-                        if (dx * dx + dy * dy < d2) bits |= 1u << b;
-                    }
-                }
-                s_mbits[lane * 16 + wv] = (uint8_t)bits;
-            } else {
-                s_mbits[lane * 16 + wv] = 0;
-            }
+            if (W <= D24_MAX_SIDE && H <= D24_MAX_SIDE)
+                greedy_test<true>(bxy, acc_xy, g0, gn, na, lane, wv, d2_32, d2, s_conf, s_mask);
+            else
+                greedy_test<false>(bxy, acc_xy, g0, gn, na, lane, wv, d2_32, d2, s_conf, s_mask);
             __syncthreads();
             if (wv == 0) {
                 const bool valid = lane < gn;
-                const int cx = valid ? s_cx[lane] : 0, cy = valid ? s_cy[lane] : 0;
+                const int2 c = valid ? bxy[g0 + lane] : make_int2(0, 0);
                 const bool pre_ok = valid && s_conf[lane] == 0;
                 const uint64_t ok = __ballot(pre_ok);
-                const uint4 mb = *reinterpret_cast<const uint4*>(&s_mbits[lane * 16]);
-                const uint32_t w4[4] = {mb.x, mb.y, mb.z, mb.w};
-                uint64_t mask = 0;
-#pragma unroll
-                for (int q = 0; q < 16; ++q) mask |= (uint64_t)((w4[q >> 2] >> (8 * (q & 3))) & 0xFu) << (4 * q);
-                mask &= ok;                                   // earlier members still eligible and too close
+                const uint64_t mask = s_mask[lane] & ok;      // earlier members still eligible and too close
                 uint64_t acc = __ballot(pre_ok && mask == 0); // no earlier eligible member too close
                 uint64_t contested = ok & ~acc;
                 while (contested) {
@@ -764,21 +892,15 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
                 const int rank_in = __popcll(acc & ((1ull << lane) - 1ull));
                 if (((acc >> lane) & 1ull) && rank_in < allowed) {
                     const int rank = na + rank_in;
-                    acc_x[rank] = cx;
-                    acc_y[rank] = cy;
+                    acc_xy[rank] = c;
                     float* o = xy_out + rank * 2;
-                    o[0] = (float)cx;
-                    o[1] = (float)cy;
+                    o[0] = (float)c.x;
+                    o[1] = (float)c.y;
                     if (score_out) score_out[rank] = __longlong_as_double((long long)bkey[g0 + lane]);
                 }
                 if (lane == 0) s_nacc = na + min(__popcll(acc), allowed);
-                // stage the next group
                 s_conf[lane] = 0;
-                if (g0 + 64 + lane < bc) {
-                    const uint32_t ix = bidx[g0 + 64 + lane];
-                    s_cx[lane] = (int32_t)(ix % (uint32_t)W);
-                    s_cy[lane] = (int32_t)(ix / (uint32_t)W);
-                }
+                s_mask[lane] = 0;
             }
             __syncthreads();
         }
@@ -796,7 +918,7 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
     if (tid == 0) *io.count_of(item) = na;
 }
 
-// the four detection launches over n items
+// the three detection launches over n items
 template <class IO>
 int launch_detect(const IO& io, int n, int width, int height, int pitch, const vs_detect_params& p, int Kmax,
                   int capacity, uint8_t* w8, hipStream_t s)
@@ -806,19 +928,14 @@ int launch_detect(const IO& io, int n, int width, int height, int pitch, const v
     int e = vs::check_launch("vs_detect_corners(init)");
     if (e) return e;
     const int rw = width - 2 * p.roi_mx, rh = height - 2 * p.roi_my;
-    // each output row belongs to one wave's segment and the survivors are sorted afterwards, so the
+    // each output row belongs to one wave's segment and the candidates are sorted afterwards, so the
     // segment height only trades per-wave warm-up rows against waves per frame
-    const int sr = vs::detect_segment_rows(n, SR_FEW, SR);   // >= SR_FEW, which sizes the survivor list
+    const int sr = vs::detect_segment_rows(n, SR_FEW, SR);
     const int strips = (rw + SW - 1) / SW, segs = (rh + sr - 1) / sr;
     const int64_t nwaves = (int64_t)n * strips * segs;
-    corner_response_kernel<<<(unsigned)((nwaves + 3) / 4), 256, 0, s>>>(io, width, height, pitch, p.roi_mx, p.roi_my, n,
-                                                                      strips, segs, sr, w8, ib);
+    corner_response_kernel<<<(unsigned)((nwaves + RESP_WAVES - 1) / RESP_WAVES), 64 * RESP_WAVES, 0, s>>>(
+        io, width, height, pitch, p.roi_mx, p.roi_my, n, strips, segs, sr, w8, ib);
     e = vs::check_launch("vs_detect_corners(response)");
-    if (e) return e;
-    // survivors are a small fraction of the ROI: 32 blocks per item stride over them (256 for
-    // batches of at most 8 frames)
-    corner_keys_kernel<<<dim3(n <= 8 ? 256 : 32, n), 256, 0, s>>>(io, width, height, pitch, p.roi_mx, p.roi_my, w8, ib);
-    e = vs::check_launch("vs_detect_corners(keys)");
     if (e) return e;
     corner_select_kernel<<<n, 1024, 0, s>>>(w8, ib, width, height, io, Kmax, p.quality, p.min_dist, capacity);
     return vs::check_launch("vs_detect_corners(select)");

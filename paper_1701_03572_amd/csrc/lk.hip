@@ -95,13 +95,7 @@ constexpr int ZERO_FLOATS = 80;   // 10 rows of 32 bytes
 constexpr int WAVE_LDS_FLOATS = RED_FLOATS + ZERO_FLOATS;
 static_assert(STAGE_ROWS * 8 <= RED_FLOATS && WAVE_LDS_FLOATS % 4 == 0, "staging fits the reduction area");
 
-// orders one wave's LDS accesses across lanes (LDS operations of a wave complete in issue order)
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+using vs::wave_lds_sync;
 
 // Wave totals of the first M of N (8 or 16) values per lane, returned in every lane. Lane l adds value
 // l % N over the N lanes of its chunk l / N, lane j < M then adds the 64 / N chunk sums of value j, and

@@ -31,6 +31,15 @@ int fit_groups_in_flight();
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Orders one wave's LDS accesses across its lanes: LDS operations of a wave complete in issue order,
+// and the fences keep the compiler from moving accesses across this point.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Wave64 butterfly sums: every lane ends with the same, bit-identical total (each stage adds the
 // same two operands in every lane, and addition is commutative).
 __device__ __forceinline__ double wave_sum_d(double v)
