@@ -472,7 +472,7 @@ int vs_batch_note_replayed(vs_batch* b, int32_t n, const int32_t* slots, int32_t
  *     workgroups on one XCD (one L2); 0 selects the default (8); 1 always, 65536 never.
  *   lk_points_per_group: points (one wave each) per tracking workgroup, 1, 2 or 4; 0: default (1).
  *   detect_segment_rows: output rows per wave segment of the corner response, 12..240; 0: by batch
- *     size (12 for at most 8 frames, else 60). Survivors are sorted afterwards, so the split is free.
+ *     size (12 for at most 8 frames, else 60). Candidates are sorted afterwards, so the split is free.
  *   fit_groups_in_flight: hypothesis workgroups of a fit launch are spread until about this many are
  *     in flight (at most 32 per pair), 64..16384; 0: default (2048). The best hypothesis is the most
  *     inliers, then the smallest index, whatever the split.
