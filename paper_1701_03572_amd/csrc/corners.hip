@@ -35,7 +35,23 @@ struct CandHeader {
     uint64_t lmax_bits;    // bit pattern of the largest candidate score (0: none yet)
 };
 
-constexpr int64_t HDR = 256;
+// Score histogram of an item's candidates: bin b counts the scores whose bits, shifted right by 48
+// (exponent and 4 leading mantissa bits: 1/16 octave), equal b + BIN_BASE, clamped to [0, NBIN_S);
+// bin 0 holds everything below 2^-25 and the last everything from 2^25 on (the exact scores of
+// 8-bit images lie between 2^-25 and 2^25). Monotone in the score.
+constexpr int BIN_SHIFT = 48;
+constexpr int NBIN_S = 50 * 16;
+constexpr int64_t BIN_BASE = (int64_t)(1023 - 25) * 16;
+__host__ __device__ inline int score_bin(uint64_t kb)
+{
+    const int64_t b = (int64_t)(kb >> BIN_SHIFT) - BIN_BASE;
+    return b < 0 ? 0 : (b >= NBIN_S ? NBIN_S - 1 : (int)b);
+}
+// the smallest score bits of bin b (1 <= b < NBIN_S): score_bin(k) >= b exactly when k >= bin_low(b)
+__host__ __device__ inline uint64_t bin_low(int b) { return (uint64_t)(b + BIN_BASE) << BIN_SHIFT; }
+
+constexpr int64_t HIST = 256;                       // the histogram follows the 256-byte header
+constexpr int64_t HDR = HIST + ((4 * NBIN_S + 255) & ~255);
 constexpr int SW = 240;         // output columns per wave strip (lanes 1..62 of 64 x 4 columns)
 constexpr int SUP = 6;          // rows per unrolled super-step (period of the register rotation)
 constexpr int SR = 60;          // output rows per wave: the pipeline runs SR + 6 pixel rows
@@ -56,10 +72,12 @@ struct WaveQueues {
     uint4 surv[QCAP];        // A, B, C (bits of exact floats), pixel index | flag << 31
     uint64_t key[KCAP];      // bits of the exact score
     uint32_t idx[KCAP];
+    uint32_t hist[NBIN_S];   // the wave's score histogram of its kept candidates
 };
 constexpr int RESP_WAVES = 4;   // waves per response workgroup
 
-// per item: header | keys (8 B each) | indices (4 B), each list with room for one entry per pixel
+// per item: header | score histogram | keys (8 B each) | indices (4 B), each list with room for one
+// entry per pixel
 __host__ __device__ inline int64_t per_item_bytes(int w, int h)
 {
     const int64_t c = (int64_t)w * h;
@@ -69,6 +87,10 @@ __host__ __device__ inline int64_t per_item_bytes(int w, int h)
 __device__ __forceinline__ CandHeader* hdr_of(uint8_t* ws, int64_t item_bytes, int item)
 {
     return reinterpret_cast<CandHeader*>(ws + item * item_bytes);
+}
+__device__ __forceinline__ uint32_t* hist_of(uint8_t* ws, int64_t item_bytes, int item)
+{
+    return reinterpret_cast<uint32_t*>(ws + item * item_bytes + HIST);
 }
 __device__ __forceinline__ uint64_t* keys_of(uint8_t* ws, int64_t item_bytes, int item)
 {
@@ -135,11 +157,15 @@ struct Step {
 template <class IO>
 __global__ void detect_init_kernel(uint8_t* ws, int64_t item_bytes, int n, IO io)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x;   // one workgroup per item
     if (i >= n || io.off(i)) return;
-    CandHeader* h = hdr_of(ws, item_bytes, i);
-    h->count = 0;
-    h->lmax_bits = 0;
+    if (threadIdx.x == 0) {
+        CandHeader* h = hdr_of(ws, item_bytes, i);
+        h->count = 0;
+        h->lmax_bits = 0;
+    }
+    uint32_t* hist = hist_of(ws, item_bytes, i);
+    for (int b = threadIdx.x; b < NBIN_S; b += blockDim.x) hist[b] = 0;
 }
 
 
@@ -229,6 +255,7 @@ struct RespCtx {
     int W, pitch;
     const uint8_t* img;
     uint32_t* count;             // the item's candidate count
+    uint32_t* hist;              // the item's score histogram
     uint64_t* keys;              // the item's candidate lists (room for one entry per pixel)
     uint32_t* idx;
     WaveQueues* q;               // this wave's LDS queues
@@ -287,6 +314,7 @@ __device__ __forceinline__ void score_chunk(RespState& st, const RespCtx& cx, in
         const int pos = st.kn + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
         cx.q->key[pos] = kb;
         cx.q->idx[pos] = ix;
+        atomicAdd(&cx.q->hist[score_bin(kb)], 1u);
         if (kb > st.kmax) st.kmax = kb;
     }
     st.kn += __popcll(bal);
@@ -443,6 +471,7 @@ __global__ __launch_bounds__(64 * RESP_WAVES) __attribute__((amdgpu_waves_per_eu
     cx.img = io.img(item);
     CandHeader* hd = hdr_of(ws, item_bytes, item);
     cx.count = &hd->count;
+    cx.hist = hist_of(ws, item_bytes, item);
     cx.keys = keys_of(ws, item_bytes, item);
     cx.idx = idx_of(ws, item_bytes, item, W, H);
     cx.q = &s_q[threadIdx.x >> 6];
@@ -459,6 +488,9 @@ __global__ __launch_bounds__(64 * RESP_WAVES) __attribute__((amdgpu_waves_per_eu
     st.qn = 0;
     st.kn = 0;
     st.kmax = 0;
+    static_assert(NBIN_S % 4 == 0, "the histogram is cleared 16 bytes at a time");
+    for (int b = 4 * cx.lane; b < NBIN_S; b += 4 * 64)   // ordered before use by the scoring's sync
+        *reinterpret_cast<uint4*>(&cx.q->hist[b]) = make_uint4(0u, 0u, 0u, 0u);
     const int nsteps = (cx.oy_end - cx.oy) + 6;
     const int nsup = (nsteps + SUP - 1) / SUP;
     uint32_t P[SUP];
@@ -492,6 +524,12 @@ __global__ __launch_bounds__(64 * RESP_WAVES) __attribute__((amdgpu_waves_per_eu
     // the last survivors and kept candidates, then the wave's largest score (one atomic per wave)
     if (st.qn > 0) score_chunk(st, cx, 0, st.qn);
     if (st.kn > 0) flush_kept(st, cx);
+    // the wave's histogram into the item's (one atomic per non-empty bin)
+    vs::wave_lds_sync();
+    for (int b = cx.lane; b < NBIN_S; b += 64) {
+        const uint32_t h = cx.q->hist[b];
+        if (h) atomicAdd(&cx.hist[b], h);
+    }
     uint64_t m = st.kmax;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
@@ -705,13 +743,50 @@ __global__ __launch_bounds__(1024) void corner_select_kernel(uint8_t* ws, int64_
     bool unbounded = true;
     u128 U = 0;                    // exclusive upper bound on composite keys still to process
 
+    // ---- 0) the first batch's cut from the score histogram the response kernel built (suffix sums
+    // over its bins): the highest bin above the threshold's from which on at least `batch` scores lie,
+    // when they fit the batch buffer; all eligible scores when the bins above the threshold's hold
+    // fewer and they fit. Otherwise, and for later batches, the radix select below.
+    __shared__ int s_cut_ok;
+    __shared__ unsigned long long s_cut;
+    {
+        constexpr int NS = 1024;
+        static_assert(NBIN_S <= NS && NS <= 1024 && NS <= NBIN, "histogram scan size");
+        const uint32_t* hh = hist_of(ws, item_bytes, item);
+        if (tid < NS) hist[tid] = tid < NBIN_S ? hh[tid] : 0u;
+        if (tid == 0) { s_cut_ok = 0; s_cut = 0; }
+        __syncthreads();
+        for (int o = 1; o < NS; o <<= 1) {
+            const uint32_t add = (tid < NS && tid + o < NS) ? hist[tid + o] : 0u;
+            __syncthreads();
+            if (tid < NS) hist[tid] += add;
+            __syncthreads();
+        }
+        // hist[b] now counts the scores in bins >= b
+        const int bb = score_bin(base);
+        if (tid > bb && tid < NBIN_S) {
+            const uint32_t sfx = hist[tid], nxt = tid + 1 < NS ? hist[tid + 1] : 0u;
+            if (sfx >= batch && nxt < batch && sfx <= CAP) {   // at most one bin qualifies
+                s_cut_ok = 1;
+                s_cut = bin_low(tid) - base;
+            }
+        }
+        if (tid == 0 && (bb + 1 < NS ? hist[bb + 1] : 0u) < batch && hist[bb] <= CAP) s_cut_ok = 1;   // T = 0
+        __syncthreads();
+    }
+    bool first = true;
+
     while (!s_done) {
         // ---- 1) radix select the cut T: all eligible keys in [T, U) form the batch. The first digit
         // pass also counts the eligible keys: none left ends the selection, and when they all fit the
         // batch is all of them (T = 0).
         u128 T = 0;
         bool none_left = false;
-        {
+        const bool from_hist = first && s_cut_ok;
+        first = false;
+        if (from_hist) {
+            T = (u128)s_cut << 32;
+        } else {
             int shift = nbits;
             u128 prefix = 0;
             if (tid == 0) { s_need = batch; s_above = 0; }
@@ -924,7 +999,7 @@ int launch_detect(const IO& io, int n, int width, int height, int pitch, const v
                   int capacity, uint8_t* w8, hipStream_t s)
 {
     const int64_t ib = per_item_bytes(width, height);
-    detect_init_kernel<<<(n + 255) / 256, 256, 0, s>>>(w8, ib, n, io);
+    detect_init_kernel<<<n, 256, 0, s>>>(w8, ib, n, io);
     int e = vs::check_launch("vs_detect_corners(init)");
     if (e) return e;
     const int rw = width - 2 * p.roi_mx, rh = height - 2 * p.roi_my;
