@@ -62,6 +62,18 @@ def test_noise_many_candidates(K, seed):
     assert nc > 4096
 
 
+@pytest.mark.parametrize("w,h", [(33000, 24), (24, 33000)])
+def test_frames_with_a_side_past_32768(w, h):
+    # the selection decides distances in 64-bit arithmetic when a side exceeds 32768 (24-bit
+    # products otherwise); a thin noise frame exercises that branch at a small size
+    say("detect long frame", w, h)
+    img = synth.random_image(w, h, 7)
+    for d in (10, 40):
+        xy, sc, cnt, alive = gpu_detect(img, 300, d=d, cap=300, roi=(2, 2))
+        nc = check_item(img, 300, xy[0], sc[0], cnt[0], alive[0], d=d, roi=(2, 2))
+        assert cnt[0] == 300 and nc > 300
+
+
 def test_checkerboard_ties_and_spacing():
     say("detect checkerboard")
     y, x = np.mgrid[0:240, 0:320]
