@@ -7,8 +7,12 @@ moving-average smoothing (radius 15), bilinear warp. Frames are generated on the
 resident in HBM before timing.
 
 One step = the whole hot path over the whole sequence through the segment-parallel sequence
-path (pyramids, corners, tracking, fits, smoothing, warps of all 600 frames). value = frames/s
-over the timed steps (the median of three timed runs of --steps steps each). Also reported: the plain per-frame streaming path (throughput when frames
+path (pyramids, corners, tracking, fits, smoothing, warps of all 600 frames). Consecutive steps are
+independent batches: by default they rotate over three stabilizer instances, one per HIP stream, so
+one batch's launches fill the gaps of another's (each step does exactly the work of a serial step,
+and every instance's outputs are checked equal to the serial run's). value = frames/s over the
+timed steps (the median of three timed runs of --steps steps each); the serial ms per step (one
+instance, one stream) is reported beside it. Also reported: the plain per-frame streaming path (throughput when frames
 are pushed back to back, and per-frame compute latency p50/p99 when each frame is processed on
 arrival), the roofline of the dominant kernel measured with HIP events on its stream, and the
 CPU oracle timed on a bounded sample.
@@ -351,9 +355,13 @@ def run_serving(seconds: float) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=0, help="truncate the sequence (0: the full 600 frames)")
+    ap.add_argument("--pipeline", type=int, default=3,
+                    help="stabilizer instances, one per HIP stream, that consecutive steps rotate over so that "
+                         "independent batches overlap (1: every step on one instance and the current stream)")
+    ap.add_argument("--serial", action="store_true", help="same as --pipeline 1 (profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=6)
@@ -422,33 +430,77 @@ def main() -> int:
         T.set_tuning(None)
         tuning["choice"] = dataclasses.asdict(T.get_tuning())
 
+    depth = 1 if args.serial else max(1, args.pipeline)
+    inst = [ss] + [SequenceStabilizer(W, H, n, P) for _ in range(depth - 1)]
+    queues = [torch.cuda.Stream() for _ in range(depth)]      # default priority
+
+    def steps_serial(k, lk_events=None, work=None):
+        for _ in range(k):
+            ss.run(frames, lk_events=lk_events)
+            if work is not None:
+                work.append(ss.lk_work.clone())
+
+    def steps_overlapped(k, first=0):
+        # step j runs on instance (first + j) % depth, on that instance's stream: consecutive batches
+        # share nothing but the read-only frames, so they overlap; each instance's own steps stay in order
+        cur = torch.cuda.current_stream()
+        for q in queues:
+            q.wait_stream(cur)
+        for j in range(k):
+            m = (first + j) % depth
+            with torch.cuda.stream(queues[m]):
+                inst[m].run(frames)
+        for q in queues:
+            cur.wait_stream(q)
+
+    def timed(fn, label):
+        runs = []
+        for r in range(3):
+            torch.cuda.synchronize()
+            t_start = torch.cuda.Event(enable_timing=True)
+            t_end = torch.cuda.Event(enable_timing=True)
+            t_start.record()
+            fn()
+            t_end.record()
+            torch.cuda.synchronize()
+            runs.append(t_start.elapsed_time(t_end))
+            log("%s run %d: %.3f ms/step" % (label, r, runs[-1] / max(args.steps, 1)))
+        return runs
+
     for i in range(args.warmup):
-        ss.run(frames)
+        if depth == 1:
+            steps_serial(1)
+        else:
+            steps_overlapped(1, first=i)
         torch.cuda.synchronize()
         log("warmup step %d done" % i)
-    # three timed runs of `steps` steps each; the reported figures are the median run's
+    if depth > 1 and args.warmup < depth:
+        steps_overlapped(depth - args.warmup, first=args.warmup)    # every instance has run once
+        torch.cuda.synchronize()
+    # three timed runs of `steps` steps each; the reported figures are the median run's. With
+    # depth > 1 the headline runs overlap consecutive batches over the instances and a serial set of
+    # runs on one instance follows, which gives the tracker's per-launch durations (not stretched by
+    # kernels of other streams) and the serial ms per step.
+    wall0 = time.perf_counter()
+    if depth > 1:
+        runs_ms = timed(lambda: steps_overlapped(args.steps), "overlapped (%d streams)" % depth)
+    wall = time.perf_counter() - wall0
     lk_events = []
     work = []
-    runs_ms = []
-    wall0 = time.perf_counter()
-    for r in range(3):
-        torch.cuda.synchronize()
-        t_start = torch.cuda.Event(enable_timing=True)
-        t_end = torch.cuda.Event(enable_timing=True)
-        t_start.record()
-        for i in range(args.steps):
-            ss.run(frames, lk_events=lk_events)
-            work.append(ss.lk_work.clone())
-        t_end.record()
-        torch.cuda.synchronize()
-        runs_ms.append(t_start.elapsed_time(t_end))
-        log("timed run %d: %.3f ms/step" % (r, runs_ms[-1] / max(args.steps, 1)))
-    wall = time.perf_counter() - wall0
+    serial_ms = timed(lambda: steps_serial(args.steps, lk_events, work), "serial")
+    if depth == 1:
+        runs_ms = serial_ms
+        wall = time.perf_counter() - wall0
+    if depth > 1:
+        for m in range(1, depth):
+            assert torch.equal(inst[m].out, ss.out) and torch.equal(inst[m].mats, ss.mats), \
+                "instance %d of the overlapped runs differs from the serial run" % m
     ms_total = float(np.median(runs_ms))
     ms_per_step = ms_total / max(args.steps, 1)
+    ms_per_step_serial = float(np.median(serial_ms)) / max(args.steps, 1)
     fps = n * args.steps / (ms_total / 1e3)
-    log("sequence path: %.3f ms/step (median of 3 runs), %.0f frames/s (wall of the 3 runs %.3f s)" %
-        (ms_per_step, fps, wall))
+    log("sequence path: %.3f ms/step (median of 3 runs, %d stream(s)), %.0f frames/s; serial %.3f ms/step "
+        "(wall of the headline runs %.3f s)" % (ms_per_step, depth, fps, ms_per_step_serial, wall))
 
     # roofline of the dominant kernel: the tracker (FP32 VALU bound)
     lk_ms = [a.elapsed_time(b) for a, b in lk_events]
@@ -461,7 +513,7 @@ def main() -> int:
     avg_lk_ms = float(np.mean(lk_ms)) if lk_ms else float("nan")
     achieved_tflops = flop_per_launch / (avg_lk_ms / 1e3) / 1e12
     achieved_ops = flop_per_launch_ops / (avg_lk_ms / 1e3) / 1e12
-    lk_share = float(np.sum(lk_ms) / np.sum(runs_ms)) if runs_ms else float("nan")
+    lk_share = float(np.sum(lk_ms) / np.sum(serial_ms)) if serial_ms else float("nan")
     log("tracker: %.3f ms per launch avg, %.3e FLOP per launch, %.2f TFLOP/s (%.3f of peak), %.0f%% of the step" %
         (avg_lk_ms, flop_per_launch, achieved_tflops, achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 100 * lk_share))
     roofline = {"kernel": "lk_kernel (vs_track_lk)", "bound": "alu", "achieved": round(achieved_tflops, 4),
@@ -567,6 +619,8 @@ def main() -> int:
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
         "runs_ms_per_step": [round(r / max(args.steps, 1), 4) for r in runs_ms],
+        "ms_per_step_serial": round(ms_per_step_serial, 4),
+        "overlapped_streams": depth,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -574,7 +628,9 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "hd: 1920x1080 uint8, %d frames, 1000 corners, 5 levels, 21x21 LK x30 it + backward "
                                "check, RANSAC(128, 1 px) hybrid rigid/similarity, moving average r=15, bilinear warp" % n,
-                   "path": "sequence (segment-parallel, one launch per stage per 5-frame step)",
+                   "path": "sequence (segment-parallel, one launch per stage per 5-frame step)" +
+                           (", consecutive batches overlapped over %d instances on %d HIP streams" % (depth, depth)
+                            if depth > 1 else ""),
                    "frames": n, "width": W, "height": H, "corners": P.max_corners, "levels": P.levels},
         "plain_path": plain,
         "differentiation_pass": diff,
