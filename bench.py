@@ -504,9 +504,12 @@ def main() -> int:
 
     # roofline of the dominant kernel: the tracker (FP32 VALU bound)
     lk_ms = [a.elapsed_time(b) for a, b in lk_events]
-    w = torch.stack(work).sum(dim=2).cpu().numpy()   # [runs x steps, 5, segments, 2] -> [runs x steps, 5, 2]
+    # [runs x steps, launches, segments, 2 or 3] -> [runs x steps, launches, 2 or 3]
+    w = torch.stack(work).sum(dim=2).cpu().numpy()
     nwin = (2 * P.win_half + 1) ** 2
     setups, iters = float(w[..., 0].sum()), float(w[..., 1].sum())
+    # set-ups formed: a backward track and the next pair's forward track share theirs
+    formed = float(w[..., 2].sum()) if w.shape[-1] > 2 else setups
     n_launch = max(len(lk_ms), 1)
     flop_per_launch = (setups * LK_FLOP_SETUP + iters * LK_FLOP_ITER) / n_launch
     flop_per_launch_ops = (setups * LK_FLOP_SETUP_PER_SAMPLE + iters * LK_FLOP_ITER_PER_SAMPLE) * nwin / n_launch
@@ -516,12 +519,19 @@ def main() -> int:
     lk_share = float(np.sum(lk_ms) / np.sum(serial_ms)) if serial_ms else float("nan")
     log("tracker: %.3f ms per launch avg, %.3e FLOP per launch, %.2f TFLOP/s (%.3f of peak), %.0f%% of the step" %
         (avg_lk_ms, flop_per_launch, achieved_tflops, achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 100 * lk_share))
-    roofline = {"kernel": "lk_kernel (vs_track_lk)", "bound": "alu", "achieved": round(achieved_tflops, 4),
+    executed_tflops = (formed * LK_FLOP_SETUP + iters * LK_FLOP_ITER) / n_launch / (avg_lk_ms / 1e3) / 1e12
+    kernel = "lk_segment_kernel7 (vs_track_lk_segments)"
+    roofline = {"kernel": kernel, "bound": "alu",
+                "achieved": round(achieved_tflops, 4),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 5),
                 "traffic": tracker_traffic_from_profile(), "avg_launch_ms": round(avg_lk_ms, 4),
                 "flop_per_launch": flop_per_launch,
                 "flop_units": "8 kFLOP per window set-up, 5.3 kFLOP per iteration (point x level x direction)",
                 "setups_per_launch": setups / n_launch, "iterations_per_launch": iters / n_launch,
+                "launches_per_step": n_launch / max(len(work), 1),
+                "setups_formed_per_launch": formed / n_launch,
+                "achieved_formed": round(executed_tflops, 4),
+                "frac_formed": round(executed_tflops / FP32_VECTOR_PEAK_TFLOPS, 5),
                 "achieved_per_operation_count": round(achieved_ops, 4),
                 "frac_per_operation_count": round(achieved_ops / FP32_VECTOR_PEAK_TFLOPS, 5),
                 "share_of_step": round(lk_share, 4),

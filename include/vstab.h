@@ -143,6 +143,40 @@ int vs_track_lk(const uint8_t* prev_frames, const uint8_t* prev_pyrs, const uint
                 float* xy_chain, uint8_t* alive_chain, uint64_t* work, void* stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * track_lk_segments -- the tracking of vs_track_lk (Section 3.2, Eqs. 3-6) with its backward check
+ * (Section 4.1) over chains of consecutive pairs, the points tracked into a frame being the previous
+ * points of the next pair (Section 3.2: features are tracked on from frame to frame between
+ * re-detections every few frames). Item i is a chain: its frame s (s = 0 .. pairs_i) is at
+ * frames + i * frame_stride + s * frame_step (pyramid at pyrs + i * pyr_stride + s * pyr_step), its
+ * pair s = (frame s, frame s + 1) has the point records r = i * istride + s (slot k of a point array
+ * at [r * capacity + k]); pairs_i = pairs for i < n - 1 and last_pairs for i = n - 1. The call tracks
+ * pairs first .. pairs_i - 1 of every item whose gate lets it in (gate NULL: every item; else
+ * gate[i * istride] < gate_min), starting from the points xy / alive of pair `first`, and writes for
+ * each of those pairs what vs_track_lk writes with xy_chain / alive_chain set to the next pair's
+ * records: dst, status, fb_err (may be NULL; NaN where not computed), n_valid[r] (may be NULL), and
+ * the next pair's xy / alive (not after an item's last pair). It assumes that no pair in the chain is
+ * skipped: where a pair s ends with n_valid < min_valid and frame s + 1 is detected again, a call
+ * with first = s + 1 and the gate at the n_valid of pair s (gate = n_valid + s, gate_min = min_valid)
+ * makes the pairs after it again from the new points; calling it for s + 1 = 1 .. pairs - 1 in
+ * order, each after the gated re-detection of frame s + 1, gives exactly the records of one
+ * vs_track_lk call per pair with the re-detection between them. One wave follows a point slot of an
+ * item through its pairs: every frame is read by its windows around one point position, and with the
+ * backward check the window set-ups of a frame (samples, gradients, tensor and eigenvalue test of
+ * Eqs. 4-6) serve both the backward track of the pair ending there and the forward track of the pair
+ * starting there. Results are those of vs_track_lk bit for bit.
+ * work (may be NULL): uint64[3 * n], set by the call: per item, the window set-ups (point x level x
+ * direction, as separate tracks would form them) and Gauss-Newton iterations of the tracks kept, and
+ * the window set-ups formed (a shared one once). Forward tracks made for points that then fail the
+ * check of the pair before are not counted.
+ * Launches are enqueued on `stream`; nothing is allocated and the host is not synchronised. */
+int vs_track_lk_segments(const uint8_t* frames, const uint8_t* pyrs, int64_t frame_stride, int64_t pyr_stride,
+                         int64_t frame_step, int64_t pyr_step, int32_t n, int32_t istride, int32_t pairs,
+                         int32_t last_pairs, int32_t first, const vs_pyramid* layout, int32_t capacity,
+                         const vs_lk_params* p, float* xy, uint8_t* alive, float* dst, uint8_t* status,
+                         float* fb_err, int32_t* n_valid, const int32_t* gate, int32_t gate_min, uint64_t* work,
+                         void* stream);
+
+/* ---------------------------------------------------------------------------------------------
  * fit_similarity -- Section 4, Eq. 7 (least-squares transform from src to dst points), the
  * similarity (4 DOF) and rigid (3 DOF, unit scale) models, the hybrid mechanism of Section 4.1
  * (compare the RMS residuals E_r and E_s, keep the choice for a dwell of `dwell` pairs) and the

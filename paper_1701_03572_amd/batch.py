@@ -22,7 +22,7 @@ import torch
 
 from . import vstab as V
 from .params import StabParams
-from .pipeline import _detect_params, _fit_params, _lk_params, _smooth_params
+from .pipeline import _detect_params, _fit_params, _lk_params, _smooth_params, track_segments
 
 
 @dataclasses.dataclass(frozen=True)
@@ -114,20 +114,8 @@ class _Class:
         ni = self.n_items
         V.vs_detect_corners(f0, e * fs, self.W, self.H, self.W, ni, e, None, 0, self._dp, cap, xy,
                             self.score.data_ptr(), self.count.data_ptr(), al, self.det_ws, self.det_ws_bytes)
-        for s in range(e):
-            chain = s < e - 1
-            V.vs_track_lk(f0 + s * fs, p0 + s * ps, f0 + (s + 1) * fs, p0 + (s + 1) * ps, e * fs, e * ps, ni, e, L,
-                          xy + s * rec2, al + s * rec1, cap, self._lkp, self.dst.data_ptr() + s * rec2,
-                          self.status.data_ptr() + s * rec1, self.fb_err.data_ptr() + s * cap * 4,
-                          self.n_valid.data_ptr() + s * 4, xy + (s + 1) * rec2 if chain else None,
-                          al + (s + 1) * rec1 if chain else None)
-            if chain:
-                # re-detect where the pair just tracked was skipped (too few valid points)
-                V.vs_detect_corners(f0 + (s + 1) * fs, e * fs, self.W, self.H, self.W, ni, e,
-                                    self.n_valid.data_ptr() + s * 4, self.P0.min_valid, self._dp, cap,
-                                    xy + (s + 1) * rec2, self.score.data_ptr() + (s + 1) * cap * 8,
-                                    self.count.data_ptr() + (s + 1) * 4, al + (s + 1) * rec1, self.det_ws,
-                                    self.det_ws_bytes)
+        track_segments(self, f0, p0, fs, ps, lambda s: ni if 0 <= s < e else 0, self.P0, L, self._lkp, self._dp,
+                       self.W, self.H)
         ib = V.FIT_INFO_BYTES
         for j, (si, spec, off, nf, nseg) in enumerate(self.streams):
             npairs = nf - 1

@@ -79,6 +79,11 @@ struct LKConst {
 };
 
 __device__ __forceinline__ bool wave_all(bool c) { return __ballot(!c) == 0; }
+// a value every lane holds equally, kept in a scalar register (frees a vector register while it waits)
+__device__ __forceinline__ float wave_uniform(float x)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
 // for a condition every lane evaluates identically: a scalar branch condition
 __device__ __forceinline__ bool uniform(bool c) { return __ballot(c) != 0; }
 
@@ -417,10 +422,20 @@ __device__ __forceinline__ void setup_staged(const Img& A, const Img& B, int bx,
     wave_lds_sync();   // the area is written again by the next staging or reduction
 }
 
-template <int RMAX>
-__device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* fb, const uint8_t* pb,
-                          const vs::LevelDesc& d, const LKConst& c, float ux, float uy, float& vx, float& vy,
-                          uint32_t& n_setup, uint32_t& n_iter, float* red)
+// The tracks of one point u of frame A into the target frames t0 .. nt - 1 (at most NT; target t is
+// frame and pyramid (fb[t], pb[t])). Per level the window set-up over A (samples, gradients, the
+// tensor, its eigenvalue test and the sums of I times the gradient) is formed once and serves every
+// target; the first target's first next-frame block is read and summed with it, and every later
+// target reads its first block as a reload. Each target then runs its own Gauss-Newton iterations
+// from its own guess. The arithmetic of a target is that of a track of its own, so its result does
+// not depend on the other targets. ok[t] is false where the point is lost (a weak tensor at level 0,
+// or a final position outside the image). n_setup[t] counts the window set-ups of target t (one per
+// level, as a track of its own would form them) and n_iter[t] its iterations.
+template <int RMAX, int NT>
+__device__ void track_from(const uint8_t* fa, const uint8_t* pa, const uint8_t* const (&fb)[NT],
+                           const uint8_t* const (&pb)[NT], int t0, int nt, const vs::LevelDesc& d, const LKConst& c,
+                           float ux, float uy, float (&vx)[NT], float (&vy)[NT], bool (&ok)[NT],
+                           uint32_t (&n_setup)[NT], uint32_t (&n_iter)[NT], float* red)
 {
     const int lane = threadIdx.x & 63;
     const int gcol = lane % c.cols, grp = lane / c.cols;
@@ -433,11 +448,16 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
     const int lane_off = grp * c.rows * 32 + gcol;       // the lane's first byte in a staged block
     uint32_t* stage = reinterpret_cast<uint32_t*>(red);
 
-    float gx = 0.f, gy = 0.f;
-    bool ok = true;
+    ux = wave_uniform(ux);
+    uy = wave_uniform(uy);
+    float gx[NT], gy[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        gx[t] = gy[t] = 0.f;
+        ok[t] = true;
+    }
     for (int l = d.levels - 1; l >= 0; --l) {
         const Img A = level_img(fa, pa, d, l);
-        const Img B = level_img(fb, pb, d, l);
         const float sc = ldexpf(1.0f, -l);
         const float cx = ux * sc, cy = uy * sc;
         const float fx = floorf(cx), fy = floorf(cy);
@@ -448,21 +468,23 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
         // window's block starting at (fx - h - 1, fy - h - 1)
         const bool a_in = wave_all(!active || (ix - 1 >= 0 && ix + 2 <= A.w - 1 && iy - 1 >= 0 && iy + RMAX + 1 <= A.h - 1));
         const int bx = (int)fx - c.hw - 1, by = (int)fy - c.hw - 1;
-        // the first iterate's next-frame block is read with the set-up, so its residual sums share the
-        // set-up's reduction: 3 tensor sums + 2 sums of I times the gradient + 8 residual sums in one
-        const int jx0 = (int)floorf(cx + gx), jy0 = (int)floorf(cy + gy);
+        // the first target's first next-frame block is read with the set-up, so its residual sums
+        // share the set-up's reduction: 3 tensor sums + 2 sums of I times the gradient + 8 residual sums
+        const Img B0 = level_img(NT == 1 || t0 == 0 ? fb[0] : fb[NT - 1], NT == 1 || t0 == 0 ? pb[0] : pb[NT - 1], d, l);
+        const float g0x = NT == 1 || t0 == 0 ? gx[0] : gx[NT - 1], g0y = NT == 1 || t0 == 0 ? gy[0] : gy[NT - 1];
+        const int jx0 = (int)floorf(cx + g0x), jy0 = (int)floorf(cy + g0y);
         float I[RMAX], Ix[RMAX], Iy[RMAX];
         float qa[RMAX + 1], qb[RMAX + 1];
         bool both_staged = false;
         if constexpr (RMAX <= 7) {
             const int x0 = jx0 + qx, y0 = jy0 + qy0;
-            both_staged = a_in && wave_all(!active || (x0 >= 0 && x0 + 1 <= B.w - 1 && y0 >= 0 && y0 + RMAX <= B.h - 1));
+            both_staged = a_in && wave_all(!active || (x0 >= 0 && x0 + 1 <= B0.w - 1 && y0 >= 0 && y0 + RMAX <= B0.h - 1));
             if (both_staged) {
                 if (c.full)
-                    setup_staged<RMAX, false>(A, B, bx, by, jx0 - c.hw, jy0 - c.hw, lane_off, a, b, nrows, active, red,
+                    setup_staged<RMAX, false>(A, B0, bx, by, jx0 - c.hw, jy0 - c.hw, lane_off, a, b, nrows, active, red,
                                               I, Ix, Iy, qa, qb);
                 else
-                    setup_staged<RMAX, true>(A, B, bx, by, jx0 - c.hw, jy0 - c.hw, lane_off, a, b, nrows, active, red,
+                    setup_staged<RMAX, true>(A, B0, bx, by, jx0 - c.hw, jy0 - c.hw, lane_off, a, b, nrows, active, red,
                                              I, Ix, Iy, qa, qb);
             }
         }
@@ -478,7 +500,7 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
                 else
                     window_samples<RMAX, false, true>(A, ix, iy, bx, by, lane_off, a, b, nrows, active, stage, I, Ix, Iy);
             }
-            load_next_block<RMAX>(B, jx0 + qx, jy0 + qy0, jx0 - c.hw, jy0 - c.hw, lane_off, active, stage, qa, qb);
+            load_next_block<RMAX>(B0, jx0 + qx, jy0 + qy0, jx0 - c.hw, jy0 - c.hw, lane_off, active, stage, qa, qb);
         }
         float v[16];
         residual_partials<RMAX>(Ix, Iy, qa, qb, v + 5);
@@ -499,66 +521,113 @@ __device__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* f
         float E[8];
         e_from_sums(Sx, tot[5], tot[6], tot[7], tot[8], E);
         e_from_sums(Sy, tot[9], tot[10], tot[11], tot[12], E + 4);
-        ++n_setup;
         const float tr = g11 + g22;
         // hardware square root (about 1 ulp): the value only enters the eigenvalue test
         const float sq = __builtin_amdgcn_sqrtf((g11 - g22) * (g11 - g22) + 4.0f * g12 * g12);
         const float lmax = 0.5f * (tr + sq);
         const float det = det2(g11, g22, g12);
-        float nux = 0.f, nuy = 0.f;
         // lambda_min = det / lambda_max, so lambda_min / N >= min_eig is det >= (N min_eig) lambda_max
         // (no division). The tensor is 4 G and the residual sums 2 b (D = 2 grad I): the threshold
         // carries the factor 4, and G^-1 b = 2 (4 G)^-1 (2 b).
         const bool strong = uniform(lmax > 0.f ? det >= c.eig_thr * lmax : c.eig_thr <= 0.f);
-        if (!strong) {
-            if (l == 0) ok = false;
-        } else {
-            // step = (4 G)^-1 (2 b) * 2 = H b with H = 2 adj(4 G) / det(4 G), formed once per level
-            const float inv = 2.0f * __builtin_amdgcn_rcpf(det);
-            const float h11 = g11 * inv, h12 = g12 * inv, h22 = g22 * inv;
-            const float px0 = cx + gx, py0 = cy + gy;
-            float cfx = floorf(px0), cfy = floorf(py0);   // the integer position of the current sums
-            for (int it = 0; it < c.max_iter; ++it) {
-                const float pxx = px0 + nux, pyy = py0 + nuy;
-                float ja = pxx - cfx, jb = pyy - cfy;
-                // the iterate left its pixel unless both fractions lie in [0, 1): as unsigned integers
-                // the bit patterns of [0, 1) are exactly those below 1.0's (negatives carry the sign bit)
-                if (uniform(__float_as_uint(ja) >= 0x3f800000u || __float_as_uint(jb) >= 0x3f800000u)) {
-                    // the integer position moved: new block, new residual sums
-                    const float jfx = floorf(pxx), jfy = floorf(pyy);
-                    cfx = jfx;
-                    cfy = jfy;
-                    ja = pxx - jfx;
-                    jb = pyy - jfy;
-                    const int jx = (int)jfx, jy = (int)jfy;
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti) {
+            // ti walks the slots t0 .. nt - 1 (one slot when NT == 1)
+            const int t = NT == 1 ? 0 : t0 + ti;
+            if (NT > 1 && t >= nt) break;
+            ++n_setup[t];
+            float nux = 0.f, nuy = 0.f;
+            if (!strong) {
+                if (l == 0) ok[t] = false;
+            } else {
+                // step = (4 G)^-1 (2 b) * 2 = H b with H = 2 adj(4 G) / det(4 G), formed once per level
+                const float inv = 2.0f * __builtin_amdgcn_rcpf(det);
+                const float h11 = g11 * inv, h12 = g12 * inv, h22 = g22 * inv;
+                const Img B = (NT == 1 || t == 0) ? level_img(fb[0], pb[0], d, l)
+                                                  : level_img(fb[NT - 1], pb[NT - 1], d, l);
+                const float px0 = cx + gx[t], py0 = cy + gy[t];
+                float cfx = floorf(px0), cfy = floorf(py0);   // the integer position of the current sums
+                if (ti > 0) {
+                    // a later target: its first block read like a reload, its sums added in the order of
+                    // the set-up's reduction (16-lane chunks), as a track of its own adds them
+                    const int jx = (int)cfx, jy = (int)cfy;
                     load_next_block<RMAX>(B, jx + qx, jy + qy0, jx - c.hw, jy - c.hw, lane_off, active, stage, qa, qb);
-                    float e[8], t8[8];
+                    float e[16], t8[8];
                     residual_partials<RMAX>(Ix, Iy, qa, qb, e);
-                    wave_sums<8, 8>(e, t8, red);
+                    wave_sums<16, 8>(e, t8, red);
                     e_from_sums(Sx, t8[0], t8[1], t8[2], t8[3], E);
                     e_from_sums(Sy, t8[4], t8[5], t8[6], t8[7], E + 4);
                 }
-                // b = E0 - ja E1 - jb E2 - ja jb E3 = (E0 - jb E2) - ja (E1 + jb E3)
-                const float b1 = fmaf(-ja, fmaf(jb, E[3], E[1]), fmaf(-jb, E[2], E[0]));
-                const float b2 = fmaf(-ja, fmaf(jb, E[7], E[5]), fmaf(-jb, E[6], E[4]));
-                const float ex = fmaf(h22, b1, -(h12 * b2));
-                const float ey = fmaf(h11, b2, -(h12 * b1));
-                nux += ex;
-                nuy += ey;
-                ++n_iter;
-                if (uniform(ex * ex + ey * ey < c.eps2)) break;
+                for (int it = 0; it < c.max_iter; ++it) {
+                    const float pxx = px0 + nux, pyy = py0 + nuy;
+                    float ja = pxx - cfx, jb = pyy - cfy;
+                    // the iterate left its pixel unless both fractions lie in [0, 1): as unsigned integers
+                    // the bit patterns of [0, 1) are exactly those below 1.0's (negatives carry the sign bit)
+                    if (uniform(__float_as_uint(ja) >= 0x3f800000u || __float_as_uint(jb) >= 0x3f800000u)) {
+                        // the integer position moved: new block, new residual sums
+                        const float jfx = floorf(pxx), jfy = floorf(pyy);
+                        cfx = jfx;
+                        cfy = jfy;
+                        ja = pxx - jfx;
+                        jb = pyy - jfy;
+                        const int jx = (int)jfx, jy = (int)jfy;
+                        load_next_block<RMAX>(B, jx + qx, jy + qy0, jx - c.hw, jy - c.hw, lane_off, active, stage, qa, qb);
+                        float e[8], t8[8];
+                        residual_partials<RMAX>(Ix, Iy, qa, qb, e);
+                        wave_sums<8, 8>(e, t8, red);
+                        e_from_sums(Sx, t8[0], t8[1], t8[2], t8[3], E);
+                        e_from_sums(Sy, t8[4], t8[5], t8[6], t8[7], E + 4);
+                    }
+                    // b = E0 - ja E1 - jb E2 - ja jb E3 = (E0 - jb E2) - ja (E1 + jb E3)
+                    const float b1 = fmaf(-ja, fmaf(jb, E[3], E[1]), fmaf(-jb, E[2], E[0]));
+                    const float b2 = fmaf(-ja, fmaf(jb, E[7], E[5]), fmaf(-jb, E[6], E[4]));
+                    const float ex = fmaf(h22, b1, -(h12 * b2));
+                    const float ey = fmaf(h11, b2, -(h12 * b1));
+                    nux += ex;
+                    nuy += ey;
+                    ++n_iter[t];
+                    if (uniform(ex * ex + ey * ey < c.eps2)) break;
+                }
+            }
+            // the guesses and results are the same in every lane: kept in scalar registers
+            if (l > 0) {
+                gx[t] = wave_uniform(2.0f * (gx[t] + nux));
+                gy[t] = wave_uniform(2.0f * (gy[t] + nuy));
+            } else {
+                vx[t] = wave_uniform(ux + gx[t] + nux);
+                vy[t] = wave_uniform(uy + gy[t] + nuy);
             }
         }
-        if (l > 0) {
-            gx = 2.0f * (gx + nux);
-            gy = 2.0f * (gy + nuy);
-        } else {
-            vx = ux + gx + nux;
-            vy = uy + gy + nuy;
-        }
     }
-    if (!(vx >= 0.f && vy >= 0.f && vx <= (float)(d.w[0] - 1) && vy <= (float)(d.h[0] - 1))) ok = false;
-    return ok;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+        if (!(vx[t] >= 0.f && vy[t] >= 0.f && vx[t] <= (float)(d.w[0] - 1) && vy[t] <= (float)(d.h[0] - 1))) ok[t] = false;
+}
+
+// one track of u from frame A into frame B
+template <int RMAX>
+__device__ __forceinline__ bool track_one(const uint8_t* fa, const uint8_t* pa, const uint8_t* fb, const uint8_t* pb,
+                                          const vs::LevelDesc& d, const LKConst& c, float ux, float uy, float& vx,
+                                          float& vy, uint32_t& n_setup, uint32_t& n_iter, float* red)
+{
+    const uint8_t* const fbs[1] = {fb};
+    const uint8_t* const pbs[1] = {pb};
+    float ox[1] = {vx}, oy[1] = {vy};
+    bool ok[1];
+    uint32_t ns[1] = {n_setup}, ni[1] = {n_iter};
+    track_from<RMAX, 1>(fa, pa, fbs, pbs, 0, 1, d, c, ux, uy, ox, oy, ok, ns, ni, red);
+    vx = ox[0];
+    vy = oy[0];
+    n_setup = ns[0];
+    n_iter = ni[0];
+    return ok[0];
+}
+
+// the round-trip error of the backward check, |b - u|, in one fixed operation order
+__device__ __forceinline__ float fb_error(float bx, float by, float ux, float uy)
+{
+    const float dx = bx - ux, dy = by - uy;
+    return sqrtf(fmaf(dx, dx, dy * dy));
 }
 
 // what one tracked item reads and writes; slot k's point is xy_prev[2k], its outputs at index k
@@ -635,8 +704,8 @@ struct Step {
 };
 
 template <int RMAX, class A>
-__global__ __launch_bounds__(256) void lk_kernel(A io, vs::LevelDesc d, int capacity, LKConst c, int fb, float fb_thresh,
-                                                unsigned long long* work, int n_items, int by_xcd)
+__device__ __forceinline__ void lk_body(const A& io, const vs::LevelDesc& d, int capacity, const LKConst& c, int fb,
+                                        float fb_thresh, unsigned long long* work, int n_items, int by_xcd)
 {
     // each wave of the workgroup tracks one point slot on its own (no barriers): slot = group *
     // waves + wave. All point slots of an item run on one XCD, so the overlapping windows of its
@@ -668,7 +737,7 @@ __global__ __launch_bounds__(256) void lk_kernel(A io, vs::LevelDesc d, int capa
         if (ok && fb) {
             float bx = vx, by = vy;
             const bool okb = track_one<RMAX>(it.fb, it.pb, it.fa, it.pa, d, c, vx, vy, bx, by, n_setup, n_iter, red);
-            err = sqrtf((bx - ux) * (bx - ux) + (by - uy) * (by - uy));
+            err = fb_error(bx, by, ux, uy);
             ok = okb && err <= fb_thresh;
         }
     }
@@ -687,6 +756,180 @@ __global__ __launch_bounds__(256) void lk_kernel(A io, vs::LevelDesc d, int capa
             atomicAdd(&work[2 * item], (unsigned long long)n_setup);
             atomicAdd(&work[2 * item + 1], (unsigned long long)n_iter);
         }
+    }
+}
+
+// Windows of at most 7 rows per lane run five waves per SIMD (at most 96 VGPRs); larger windows keep
+// the registers they need.
+template <class A>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void lk_kernel7(
+    A io, vs::LevelDesc d, int capacity, LKConst c, int fb, float fb_thresh, unsigned long long* work, int n_items,
+    int by_xcd)
+{
+    lk_body<7>(io, d, capacity, c, fb, fb_thresh, work, n_items, by_xcd);
+}
+
+template <class A>
+__global__ __launch_bounds__(256) void lk_kernel16(A io, vs::LevelDesc d, int capacity, LKConst c, int fb,
+                                                  float fb_thresh, unsigned long long* work, int n_items, int by_xcd)
+{
+    lk_body<16>(io, d, capacity, c, fb, fb_thresh, work, n_items, by_xcd);
+}
+
+// One call over chains of tracked pairs (vs_track_lk_segments). Item i holds the frames
+// F(i, s) = frames + i * frame_stride + s * frame_step and the point records of its pair s at record
+// i * istride + s. One wave carries one point slot of one item through the item's pairs: the forward
+// track of the first pair, then for every later frame one window set-up that serves both the
+// backward track of the pair ending there and the forward track of the pair starting there. Each
+// frame of the chain is read by the wave's windows around one point position, so its blocks are
+// fetched once and found in the caches by the tracks that follow.
+struct SegIO {
+    const uint8_t *frames, *pyrs;
+    int64_t frame_stride, pyr_stride, frame_step, pyr_step;
+    int n, istride, capacity, first, pairs, last_pairs;
+    float* xy;
+    uint8_t* alive;
+    float* dst;
+    uint8_t* status;
+    float* fb_err;
+    int32_t* n_valid;
+    const int32_t* gate;
+    int gate_min;
+
+    __device__ __forceinline__ int pairs_of(int i) const { return i == n - 1 ? last_pairs : pairs; }
+    __device__ __forceinline__ bool gated_in(int i) const { return !gate || gate[(int64_t)i * istride] < gate_min; }
+};
+
+template <int RMAX>
+__device__ __forceinline__ void lk_segment_body(const SegIO& io, const vs::LevelDesc& d, const LKConst& c, int fb,
+                                                float fb_thresh, unsigned long long* work, int by_xcd)
+{
+    const int ppg = blockDim.x >> 6;
+    const int groups = (io.capacity + ppg - 1) / ppg;
+    int item, group;
+    if (!vs::xcd_map(blockIdx.x, io.n, groups, by_xcd != 0, item, group)) return;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
+    const int slot = group * ppg + wave;
+    if (slot >= io.capacity) return;
+    const int last = io.pairs_of(item);
+    if (io.first >= last || !io.gated_in(item)) return;
+    const int lane = threadIdx.x & 63;
+    extern __shared__ float lk_lds[];
+    float* red = lk_lds + wave * WAVE_LDS_FLOATS;
+    red[RED_FLOATS + lane] = 0.f;
+    if (lane < ZERO_FLOATS - 64) red[RED_FLOATS + 64 + lane] = 0.f;
+    wave_lds_sync();
+    const uint8_t* f0 = io.frames + item * io.frame_stride;
+    const uint8_t* p0 = io.pyrs + item * io.pyr_stride;
+    const int64_t r0 = (int64_t)item * io.istride;
+    const int cap = io.capacity;
+    int s = io.first;
+    // the point at the start of pair s, whether it entered the pair, and its forward track
+    int64_t k = (r0 + s) * cap + slot;
+    float px = io.xy[2 * k], py = io.xy[2 * k + 1];
+    bool live = io.alive[k] != 0;
+    float vx = px, vy = py;
+    bool fok = false;
+    uint32_t n_kept = 0, i_kept = 0, n_formed = 0;
+    if (live) {
+        uint32_t ns = 0, ni = 0;
+        fok = track_one<RMAX>(f0 + s * io.frame_step, p0 + s * io.pyr_step, f0 + (s + 1) * io.frame_step,
+                              p0 + (s + 1) * io.pyr_step, d, c, px, py, vx, vy, ns, ni, red);
+        n_kept += ns;
+        i_kept += ni;
+        n_formed += ns;
+    }
+    for (; s < last; ++s) {
+        k = (r0 + s) * cap + slot;
+        const bool more = s + 1 < last;
+        const uint8_t* fm = f0 + (s + 1) * io.frame_step;   // the frame pair s ends on
+        const uint8_t* pm = p0 + (s + 1) * io.pyr_step;
+        float nx = vx, ny = vy;                           // the next pair's forward track
+        bool okn = false, ok_s = false;
+        float err = __int_as_float(0x7fc00000);
+        uint32_t ns[2] = {0u, 0u}, ni[2] = {0u, 0u};
+        if (live && fok) {
+            if (fb) {
+                // backward into frame s and forward into frame s + 2 from the same windows of frame s + 1
+                const uint8_t* const fts[2] = {f0 + s * io.frame_step, more ? fm + io.frame_step : fm};
+                const uint8_t* const pts[2] = {p0 + s * io.pyr_step, more ? pm + io.pyr_step : pm};
+                float ox[2] = {vx, vx}, oy[2] = {vy, vy};
+                bool ok[2] = {false, false};
+                track_from<RMAX, 2>(fm, pm, fts, pts, 0, more ? 2 : 1, d, c, vx, vy, ox, oy, ok, ns, ni, red);
+                err = fb_error(ox[0], oy[0], px, py);
+                ok_s = ok[0] && err <= fb_thresh;
+                nx = ox[1];
+                ny = oy[1];
+                okn = ok[1];
+            } else {
+                ok_s = true;
+                if (more)
+                    okn = track_one<RMAX>(fm, pm, fm + io.frame_step, pm + io.pyr_step, d, c, vx, vy, nx, ny, ns[1],
+                                          ni[1], red);
+            }
+        }
+        n_kept += ns[0] + (ok_s ? ns[1] : 0u);
+        i_kept += ni[0] + (ok_s ? ni[1] : 0u);
+        n_formed += fb ? ns[0] : (ok_s ? ns[1] : 0u);
+        if (lane == 0) {
+            io.dst[2 * k] = vx;
+            io.dst[2 * k + 1] = vy;
+            io.status[k] = ok_s ? 1 : 0;
+            if (io.fb_err) io.fb_err[k] = err;
+            if (ok_s && io.n_valid) atomicAdd(io.n_valid + r0 + s, 1);
+            if (more) {
+                const int64_t kn = k + cap;
+                io.xy[2 * kn] = vx;
+                io.xy[2 * kn + 1] = vy;
+                io.alive[kn] = ok_s ? 1 : 0;
+            }
+        }
+        // pair s + 1 starts where pair s ended; a point lost in pair s stays there
+        px = vx;
+        py = vy;
+        live = ok_s;
+        if (ok_s) {
+            vx = wave_uniform(nx);
+            vy = wave_uniform(ny);
+        }
+        fok = ok_s && okn;
+    }
+    if (lane == 0 && work && n_formed) {
+        atomicAdd(&work[3 * item], (unsigned long long)n_kept);
+        atomicAdd(&work[3 * item + 1], (unsigned long long)i_kept);
+        atomicAdd(&work[3 * item + 2], (unsigned long long)n_formed);
+    }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void lk_segment_kernel7(
+    SegIO io, vs::LevelDesc d, LKConst c, int fb, float fb_thresh, unsigned long long* work, int by_xcd)
+{
+    lk_segment_body<7>(io, d, c, fb, fb_thresh, work, by_xcd);
+}
+
+__global__ __launch_bounds__(256) void lk_segment_kernel16(SegIO io, vs::LevelDesc d, LKConst c, int fb,
+                                                          float fb_thresh, unsigned long long* work, int by_xcd)
+{
+    lk_segment_body<16>(io, d, c, fb, fb_thresh, work, by_xcd);
+}
+
+// points (waves) per workgroup of a gated segment call: the most the kernels' 256-thread bound allows
+constexpr int LK_MAX_THREADS = 256;
+constexpr int GATED_POINTS_PER_GROUP = LK_MAX_THREADS / 64;
+
+// clears the valid counts of the pairs a segment call makes (items the gate lets in) and its counters
+__global__ void zero_segment_counters(SegIO io, unsigned long long* work)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= io.n) return;
+    if (io.n_valid && io.gated_in(i)) {
+        const int last = io.pairs_of(i);
+        for (int s = io.first; s < last; ++s) io.n_valid[(int64_t)i * io.istride + s] = 0;
+    }
+    if (work) {
+        work[3 * i] = 0;
+        work[3 * i + 1] = 0;
+        work[3 * i + 2] = 0;
     }
 }
 
@@ -728,9 +971,9 @@ int launch_lk(const A& io, const vs_pyramid& layout, int capacity, const LKConst
     const unsigned threads = 64u * (unsigned)ppg;
     const size_t lds = sizeof(float) * WAVE_LDS_FLOATS * (size_t)ppg;
     if (c.rows <= 7)
-        lk_kernel<7, A><<<grid, threads, lds, s>>>(io, d, capacity, c, p.fb, p.fb_thresh, wk, n, by_xcd);
+        lk_kernel7<A><<<grid, threads, lds, s>>>(io, d, capacity, c, p.fb, p.fb_thresh, wk, n, by_xcd);
     else
-        lk_kernel<16, A><<<grid, threads, lds, s>>>(io, d, capacity, c, p.fb, p.fb_thresh, wk, n, by_xcd);
+        lk_kernel16<A><<<grid, threads, lds, s>>>(io, d, capacity, c, p.fb, p.fb_thresh, wk, n, by_xcd);
     return vs::check_launch("vs_track_lk");
 }
 
@@ -791,4 +1034,46 @@ extern "C" int vs_track_lk(const uint8_t* prev_frames, const uint8_t* prev_pyrs,
     const Strided io{prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride, pyr_stride, istride, capacity,
                      xy_prev, alive_prev, xy_next, status, fb_err, n_valid, xy_chain, alive_chain};
     return launch_lk(io, *layout, capacity, c, *p, wk, n, s);
+}
+
+extern "C" int vs_track_lk_segments(const uint8_t* frames, const uint8_t* pyrs, int64_t frame_stride,
+                                    int64_t pyr_stride, int64_t frame_step, int64_t pyr_step, int32_t n,
+                                    int32_t istride, int32_t pairs, int32_t last_pairs, int32_t first,
+                                    const vs_pyramid* layout, int32_t capacity, const vs_lk_params* p, float* xy,
+                                    uint8_t* alive, float* dst, uint8_t* status, float* fb_err, int32_t* n_valid,
+                                    const int32_t* gate, int32_t gate_min, uint64_t* work, void* stream)
+{
+    if (!layout || !p) return vs::set_error(VS_ERR_INVALID, "vs_track_lk_segments: null argument");
+    if (n < 0 || capacity < 0 || istride < 1 || pairs < 0 || last_pairs < 0 || last_pairs > pairs || first < 0 ||
+        pairs > istride)
+        return vs::set_error(VS_ERR_INVALID, "vs_track_lk_segments: bad count, stride or pair range");
+    if (n == 0 || capacity == 0 || first >= pairs) return VS_OK;
+    if (!frames || (layout->levels > 1 && !pyrs) || !xy || !alive || !dst || !status)
+        return vs::set_error(VS_ERR_INVALID, "vs_track_lk_segments: null argument");
+    const int ec = check_lk(*layout, *p, capacity, n);
+    if (ec) return ec;
+    const LKConst c = lk_const(*p);
+    hipStream_t s = vs::as_stream(stream);
+    unsigned long long* wk = reinterpret_cast<unsigned long long*>(work);
+    const SegIO io{frames, pyrs, frame_stride, pyr_stride, frame_step, pyr_step, n, istride, capacity, first, pairs,
+                   last_pairs, xy, alive, dst, status, fb_err, n_valid, gate, gate_min};
+    if (n_valid || wk) {
+        zero_segment_counters<<<(n + 255) / 256, 256, 0, s>>>(io, wk);
+        const int e = vs::check_launch("vs_track_lk_segments(zero)");
+        if (e) return e;
+    }
+    const vs::LevelDesc d = vs::level_desc(*layout);
+    const bool by_xcd = n >= vs::xcd_min_items(vs::XCD_LK);
+    // a gated call usually lets few items in: larger workgroups make the ones gated out cheap to dispatch
+    const int ppg = gate ? GATED_POINTS_PER_GROUP : vs::lk_points_per_group();
+    const int64_t nblk = vs::xcd_grid(n, (capacity + ppg - 1) / ppg, by_xcd);
+    if (nblk > 0x7fffffff) return vs::set_error(VS_ERR_INVALID, "vs_track_lk_segments: grid too large");
+    const unsigned threads = 64u * (unsigned)ppg;
+    if (threads > (unsigned)LK_MAX_THREADS) return vs::set_error(VS_ERR_INVALID, "vs_track_lk_segments: workgroup too large");
+    const size_t lds = sizeof(float) * WAVE_LDS_FLOATS * (size_t)ppg;
+    if (c.rows <= 7)
+        lk_segment_kernel7<<<(unsigned)nblk, threads, lds, s>>>(io, d, c, p->fb, p->fb_thresh, wk, by_xcd);
+    else
+        lk_segment_kernel16<<<(unsigned)nblk, threads, lds, s>>>(io, d, c, p->fb, p->fb_thresh, wk, by_xcd);
+    return vs::check_launch("vs_track_lk_segments");
 }

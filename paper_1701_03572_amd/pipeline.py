@@ -74,6 +74,81 @@ def _bytes(n: int, device) -> torch.Tensor:
     return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
 
 
+def track_segments(o, f0: int, p0: int, fs: int, ps: int, pairs_of, P: StabParams, layout, lkp, dp, W: int, H: int,
+                   work: torch.Tensor | None = None, lk_events: list | None = None, chain: bool | None = None) -> None:
+    """Tracks every 5-frame segment of a resident sequence (or of a batch of sequences laid out on the
+    same cadence): segment i starts at frame i * e (e = P.redetect_every) with the corners detected
+    there, and its pairs (i e + s, i e + s + 1), s = 0 .. e - 1, are tracked in chain (Section 3.2),
+    re-detecting on the device after a skipped pair. pairs_of(s) is the number of segments that have
+    pair s (a prefix of the segments). ``o`` holds the point records (src, asrc, dst, status, fb_err:
+    pair-major, capacity slots each), n_valid, the detection outputs (score, count) and the detection
+    workspace (det_ws, det_ws_bytes).
+
+    By default one vs_track_lk_segments call tracks every segment through all its pairs (one wave per
+    point and segment), assuming that no pair is skipped; then, for s = 1 .. e - 1, the segments whose
+    pair s - 1 was skipped detect frame s again and have their pairs from s on tracked again (both
+    gated on the device by that pair's valid count). ``chain=False`` makes one vs_track_lk call per
+    pair instead, each followed by the gated re-detection. Both give the same records. work: int64
+    [1, segments, 3] (segment calls) or [e, segments, 2] (per-pair calls) counters of the first call;
+    lk_events: (start, end) timing events around every tracking launch are appended."""
+    e, cap = P.redetect_every, o.src.shape[1]
+    xy, al, dst, st = o.src.data_ptr(), o.asrc.data_ptr(), o.dst.data_ptr(), o.status.data_ptr()
+    fbe, nv = o.fb_err.data_ptr(), o.n_valid.data_ptr()
+    rec2, rec1, rec4 = cap * 2 * 4, cap, cap * 4
+
+    def timed_launch(fn):
+        if lk_events is None:
+            fn()
+            return
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        ev[0].record()
+        fn()
+        ev[1].record()
+        lk_events.append(ev)
+
+    def redetect(t: int, n_items: int):
+        # re-detect frame t where pair t - 1 was skipped (too few valid points)
+        V.vs_detect_corners(f0 + t * fs, e * fs, W, H, W, n_items, e, nv + (t - 1) * 4, P.min_valid, dp, cap,
+                            xy + t * rec2, o.score.data_ptr() + t * cap * 8, o.count.data_ptr() + t * 4,
+                            al + t * rec1, o.det_ws, o.det_ws_bytes)
+
+    if chain is None:
+        chain = True
+    if chain:
+        n_seg = pairs_of(0)
+        if n_seg <= 0:
+            return
+        last_pairs = sum(1 for s in range(e) if pairs_of(s) == n_seg)
+        assert all(pairs_of(s) >= n_seg - 1 for s in range(e)), "only the last segment may be shorter"
+
+        def segments(first: int, n_items: int, gate: int | None, wk):
+            lp = last_pairs if n_items == n_seg else e
+            V.vs_track_lk_segments(f0, p0, e * fs, e * ps, fs, ps, n_items, e, e, lp, first, layout, cap, lkp, xy,
+                                   al, dst, st, fbe, nv, gate, P.min_valid, wk)
+
+        timed_launch(lambda: segments(0, n_seg, None, work[0] if work is not None else None))
+        for s in range(1, e):
+            n_s = pairs_of(s)
+            if n_s <= 0:
+                break
+            redetect(s, n_s)
+            timed_launch(lambda: segments(s, n_s, nv + (s - 1) * 4, None))
+        return
+    for s in range(e):
+        n_s = pairs_of(s)
+        if n_s <= 0:
+            break
+        chain = s < e - 1
+        timed_launch(lambda: V.vs_track_lk(
+            f0 + s * fs, p0 + s * ps, f0 + (s + 1) * fs, p0 + (s + 1) * ps, e * fs, e * ps, n_s, e, layout,
+            xy + s * rec2, al + s * rec1, cap, lkp, dst + s * rec2, st + s * rec1, fbe + s * rec4, nv + s * 4,
+            xy + (s + 1) * rec2 if chain else None, al + (s + 1) * rec1 if chain else None,
+            work[s] if work is not None else None))
+        n_next = pairs_of(s + 1) if chain else 0
+        if n_next > 0:
+            redetect(s + 1, n_next)
+
+
 class SequenceStabilizer:
     """Whole-sequence (offline) path with segment-parallel tracking. Buffers are allocated once
     for a (width, height, max_frames) shape and reused by every ``run``."""
@@ -110,8 +185,8 @@ class SequenceStabilizer:
         self.n_emitted = torch.zeros(1, dtype=torch.int32, device=dev)
         self.first = torch.zeros(1, dtype=torch.int64, device=dev)
         self.out = torch.empty((n, height, width), dtype=torch.uint8, device=dev)
-        # per tracking step and segment: [window set-ups, iterations] of its vs_track_lk launch
-        self.lk_work = torch.zeros((P.redetect_every, self.n_seg_max, 2), dtype=torch.int64, device=dev)
+        # per segment: [window set-ups, iterations, set-ups formed] of the tracking call
+        self.lk_work = torch.zeros((1, self.n_seg_max, 3), dtype=torch.int64, device=dev)
         self._lkp = _lk_params(P)
         self._dp = _detect_params(P, width, height)
         self._fp = _fit_params(P, width, height)
@@ -136,31 +211,8 @@ class SequenceStabilizer:
             xy, al = self.src.data_ptr(), self.asrc.data_ptr()
             V.vs_detect_corners(f0, e * fs, self.W, self.H, self.W, n_seg, e, None, 0, self._dp, cap, xy,
                                 self.score.data_ptr(), self.count.data_ptr(), al, self.det_ws, self.det_ws_bytes)
-            rec2, rec1 = cap * 2 * 4, cap                      # bytes per point record / flag record
-            for s in range(e):
-                n_s = (n_pairs - 1 - s) // e + 1 if s <= n_pairs - 1 else 0
-                if n_s <= 0:
-                    break
-                chain = s < e - 1
-                if lk_events is not None:
-                    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                    ev[0].record()
-                V.vs_track_lk(f0 + s * fs, p0 + s * ps, f0 + (s + 1) * fs, p0 + (s + 1) * ps, e * fs, e * ps, n_s, e,
-                              L, xy + s * rec2, al + s * rec1, cap, self._lkp, self.dst.data_ptr() + s * rec2,
-                              self.status.data_ptr() + s * rec1, self.fb_err.data_ptr() + s * cap * 4,
-                              self.n_valid.data_ptr() + s * 4, xy + (s + 1) * rec2 if chain else None,
-                              al + (s + 1) * rec1 if chain else None, self.lk_work[s])
-                if lk_events is not None:
-                    ev[1].record()
-                    lk_events.append(ev)
-                n_next = (n_pairs - 1 - (s + 1)) // e + 1 if s + 1 <= n_pairs - 1 else 0
-                if chain and n_next > 0:
-                    # re-detect where the pair just tracked was skipped (too few valid points)
-                    V.vs_detect_corners(f0 + (s + 1) * fs, e * fs, self.W, self.H, self.W, n_next, e,
-                                        self.n_valid.data_ptr() + s * 4, P.min_valid, self._dp, cap,
-                                        xy + (s + 1) * rec2, self.score.data_ptr() + (s + 1) * cap * 8,
-                                        self.count.data_ptr() + (s + 1) * 4, al + (s + 1) * rec1, self.det_ws,
-                                        self.det_ws_bytes)
+            track_segments(self, f0, p0, fs, ps, lambda s: (n_pairs - 1 - s) // e + 1 if 0 <= s <= n_pairs - 1 else 0,
+                           P, L, self._lkp, self._dp, self.W, self.H, self.lk_work, lk_events)
             V.vs_fit_state_init(self.fit_state)
             V.vs_fit_motion(self.src, self.dst, self.status, cap, n_pairs, self._fp, 0, self.fit_state,
                             self.pair_params, self.affine6, self.info, self.inliers, self.fit_ws, self.fit_ws_bytes)

@@ -121,6 +121,9 @@ _SIGS = {
                                     C.POINTER(vs_detect_params), C.c_int32, _P, _P, _P, _P, _P, C.c_size_t, _P]),
     "vs_track_lk": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.POINTER(vs_pyramid), _P, _P,
                               C.c_int32, C.POINTER(vs_lk_params), _P, _P, _P, _P, _P, _P, _P, _P]),
+    "vs_track_lk_segments": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
+                                       C.c_int32, C.c_int32, C.c_int32, C.POINTER(vs_pyramid), C.c_int32,
+                                       C.POINTER(vs_lk_params), _P, _P, _P, _P, _P, _P, _P, C.c_int32, _P, _P]),
     "vs_fit_workspace": (C.c_size_t, [C.c_int32, C.c_int32]),
     "vs_fit_state_init": (C.c_int, [_P, _P]),
     "vs_fit_similarity": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.POINTER(vs_fit_params), C.c_int64, _P, _P,
@@ -308,6 +311,16 @@ def vs_track_lk(prev_frames, prev_pyrs, next_frames, next_pyrs, frame_stride: in
                               pyr_stride, n, istride, C.byref(layout), _ptr(xy_prev), _ptr(alive_prev), capacity,
                               C.byref(params), _ptr(xy_next), _ptr(status), _ptr(fb_err), _ptr(n_valid),
                               _ptr(xy_chain), _ptr(alive_chain), _ptr(work), _stream(stream)), "vs_track_lk")
+
+
+def vs_track_lk_segments(frames, pyrs, frame_stride: int, pyr_stride: int, frame_step: int, pyr_step: int, n: int,
+                         istride: int, pairs: int, last_pairs: int, first: int, layout: vs_pyramid, capacity: int,
+                         params: vs_lk_params, xy, alive, dst, status, fb_err=None, n_valid=None, gate=None,
+                         gate_min: int = 0, work=None, stream=None):
+    _check(load().vs_track_lk_segments(_ptr(frames), _ptr(pyrs), frame_stride, pyr_stride, frame_step, pyr_step, n,
+                                       istride, pairs, last_pairs, first, C.byref(layout), capacity, C.byref(params),
+                                       _ptr(xy), _ptr(alive), _ptr(dst), _ptr(status), _ptr(fb_err), _ptr(n_valid),
+                                       _ptr(gate), gate_min, _ptr(work), _stream(stream)), "vs_track_lk_segments")
 
 
 def vs_fit_workspace(n: int, capacity: int) -> int:

@@ -1,0 +1,120 @@
+"""vs_track_lk_segments against one vs_track_lk call per pair (Section 3.2, Eqs. 3-6; Section 4.1).
+
+One call that carries every point of a segment through all its pairs (sharing each frame's window
+set-ups between the backward track ending there and the forward track starting there), followed by
+the gated re-detections and gated re-tracking of the pairs after a skipped one, must leave exactly the
+records that one vs_track_lk call per pair leaves (positions, statuses, round-trip errors, valid
+counts, chained points), bit for bit: without skips, with skipped pairs (blank frames: the device gate
+re-detects the frame after a skipped pair and the gated call tracks the rest of that segment again),
+with a last segment shorter than the others, without the backward check, and with points the
+detection left dead. The work counters of the kept tracks equal the per-pair calls' in segments
+without a skipped pair, and the set-ups formed are fewer (none is shared in a segment whose points all died).
+"""
+import dataclasses
+import types
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import dev, say
+from paper_1701_03572_amd import params, synth
+from paper_1701_03572_amd import vstab as V
+from paper_1701_03572_amd.pipeline import _detect_params, _lk_params, track_segments
+
+pytestmark = pytest.mark.gpu
+
+
+def run_tracking(frames_np, P, chain):
+    n, h, w = frames_np.shape
+    e, cap = P.redetect_every, P.max_corners
+    n_pairs = n - 1
+    n_seg = -(-n_pairs // e)
+    L = V.vs_pyramid_layout(w, h, w, P.levels)
+    frames = dev(frames_np)
+    pyr = torch.zeros((n, max(L.bytes, 1)), dtype=torch.uint8, device="cuda")
+    V.vs_build_pyramid(frames, h * w, pyr, L.bytes, n, L)
+    o = types.SimpleNamespace()
+    o.src = torch.full((n, cap, 2), -3.0, dtype=torch.float32, device="cuda")
+    o.asrc = torch.zeros((n, cap), dtype=torch.uint8, device="cuda")
+    o.dst = torch.full((n, cap, 2), -7.0, dtype=torch.float32, device="cuda")
+    o.status = torch.full((n, cap), 9, dtype=torch.uint8, device="cuda")
+    o.fb_err = torch.full((n, cap), -1.0, dtype=torch.float32, device="cuda")
+    o.n_valid = torch.full((n,), -5, dtype=torch.int32, device="cuda")
+    o.count = torch.zeros(n, dtype=torch.int32, device="cuda")
+    o.score = torch.zeros((n, cap), dtype=torch.float64, device="cuda")
+    o.det_ws_bytes = V.vs_detect_workspace(w, h, n_seg)
+    o.det_ws = torch.empty(o.det_ws_bytes, dtype=torch.uint8, device="cuda")
+    dp = _detect_params(P, w, h)
+    V.vs_detect_corners(frames, e * h * w, w, h, w, n_seg, e, None, 0, dp, cap, o.src, o.score, o.count, o.asrc,
+                        o.det_ws, o.det_ws_bytes)
+    work = torch.zeros((1, n_seg, 3) if chain else (e, n_seg, 2), dtype=torch.int64, device="cuda")
+    track_segments(o, frames.data_ptr(), pyr.data_ptr(), h * w, L.bytes,
+                   lambda s: (n_pairs - 1 - s) // e + 1 if 0 <= s <= n_pairs - 1 else 0, P, L, _lk_params(P), dp, w, h,
+                   work, chain=chain)
+    torch.cuda.synchronize()
+    rec = {k: getattr(o, k)[:n_pairs].cpu().numpy() for k in ("src", "asrc", "dst", "status", "fb_err", "n_valid")}
+    return rec, work.cpu().numpy()
+
+
+def check_equal(a, b):
+    for k in a:
+        if k == "fb_err":
+            np.testing.assert_array_equal(a[k].view(np.uint32), b[k].view(np.uint32), err_msg=k)
+        else:
+            np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+@pytest.mark.parametrize("name,n,blanks,fb", [("tiny", 23, (), True), ("tiny", 23, (3, 12), True),
+                                              ("tiny", 19, (4, 5, 16), True), ("vga", 13, (7,), True),
+                                              ("tiny", 23, (3, 12), False), ("tiny", 21, (), False)])
+def test_segments_equal_per_pair_calls(name, n, blanks, fb):
+    say("lk segments", name, n, blanks, "fb", fb)
+    sq = synth.make_sequence(name, n_frames=n)
+    frames = sq.frames.copy()
+    for b in blanks:
+        frames[b] = 90                   # a blank frame: the pair into it is skipped, it is re-detected
+    P = dataclasses.replace(params.PRESETS[name], fb=fb)
+    ref, w_ref = run_tracking(frames, P, chain=False)
+    got, w_got = run_tracking(frames, P, chain=True)
+    check_equal(ref, got)
+    skipped = ref["n_valid"] < P.min_valid
+    say("pairs", n - 1, "skipped", np.nonzero(skipped)[0].tolist(), "valid", ref["n_valid"].tolist())
+    if blanks:
+        assert skipped.any()
+    else:
+        assert not skipped.any()
+    # counters: per segment, the kept tracks' set-ups and iterations; fewer set-ups formed
+    # (the counters are the first call's: in segments with a skipped pair, of its tracks past the skip too)
+    s_ref, s_got = w_ref.sum(axis=0), w_got.sum(axis=0)
+    e = P.redetect_every
+    clean = np.array([not skipped[i * e:(i + 1) * e].any() for i in range(len(s_ref))])
+    np.testing.assert_array_equal(s_ref[clean, :2], s_got[clean, :2])
+    if fb:
+        assert (s_got[:, 2] <= s_got[:, 0]).all() and s_got[:, 2].sum() < s_got[:, 0].sum()
+    else:
+        np.testing.assert_array_equal(s_got[:, 2], s_got[:, 0])
+    say("set-ups", int(s_got[:, 0].sum()), "formed", int(s_got[:, 2].sum()), "iterations", int(s_got[:, 1].sum()))
+
+
+def test_segment_call_without_items_is_a_noop():
+    P = params.PRESETS["tiny"]
+    L = V.vs_pyramid_layout(320, 240, 320, P.levels)
+    f = torch.zeros((2, 240, 320), dtype=torch.uint8, device="cuda")
+    xy = torch.zeros((8, 2), dtype=torch.float32, device="cuda")
+    fl = torch.zeros(8, dtype=torch.uint8, device="cuda")
+    V.vs_track_lk_segments(f, f, 0, 0, 0, 0, 0, 5, 5, 5, 0, L, 8, _lk_params(P), xy, fl, xy, fl)
+    V.vs_track_lk_segments(f, f, 0, 0, 0, 0, 1, 5, 5, 5, 5, L, 8, _lk_params(P), xy, fl, xy, fl)
+    torch.cuda.synchronize()
+
+
+def test_segment_call_rejects_bad_ranges():
+    P = params.PRESETS["tiny"]
+    L = V.vs_pyramid_layout(320, 240, 320, P.levels)
+    f = torch.zeros((2, 240, 320), dtype=torch.uint8, device="cuda")
+    xy = torch.zeros((8, 2), dtype=torch.float32, device="cuda")
+    fl = torch.zeros(8, dtype=torch.uint8, device="cuda")
+    for pairs, last, first, istride in ((5, 6, 0, 5), (6, 5, 0, 5), (5, 5, -1, 5)):
+        with pytest.raises(V.VsError):
+            V.vs_track_lk_segments(f, f, 0, 0, 0, 0, 1, istride, pairs, last, first, L, 8, _lk_params(P), xy, fl, xy,
+                                   fl)
