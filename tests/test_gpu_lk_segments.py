@@ -97,6 +97,21 @@ def test_segments_equal_per_pair_calls(name, n, blanks, fb):
     say("set-ups", int(s_got[:, 0].sum()), "formed", int(s_got[:, 2].sum()), "iterations", int(s_got[:, 1].sum()))
 
 
+@pytest.mark.parametrize("win_half", [2, 5, 7, 12, 15])
+def test_segments_equal_per_pair_calls_other_windows(win_half):
+    # windows whose rows do not fill every lane group (weighted samples) and windows of more than 7 rows
+    # per lane (the 16-row kernel instance), with a skipped pair
+    say("lk segments win_half", win_half)
+    sq = synth.make_sequence("tiny", n_frames=14)
+    frames = sq.frames.copy()
+    frames[7] = 90
+    P = dataclasses.replace(params.PRESETS["tiny"], win_half=win_half)
+    ref, w_ref = run_tracking(frames, P, chain=False)
+    got, w_got = run_tracking(frames, P, chain=True)
+    check_equal(ref, got)
+    assert (ref["n_valid"] < P.min_valid).any() and (ref["n_valid"] >= P.min_valid).any()
+
+
 def test_segment_call_without_items_is_a_noop():
     P = params.PRESETS["tiny"]
     L = V.vs_pyramid_layout(320, 240, 320, P.levels)
