@@ -3,8 +3,8 @@
 Streams whose frame shape and launch-wide parameters agree form a class. The frames of a class's
 streams share one buffer in which every stream starts at a slot that is a multiple of the
 re-detection cadence e, so the 5-frame segments of all its streams are the items of the same
-launches: pyramids, corner detection (each segment with its stream's corner budget), the e tracking
-steps with device-side re-detection, and the warps run once per class. The slot after a stream's last
+launches: pyramids, corner detection (each segment with its stream's corner budget), the tracking of
+every segment through its pairs with device-side re-detection, and the warps run once per class. The slot after a stream's last
 segment is padding: its segment gets a corner budget of 0 and its frames replicate the stream's last
 frame, so it costs little and touches nothing of the stream. Fits and smoothing keep per-stream
 state (dwell decisions, trajectory) and run once per stream. ``run`` enqueues everything on the

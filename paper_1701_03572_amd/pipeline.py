@@ -7,9 +7,9 @@ window) or not at all (causal / Kalman).
 
 ``SequenceStabilizer`` runs a whole resident sequence (the offline version, Stage I of the paper,
 Section 7.1) with cross-frame parallelism: all pyramids in one launch, corner detection on every
-5th frame in one launch, then five tracking steps each covering all 5-frame segments at once
-(re-detection after a skipped pair stays on the device through gated launches), all fits, the
-smoothing and all warps in one launch each. Segments are independent because corners are
+5th frame in one launch, then one tracking launch that carries every point of every 5-frame segment
+through the segment's pairs (re-detection and re-tracking after a skipped pair stay on the device
+through gated launches), all fits, the smoothing and all warps in one launch each. Segments are independent because corners are
 re-detected every 5 frames (Section 3.2), so both paths produce bit-identical results.
 
 Every operation runs in libvstab's HIP kernels; torch only allocates device memory and supplies
