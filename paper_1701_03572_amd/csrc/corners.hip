@@ -450,7 +450,9 @@ __global__ __launch_bounds__(64 * RESP_WAVES) __attribute__((amdgpu_waves_per_eu
                                                                           uint8_t* ws, int64_t item_bytes)
 {
     __shared__ WaveQueues s_q[RESP_WAVES];
-    const int gw = blockIdx.x * RESP_WAVES + (threadIdx.x >> 6);   // one independent wave per (item, strip, segment)
+    // one independent wave per (item, strip, segment); the wave index is read as a scalar, so the item,
+    // its image and the buffer descriptor are known to be uniform (no per-load waterfall loops)
+    const int gw = blockIdx.x * RESP_WAVES + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int per_item = strips * segs;
     const int item = gw / per_item;
     if (item >= n_items) return;
@@ -468,7 +470,7 @@ __global__ __launch_bounds__(64 * RESP_WAVES) __attribute__((amdgpu_waves_per_eu
     cx.xb = ((cx.out_lo - 4) & ~3) + 4 * cx.lane;   // lanes 1..62 cover [out_lo, out_lo + SW)
     cx.oy = my + sr * seg;
     cx.oy_end = min(cx.oy + sr, cx.ry1);
-    cx.img = io.img(item);
+    cx.img = vs::uniform_ptr(io.img(item));   // a batched step reads it from memory
     CandHeader* hd = hdr_of(ws, item_bytes, item);
     cx.count = &hd->count;
     cx.hist = hist_of(ws, item_bytes, item);

@@ -40,6 +40,17 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A pointer every lane of the wave holds equally, as a scalar (a buffer descriptor made from it then
+// stays in scalar registers instead of being re-checked lane by lane before every load).
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p)
+{
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
 // Wave64 butterfly sums: every lane ends with the same, bit-identical total (each stage adds the
 // same two operands in every lane, and addition is commutative).
 __device__ __forceinline__ double wave_sum_d(double v)

@@ -107,6 +107,10 @@ __global__ __launch_bounds__(256, 5) void warp_kernel(IO io, int W, int H, int s
     const double* M;
     uint8_t* dst;
     if (!io.at(item, s, M, dst)) return;
+    // the item is the workgroup's: its pointers are uniform (a batched step reads them from memory)
+    s = vs::uniform_ptr(s);
+    M = vs::uniform_ptr(M);
+    dst = vs::uniform_ptr(dst);
     const double rdet = 1.0 / (M[0] * M[4] - M[1] * M[3]);
     const double i00 = M[4] * rdet, i01 = -M[1] * rdet, i10 = -M[3] * rdet, i11 = M[0] * rdet;
     const double i02 = -(i00 * M[2] + i01 * M[5]);
