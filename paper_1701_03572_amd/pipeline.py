@@ -75,7 +75,7 @@ def _bytes(n: int, device) -> torch.Tensor:
 
 
 def track_segments(o, f0: int, p0: int, fs: int, ps: int, pairs_of, P: StabParams, layout, lkp, dp, W: int, H: int,
-                   work: torch.Tensor | None = None, lk_events: list | None = None, chain: bool | None = None) -> None:
+                   work: torch.Tensor | None = None, lk_events: list | None = None, per_pair: bool = False) -> None:
     """Tracks every 5-frame segment of a resident sequence (or of a batch of sequences laid out on the
     same cadence): segment i starts at frame i * e (e = P.redetect_every) with the corners detected
     there, and its pairs (i e + s, i e + s + 1), s = 0 .. e - 1, are tracked in chain (Section 3.2),
@@ -87,7 +87,7 @@ def track_segments(o, f0: int, p0: int, fs: int, ps: int, pairs_of, P: StabParam
     By default one vs_track_lk_segments call tracks every segment through all its pairs (one wave per
     point and segment), assuming that no pair is skipped; then, for s = 1 .. e - 1, the segments whose
     pair s - 1 was skipped detect frame s again and have their pairs from s on tracked again (both
-    gated on the device by that pair's valid count). ``chain=False`` makes one vs_track_lk call per
+    gated on the device by that pair's valid count). ``per_pair=True`` makes one vs_track_lk call per
     pair instead, each followed by the gated re-detection. Both give the same records. work: int64
     [1, segments, 3] (segment calls) or [e, segments, 2] (per-pair calls) counters of the first call;
     lk_events: (start, end) timing events around every tracking launch are appended."""
@@ -112,9 +112,7 @@ def track_segments(o, f0: int, p0: int, fs: int, ps: int, pairs_of, P: StabParam
                             xy + t * rec2, o.score.data_ptr() + t * cap * 8, o.count.data_ptr() + t * 4,
                             al + t * rec1, o.det_ws, o.det_ws_bytes)
 
-    if chain is None:
-        chain = True
-    if chain:
+    if not per_pair:
         n_seg = pairs_of(0)
         if n_seg <= 0:
             return
@@ -138,13 +136,13 @@ def track_segments(o, f0: int, p0: int, fs: int, ps: int, pairs_of, P: StabParam
         n_s = pairs_of(s)
         if n_s <= 0:
             break
-        chain = s < e - 1
+        chained = s < e - 1
         timed_launch(lambda: V.vs_track_lk(
             f0 + s * fs, p0 + s * ps, f0 + (s + 1) * fs, p0 + (s + 1) * ps, e * fs, e * ps, n_s, e, layout,
             xy + s * rec2, al + s * rec1, cap, lkp, dst + s * rec2, st + s * rec1, fbe + s * rec4, nv + s * 4,
-            xy + (s + 1) * rec2 if chain else None, al + (s + 1) * rec1 if chain else None,
+            xy + (s + 1) * rec2 if chained else None, al + (s + 1) * rec1 if chained else None,
             work[s] if work is not None else None))
-        n_next = pairs_of(s + 1) if chain else 0
+        n_next = pairs_of(s + 1) if chained else 0
         if n_next > 0:
             redetect(s + 1, n_next)
 

@@ -25,7 +25,7 @@ from paper_1701_03572_amd.pipeline import _detect_params, _lk_params, track_segm
 pytestmark = pytest.mark.gpu
 
 
-def run_tracking(frames_np, P, chain):
+def run_tracking(frames_np, P, per_pair):
     n, h, w = frames_np.shape
     e, cap = P.redetect_every, P.max_corners
     n_pairs = n - 1
@@ -48,10 +48,10 @@ def run_tracking(frames_np, P, chain):
     dp = _detect_params(P, w, h)
     V.vs_detect_corners(frames, e * h * w, w, h, w, n_seg, e, None, 0, dp, cap, o.src, o.score, o.count, o.asrc,
                         o.det_ws, o.det_ws_bytes)
-    work = torch.zeros((1, n_seg, 3) if chain else (e, n_seg, 2), dtype=torch.int64, device="cuda")
+    work = torch.zeros((e, n_seg, 2) if per_pair else (1, n_seg, 3), dtype=torch.int64, device="cuda")
     track_segments(o, frames.data_ptr(), pyr.data_ptr(), h * w, L.bytes,
                    lambda s: (n_pairs - 1 - s) // e + 1 if 0 <= s <= n_pairs - 1 else 0, P, L, _lk_params(P), dp, w, h,
-                   work, chain=chain)
+                   work, per_pair=per_pair)
     torch.cuda.synchronize()
     rec = {k: getattr(o, k)[:n_pairs].cpu().numpy() for k in ("src", "asrc", "dst", "status", "fb_err", "n_valid")}
     return rec, work.cpu().numpy()
@@ -75,8 +75,8 @@ def test_segments_equal_per_pair_calls(name, n, blanks, fb):
     for b in blanks:
         frames[b] = 90                   # a blank frame: the pair into it is skipped, it is re-detected
     P = dataclasses.replace(params.PRESETS[name], fb=fb)
-    ref, w_ref = run_tracking(frames, P, chain=False)
-    got, w_got = run_tracking(frames, P, chain=True)
+    ref, w_ref = run_tracking(frames, P, per_pair=True)
+    got, w_got = run_tracking(frames, P, per_pair=False)
     check_equal(ref, got)
     skipped = ref["n_valid"] < P.min_valid
     say("pairs", n - 1, "skipped", np.nonzero(skipped)[0].tolist(), "valid", ref["n_valid"].tolist())
@@ -106,8 +106,8 @@ def test_segments_equal_per_pair_calls_other_windows(win_half):
     frames = sq.frames.copy()
     frames[7] = 90
     P = dataclasses.replace(params.PRESETS["tiny"], win_half=win_half)
-    ref, w_ref = run_tracking(frames, P, chain=False)
-    got, w_got = run_tracking(frames, P, chain=True)
+    ref, w_ref = run_tracking(frames, P, per_pair=True)
+    got, w_got = run_tracking(frames, P, per_pair=False)
     check_equal(ref, got)
     assert (ref["n_valid"] < P.min_valid).any() and (ref["n_valid"] >= P.min_valid).any()
 
