@@ -780,9 +780,10 @@ __global__ __launch_bounds__(256) void lk_kernel16(A io, vs::LevelDesc d, int ca
 // F(i, s) = frames + i * frame_stride + s * frame_step and the point records of its pair s at record
 // i * istride + s. One wave carries one point slot of one item through the item's pairs: the forward
 // track of the first pair, then for every later frame one window set-up that serves both the
-// backward track of the pair ending there and the forward track of the pair starting there. Each
-// frame of the chain is read by the wave's windows around one point position, so its blocks are
-// fetched once and found in the caches by the tracks that follow.
+// backward track of the pair ending there and the forward track of the pair starting there (a
+// segment of 5 pairs forms 6 set-ups per point and level instead of 10). A pair skipped for too few
+// valid points is only known once all of its points are done, so the call assumes none is; a gated
+// call from the pair after a skipped one tracks the rest of that item again.
 struct SegIO {
     const uint8_t *frames, *pyrs;
     int64_t frame_stride, pyr_stride, frame_step, pyr_step;
