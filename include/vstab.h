@@ -168,7 +168,11 @@ int vs_track_lk(const uint8_t* prev_frames, const uint8_t* prev_pyrs, const uint
  * direction, as separate tracks would form them) and Gauss-Newton iterations of the tracks kept, and
  * the window set-ups formed (a shared one once). Forward tracks made for points that then fail the
  * check of the pair before are not counted.
- * Launches are enqueued on `stream`; nothing is allocated and the host is not synchronised. */
+ * Errors: VS_ERR_INVALID for a null layout, parameters, frame, pyramid (more than one level) or
+ * point array, a negative count, istride < 1, pairs > istride, last_pairs > pairs or first < 0;
+ * otherwise those of vs_track_lk. n = 0, capacity = 0 or first >= pairs enqueue nothing.
+ * Device buffers are the caller's; launches are enqueued on `stream`; nothing is allocated and the
+ * host is not synchronised. */
 int vs_track_lk_segments(const uint8_t* frames, const uint8_t* pyrs, int64_t frame_stride, int64_t pyr_stride,
                          int64_t frame_step, int64_t pyr_step, int32_t n, int32_t istride, int32_t pairs,
                          int32_t last_pairs, int32_t first, const vs_pyramid* layout, int32_t capacity,
