@@ -9,8 +9,9 @@
 // Arithmetic is binary64 throughout: vector FP64 issues at the rate of unpacked FP32 on this
 // hardware, and every pass is small next to the tracker.
 //
-// photo_sums_kernel: a 256-thread workgroup covers a 256 x 32 tile of Omega (4 x 8 pixels per thread)
-// and accumulates the loss, the gradient, J^T J (upper triangle) and J^T r; the per-thread sums are
+// photo_sums_kernel: a 256-thread workgroup covers a 256 x 32 tile of Omega (4 x 8 pixels per thread),
+// reads its taps from LDS copies of the tile and of the tile's source box in the next frame, and
+// accumulates the loss, the gradient, J^T J (upper triangle) and J^T r; the per-thread sums are
 // reduced over the workgroup in a fixed order and stored as the tile's 19 partial sums in the
 // workspace. photo_reduce_kernel: one workgroup per pair adds its tiles' partials, again in a fixed
 // order (tile t goes to thread t mod 256, the threads' totals through a wave butterfly and the four
@@ -71,6 +72,72 @@ __device__ __forceinline__ double sample(const Frame& f, double x, double y)
     return fma(b, bot - top, top);
 }
 
+// Staged source boxes: a tile's pixels map (affinely) into a box of the next frame, which is staged in
+// LDS with 16-byte loads, rows and columns clamped to the frame (the sampler's edge replication), and
+// so is the tile of the previous frame; every tap is then an LDS byte read. Boxes larger than the
+// buffer take the direct path (per-tap global loads).
+constexpr int SLP = 288;                 // LDS row pitch of the staged blocks (18 chunks of 16 bytes)
+constexpr int SNCH = SLP / 16;
+constexpr int SMAXR = 80;                // staged next-frame rows at most
+constexpr double SBIG = 1048576.0;       // boxes beyond +-2^20 take the direct path
+constexpr uint32_t RSRC_WORD3 = 0x00020000;   // raw (untyped) buffer access on gfx9-family parts
+
+// the position in the next frame of pixel (x, y), dx = (x - cx) / rho and dy = (y - cy) / rho
+__device__ __forceinline__ void map_px(int x, double dx, int y, double dy, double t0, double t1, double t2, double t3,
+                                       double& px_, double& py_)
+{
+    px_ = (double)x + t0 * dx - t1 * dy + t2;
+    py_ = (double)y + t1 * dx + t0 * dy + t3;
+}
+
+// adds one pixel's residual (and with need_grad its Jacobian row's products) to the thread's sums
+__device__ __forceinline__ void accumulate(double res, double gx, double gy, double dx, double dy, int need_grad,
+                                           double (&s)[NACC])
+{
+    s[0] = fma(res, res, s[0]);
+    if (need_grad) {
+        const double J[4] = {gx * dx + gy * dy, gy * dx - gx * dy, gx, gy};
+        int t = 5;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            s[1 + i] = fma(2.0 * res, J[i], s[1 + i]);
+            s[15 + i] = fma(J[i], res, s[15 + i]);
+#pragma unroll
+            for (int j = i; j < 4; ++j) {
+                s[t] = fma(J[i], J[j], s[t]);
+                ++t;
+            }
+        }
+    }
+}
+
+// Stages rows r0 .. r0 + nr - 1 (each clamped to the frame) and the 16-byte chunks starting at column
+// c0 (c0 a multiple of 16; columns clamped to the frame) of F into buf (row r at r * SLP).
+__device__ __forceinline__ void stage_block(const Frame& F, bool vec_ok, int r0, int nr, int c0, int nch, uint8_t* buf)
+{
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(F.p), (short)0,
+                                                                        F.pitch * F.h, RSRC_WORD3);
+    using V4 = __attribute__((ext_vector_type(4))) unsigned int;
+    for (int k = threadIdx.x; k < nr * nch; k += blockDim.x) {
+        const int r = k / nch, c = k - r * nch;
+        const int gy = vs::clampi(r0 + r, 0, F.h - 1);
+        const int gx = c0 + 16 * c;
+        V4 v;
+        if (vec_ok && gx >= 0 && gx + 16 <= F.w) {
+            v = __builtin_bit_cast(V4, __builtin_amdgcn_raw_buffer_load_b128(rs, gy * F.pitch + gx, 0, 0));
+        } else {
+            uint32_t wd[4] = {0u, 0u, 0u, 0u};
+            for (int e = 0; e < 16; ++e) {
+                const uint32_t byte = __builtin_amdgcn_raw_buffer_load_b8(rs, gy * F.pitch + vs::clampi(gx + e, 0, F.w - 1),
+                                                                         0, 0);
+                wd[e >> 2] |= byte << (8 * (e & 3));
+            }
+            v = V4{wd[0], wd[1], wd[2], wd[3]};
+        }
+        *reinterpret_cast<V4*>(&buf[r * SLP + 16 * c]) = v;
+    }
+}
+
 // Which parameters: theta_src[item * tstride] when state == nullptr, else the state's candidate
 // (pairs already stopped are skipped). The tile's sums go to part[(item * tiles + tile) * NACC + k]
 // for k < 1 (loss only) or k < NACC.
@@ -81,6 +148,8 @@ __global__ __launch_bounds__(256) void photo_sums_kernel(const uint8_t* __restri
                                                          double* __restrict__ part, int tiles_x, int tiles_y)
 {
     __shared__ double red[4][NACC];
+    __shared__ __attribute__((aligned(16))) uint8_t box1[SMAXR * SLP];   // the next frame's source box
+    __shared__ __attribute__((aligned(16))) uint8_t box0[TH * SLP];      // the previous frame's tile
     const int tiles = tiles_x * tiles_y;
     const int item = blockIdx.x / tiles, tile = blockIdx.x - item * tiles;
     const double* th;
@@ -99,33 +168,83 @@ __global__ __launch_bounds__(256) void photo_sums_kernel(const uint8_t* __restri
     double s[NACC];
 #pragma unroll
     for (int k = 0; k < NACC; ++k) s[k] = 0.0;
-    for (int r = 0; r < RPT; ++r) {
-        const int y = yb + r;
-        if (y >= oy1) break;
-        const double dy = ((double)y - cy) / rho;
-        for (int q = 0; q < 4; ++q) {
-            const int x = xb + q;
-            if (x >= ox1) break;
-            const double dx = ((double)x - cx) / rho;
-            const double px_ = (double)x + t0 * dx - t1 * dy + t2;
-            const double py_ = (double)y + t1 * dx + t0 * dy + t3;
-            double v, gx, gy;
-            sample_grad(F1, px_, py_, v, gx, gy);
-            const double res = v - (double)F0.p[(int64_t)y * pitch + x];
-            s[0] = fma(res, res, s[0]);
-            if (need_grad) {
-                const double J[4] = {gx * dx + gy * dy, gy * dx - gx * dy, gx, gy};
-                int t = 5;
+
+    // the tile's pixels [X0, X1) x [Y0, Y1); their positions are monotone in x and in y (every operation
+    // rounds monotonically), so the box of the four corners, widened by one pixel, holds every tap
+    const int X0 = ox0 + tx * TW, X1 = min(X0 + TW, ox1), Y0 = oy0 + ty * TH, Y1 = min(Y0 + TH, oy1);
+    double mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
+    bool finite = true;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    s[1 + i] = fma(2.0 * res, J[i], s[1 + i]);
-                    s[15 + i] = fma(J[i], res, s[15 + i]);
+    for (int cyi = 0; cyi < 2; ++cyi)
 #pragma unroll
-                    for (int j = i; j < 4; ++j) {
-                        s[t] = fma(J[i], J[j], s[t]);
-                        ++t;
-                    }
-                }
+        for (int cxi = 0; cxi < 2; ++cxi) {
+            const int x = cxi ? X1 - 1 : X0, y = cyi ? Y1 - 1 : Y0;
+            double qx, qy;
+            map_px(x, ((double)x - cx) / rho, y, ((double)y - cy) / rho, t0, t1, t2, t3, qx, qy);
+            mnx = fmin(mnx, qx);
+            mxx = fmax(mxx, qx);
+            mny = fmin(mny, qy);
+            mxy = fmax(mxy, qy);
+            finite = finite && qx > -SBIG && qx < SBIG && qy > -SBIG && qy < SBIG;   // false for NaN
+        }
+    int a0 = 0, by0 = 0, nr = 0;
+    // a map far from degenerate (|t0|, |t1| < rho / 2): each position moves by at least half a pixel
+    // per pixel along its own axis, so the corners bound the tile
+    bool staged = finite && fabs(t0) < 0.5 * rho && fabs(t1) < 0.5 * rho;
+    if (staged) {
+        a0 = ((int)floor(mnx) - 1) & ~15;
+        by0 = (int)floor(mny) - 1;
+        nr = (int)floor(mxy) + 2 - by0 + 1;
+        staged = (int)floor(mxx) + 2 - a0 < SLP && nr <= SMAXR;
+    }
+    if (staged) {
+        const int c00 = X0 & ~15;
+        stage_block(F1, ((reinterpret_cast<uintptr_t>(F1.p) | (uintptr_t)pitch) & 15) == 0, by0, nr, a0, SNCH, box1);
+        stage_block(F0, ((reinterpret_cast<uintptr_t>(F0.p) | (uintptr_t)pitch) & 15) == 0, Y0, Y1 - Y0, c00,
+                    min(SNCH, (X1 - c00 + 15) / 16), box0);
+        __syncthreads();
+        double dxq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dxq[q] = ((double)(xb + q) - cx) / rho;
+        for (int r = 0; r < RPT; ++r) {
+            const int y = yb + r;
+            if (y >= oy1) break;
+            const double dy = ((double)y - cy) / rho;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int x = xb + q;
+                if (x >= ox1) break;
+                const double dx = dxq[q];
+                double px_, py_;
+                map_px(x, dx, y, dy, t0, t1, t2, t3, px_, py_);
+                // the sampler of sample_grad, its taps read from the staged box
+                const double fx = floor(px_), fy = floor(py_);
+                const double a = px_ - fx, b = py_ - fy;
+                const int o = ((int)fy - by0) * SLP + ((int)fx - a0);
+                const double p00 = box1[o], p10 = box1[o + 1], p01 = box1[o + SLP], p11 = box1[o + SLP + 1];
+                const double top = fma(a, p10 - p00, p00), bot = fma(a, p11 - p01, p01);
+                const double v = fma(b, bot - top, top);
+                const double gx = fma(b, (p11 - p01) - (p10 - p00), p10 - p00);
+                const double gy = fma(a, (p11 - p10) - (p01 - p00), p01 - p00);
+                const double res = v - (double)box0[(y - Y0) * SLP + (x - c00)];
+                accumulate(res, gx, gy, dx, dy, need_grad, s);
+            }
+        }
+    } else {
+        for (int r = 0; r < RPT; ++r) {
+            const int y = yb + r;
+            if (y >= oy1) break;
+            const double dy = ((double)y - cy) / rho;
+            for (int q = 0; q < 4; ++q) {
+                const int x = xb + q;
+                if (x >= ox1) break;
+                const double dx = ((double)x - cx) / rho;
+                double px_, py_;
+                map_px(x, dx, y, dy, t0, t1, t2, t3, px_, py_);
+                double v, gx, gy;
+                sample_grad(F1, px_, py_, v, gx, gy);
+                const double res = v - (double)F0.p[(int64_t)y * pitch + x];
+                accumulate(res, gx, gy, dx, dy, need_grad, s);
             }
         }
     }

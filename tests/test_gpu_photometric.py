@@ -77,6 +77,49 @@ def test_sums_match_oracle(w, h, n):
     np.testing.assert_allclose(s["loss"].cpu().numpy(), raw[:, 0], rtol=1e-12)
 
 
+@pytest.mark.parametrize("pad", [0, 7])
+def test_sums_for_every_source_box(pad):
+    """The sums kernel stages a tile's source box in LDS when the box is small and the map far from
+    degenerate, and reads the next frame directly otherwise; the row pitch decides between 16-byte and
+    byte staging loads (pad 7: an odd pitch). Over the whole frame as Omega (taps beyond the edges
+    take the sampler's edge replication), cases for each: translation only, zoom out, zoom in past the
+    staged width (ragged last tiles still staged), rotation past the staged height, and maps beyond
+    the near-identity guard. Every case within the oracle's 1e-8 and bit-reproducible."""
+    w, h = 320, 240
+    rho = max(w, h) / 2
+    th = np.array([[0.0, 0.0, 25.0, -18.0],          # staged; taps clamp at the right and top edges
+                   [-0.45 * rho, 0.03 * rho, 3.0, 2.0],   # zoom out: staged
+                   [0.3 * rho, 0.0, -4.0, 1.0],      # zoom in: full tiles too wide, the last ones staged
+                   [0.02 * rho, 0.2 * rho, 1.0, -2.0],    # rotation: full tiles too tall
+                   [-0.6 * rho, 0.1 * rho, 0.0, 0.0],     # |a| past rho / 2: direct
+                   [0.1 * rho, -0.7 * rho, 5.0, 5.0]])    # |b| past rho / 2: direct
+    n = len(th)
+    f0 = np.stack([synth.smooth_random_image(w, h, 700 + i, sigma=1.8) for i in range(n)])
+    f1 = np.stack([synth.smooth_random_image(w, h, 800 + i, sigma=2.5) for i in range(n)])
+    pitch = w + pad
+    say("photometric source boxes, pitch", pitch)
+
+    def pitched(f):
+        buf = np.full((n, h, pitch), 255, np.uint8)       # the padding is never read
+        buf[:, :, :w] = f
+        return dev(buf)
+
+    g0, g1, theta = pitched(f0), pitched(f1), dev(th)
+    om = V.vs_rect(0, 0, w, h)
+    cx, cy, rho_ = PH.frame_geometry(w, h)
+    wsb = V.vs_photometric_workspace(n, w, h)
+    ws = torch.empty((wsb,), dtype=torch.uint8, device="cuda")
+    raw = torch.empty((n, V.VS_PHOTO_SUMS), dtype=torch.float64, device="cuda")
+    again = torch.empty_like(raw)
+    V.vs_photometric_bwd(g0, g1, h * pitch, w, h, pitch, n, theta, 4, cx, cy, rho_, om, raw, ws, wsb)
+    V.vs_photometric_bwd(g0, g1, h * pitch, w, h, pitch, n, theta, 4, cx, cy, rho_, om, again, ws, wsb)
+    torch.cuda.synchronize()
+    raw = raw.cpu().numpy()
+    assert np.array_equal(again.cpu().numpy().view(np.uint64), raw.view(np.uint64))
+    for i in range(n):
+        check_sums(raw[i], O.photo_global(f0[i], f1[i], th[i], (0, 0, w, h)))
+
+
 def test_autograd_matches_finite_differences():
     w, h, n = 256, 192, 2
     f0, f1, th = pair_batch(w, h, n, seed=5)
