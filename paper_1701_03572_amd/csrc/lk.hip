@@ -87,11 +87,13 @@ __device__ __forceinline__ float wave_uniform(float x)
 // for a condition every lane evaluates identically: a scalar branch condition
 __device__ __forceinline__ bool uniform(bool c) { return __ballot(c) != 0; }
 
-// Per-wave LDS scratch of the window sums: the lanes' values stored transposed (value j of lane l at
-// j * RED_STRIDE + l; the odd stride puts the lanes of every later read on distinct banks), then 64
-// chunk sums and 16 totals.
+// Per-wave LDS scratch of the window sums: 64 chunk sums and 16 totals first (within reach of the
+// LDS instructions' immediate offsets from the area's base), then the lanes' values stored
+// transposed (value j of lane l at RED_T + j * RED_STRIDE + l; the odd stride puts the lanes of
+// every later read on distinct banks).
 constexpr int RED_STRIDE = 65;
-constexpr int RED_FLOATS = 16 * RED_STRIDE + 64 + 16;
+constexpr int RED_T = 64 + 16;
+constexpr int RED_FLOATS = RED_T + 16 * RED_STRIDE;
 // The same per-wave area first holds staged image blocks: STAGE_ROWS rows of 32 bytes (the window's
 // rows, 4-byte aligned at the left), written by one 16-byte load per lane pair. A zeroed area after
 // it serves the lanes outside the window, whose reads must return 0.
@@ -114,14 +116,14 @@ __device__ __forceinline__ void wave_sums(const float (&v)[N], float (&tot)[M], 
     constexpr int C = 64 / N;   // chunks
     const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int j = 0; j < M; ++j) red[j * RED_STRIDE + lane] = v[j];
+    for (int j = 0; j < M; ++j) red[RED_T + j * RED_STRIDE + lane] = v[j];
     wave_lds_sync();
     const int vj = lane % N, ch = lane / N;
-    const float* col = red + vj * RED_STRIDE + ch * N;
+    const float* col = red + RED_T + vj * RED_STRIDE + ch * N;
     float s = col[0];
 #pragma unroll
     for (int i = 1; i < N; ++i) s += col[i];
-    float* part = red + 16 * RED_STRIDE;
+    float* part = red;
     part[vj * C + ch] = s;
     wave_lds_sync();
     float* T = part + 64;
