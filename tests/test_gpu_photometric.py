@@ -157,6 +157,43 @@ def test_feature_loss_matches_oracle():
         np.testing.assert_allclose(grad.cpu().numpy(), rg, rtol=1e-9, atol=1e-6 * (np.abs(rg).max() + 1))
 
 
+@pytest.mark.parametrize("w,h,pad", [(320, 240, 0), (97, 61, 5), (13, 9, 0)])
+def test_feature_loss_every_window_block(w, h, pad):
+    """Per-point window loss and its displacement gradient with windows inside, across and wholly
+    outside the frame (edge replication), centres far outside it, a displacement whose sum with the
+    centre rounds at a power of two, the largest half-width (31), an odd row pitch and a frame
+    narrower than 16 bytes: against the oracle's 1e-9, and bit-reproducible."""
+    f0 = synth.smooth_random_image(w, h, 900 + w, sigma=1.6)
+    f1 = synth.smooth_random_image(w, h, 901 + w, sigma=1.6)
+    rng = np.random.default_rng(w)
+    m = 40
+    u = np.column_stack([rng.uniform(-8, w + 8, m), rng.uniform(-8, h + 8, m)])
+    u[:6] = [[-40.25, 3.5], [w + 40.5, h + 39.75], [0.0, 0.0], [w - 1.0, h - 1.0], [2.0e6, 5.5], [7.5, -1.5e6]]
+    u = u.astype(np.float32)
+    d = rng.normal(0, 2.0, (m, 2)).astype(np.float32)
+    d[6] = [1023.999, -0.001]
+    pitch = w + pad
+    say("feature windows", w, h, "pitch", pitch)
+
+    def pitched(f):
+        buf = np.full((h, pitch), 255, np.uint8)       # the padding is never read
+        buf[:, :w] = f
+        return dev(buf)
+
+    g0, g1, du, dd = pitched(f0), pitched(f1), dev(u), dev(d)
+    for hw in (31, 10, 1):
+        loss = torch.empty(m, dtype=torch.float64, device="cuda")
+        grad = torch.empty((m, 2), dtype=torch.float64, device="cuda")
+        again = torch.empty_like(grad)
+        V.vs_photometric_features(g0, g1, h * pitch, w, h, pitch, 1, du, dd, m, hw, loss, grad)
+        V.vs_photometric_features(g0, g1, h * pitch, w, h, pitch, 1, du, dd, m, hw, torch.empty_like(loss), again)
+        torch.cuda.synchronize()
+        assert np.array_equal(again.cpu().numpy().view(np.uint64), grad.cpu().numpy().view(np.uint64))
+        rl, rg = O.photo_feature(f0, f1, u.astype(np.float64), d.astype(np.float64), win_half=hw)
+        np.testing.assert_allclose(loss.cpu().numpy(), rl, rtol=1e-9, atol=1e-6)
+        np.testing.assert_allclose(grad.cpu().numpy(), rg, rtol=1e-9, atol=1e-6 * (np.abs(rg).max() + 1))
+
+
 def test_refine_matches_oracle_and_lowers_the_loss():
     w, h, n = 320, 240, 4
     f0, f1, th0 = pair_batch(w, h, n, seed=11)
