@@ -78,7 +78,7 @@ __device__ __forceinline__ double sample(const Frame& f, double x, double y)
 // buffer take the direct path (per-tap global loads).
 constexpr int SLP = 288;                 // LDS row pitch of the staged blocks (18 chunks of 16 bytes)
 constexpr int SNCH = SLP / 16;
-constexpr int SMAXR = 80;                // staged next-frame rows at most
+constexpr int SMAXR = 79;                // staged next-frame rows at most (the LDS of 5 workgroups per CU)
 constexpr double SBIG = 1048576.0;       // boxes beyond +-2^20 take the direct path
 constexpr uint32_t RSRC_WORD3 = 0x00020000;   // raw (untyped) buffer access on gfx9-family parts
 
@@ -90,7 +90,10 @@ __device__ __forceinline__ void map_px(int x, double dx, int y, double dy, doubl
     py_ = (double)y + t1 * dx + t0 * dy + t3;
 }
 
-// adds one pixel's residual (and with need_grad its Jacobian row's products) to the thread's sums
+// Adds one pixel's residual (and with need_grad its Jacobian row's products) to the thread's sums.
+// The gradient slots 1..4 are left alone: the gradient's sum is 2 J^T r exactly (doubling is exact,
+// so fma(2 r, J, 2 s) = 2 fma(r, J, s) at every step, and so for every sum of such terms in a fixed
+// order), and the tile's gradient is written as twice its J^T r.
 __device__ __forceinline__ void accumulate(double res, double gx, double gy, double dx, double dy, int need_grad,
                                            double (&s)[NACC])
 {
@@ -100,7 +103,6 @@ __device__ __forceinline__ void accumulate(double res, double gx, double gy, dou
         int t = 5;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            s[1 + i] = fma(2.0 * res, J[i], s[1 + i]);
             s[15 + i] = fma(J[i], res, s[15 + i]);
 #pragma unroll
             for (int j = i; j < 4; ++j) {
@@ -252,15 +254,16 @@ __global__ __launch_bounds__(256) void photo_sums_kernel(const uint8_t* __restri
     const int nk = need_grad ? NACC : 1;
 #pragma unroll
     for (int k = 0; k < NACC; ++k) {
-        if (k < nk) {
+        if (k < nk && (k < 1 || k > 4)) {
             const double t = vs::wave_sum_d(s[k]);
             if (lane == 0) red[wv][k] = t;
         }
     }
     __syncthreads();
     if ((int)threadIdx.x < nk) {
-        const int k = threadIdx.x;
-        out[k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+        const int k = threadIdx.x, j = k >= 1 && k <= 4 ? k + 14 : k;
+        const double t = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
+        out[k] = j != k ? 2.0 * t : t;
     }
 }
 

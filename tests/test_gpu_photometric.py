@@ -90,7 +90,7 @@ def test_sums_for_every_source_box(pad):
     th = np.array([[0.0, 0.0, 25.0, -18.0],          # staged; taps clamp at the right and top edges
                    [-0.45 * rho, 0.03 * rho, 3.0, 2.0],   # zoom out: staged
                    [0.3 * rho, 0.0, -4.0, 1.0],      # zoom in: full tiles too wide, the last ones staged
-                   [0.02 * rho, 0.2 * rho, 1.0, -2.0],    # rotation: full tiles too tall
+                   [0.02 * rho, 0.2 * rho, 1.0, -2.0],    # rotation: full tiles too tall (more than 79 rows)
                    [-0.6 * rho, 0.1 * rho, 0.0, 0.0],     # |a| past rho / 2: direct
                    [0.1 * rho, -0.7 * rho, 5.0, 5.0]])    # |b| past rho / 2: direct
     n = len(th)
