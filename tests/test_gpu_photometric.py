@@ -69,6 +69,7 @@ def test_sums_match_oracle(w, h, n):
     torch.cuda.synchronize()
     raw, fwd = raw.cpu().numpy(), fwd.cpu().numpy()
     assert np.array_equal(again.cpu().numpy().view(np.uint64), raw.view(np.uint64))   # bit-reproducible
+    np.testing.assert_array_equal(raw[:, 1:5], 2.0 * raw[:, 15:19])   # the gradient is 2 J^T r exactly
     for i in range(n):
         ref = O.photo_global(f0[i], f1[i], th[i], rect_tuple(om))
         check_sums(raw[i], ref)
