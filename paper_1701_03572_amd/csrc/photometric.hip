@@ -11,9 +11,9 @@
 //
 // photo_sums_kernel: a 256-thread workgroup covers a 256 x 32 tile of Omega (4 x 8 pixels per thread),
 // reads its taps from LDS copies of the tile and of the tile's source box in the next frame, and
-// accumulates the loss, the gradient, J^T J (upper triangle) and J^T r; the per-thread sums are
-// reduced over the workgroup in a fixed order and stored as the tile's 19 partial sums in the
-// workspace. photo_reduce_kernel: one workgroup per pair adds its tiles' partials, again in a fixed
+// accumulates the loss, J^T J (upper triangle) and J^T r; the per-thread sums are reduced over the
+// workgroup in a fixed order and stored as the tile's 19 partial sums in the workspace (the gradient
+// as twice the J^T r sums, which it equals exactly). photo_reduce_kernel: one workgroup per pair adds its tiles' partials, again in a fixed
 // order (tile t goes to thread t mod 256, the threads' totals through a wave butterfly and the four
 // wave totals in sequence), so every sum is reproducible bit for bit from run to run.
 // photo_feature_kernel: one wave per point; the window's samples are spread over the lanes.
