@@ -1,8 +1,10 @@
 // warp_frame: inverse-mapped bilinear warp of 8-bit frames, all items of a batch in one launch.
 //
-// A 256-thread workgroup covers a 256 x 64 output tile; each thread produces 4 consecutive pixels in
-// each of 16 rows (tall tiles spread the per-tile matrix inversion, source box and staging over more
-// pixels), stored as one 32-bit word per row when the row allows it. The 2x3 matrix is
+// A 256-thread workgroup covers a 256 x 64 output tile (tall tiles spread the per-tile matrix
+// inversion, source box and staging over more pixels). Wave w takes the tile's columns
+// 64 w .. 64 w + 63; its lanes cover 64 columns x 4 rows at a time (4 consecutive pixels per lane,
+// 16 lanes per row), and each thread produces its 4 pixels in 16 rows 4 apart, stored as one 32-bit
+// word per row when the row allows it. The 2x3 matrix is
 // inverted in binary64; per-pixel source coordinates are FP32, relative to the tile's source box.
 //
 // Source box: the map is affine and is evaluated in a form that is monotone in x and in y, so the
@@ -10,18 +12,19 @@
 // one-pixel margin) is staged in LDS with 16-byte loads; bytes outside the frame are staged as the
 // border value, which gives every tap exactly the border semantics of a per-tap test. Each pixel then
 // reads its four taps as single bytes from LDS (a fixed row pitch makes the lower taps immediate
-// offsets). Tiles whose box does not fit the LDS buffer (strong zoom-out or rotation) take a
+// offsets; at 80 words it puts the four rows one instruction reads on distinct banks). Tiles whose box does not fit the LDS buffer (strong zoom-out or rotation) take a
 // per-pixel path that reads the frame directly.
 // Values are rounded half up: floor(v + 0.5) is an integer in [0, 255], packed exactly.
 #include "vs_common.hpp"
 
 namespace {
 
-constexpr int TW = 256;                 // tile width: 64 lanes x 4 pixels
+constexpr int TW = 256;                 // tile width: 4 waves x 16 lanes x 4 pixels
 constexpr int RPT = 16;                 // rows per thread
-constexpr int TH = 4 * RPT;             // 4 waves stacked vertically
-constexpr int LW = 288;                 // LDS row pitch: 18 chunks of 16 bytes
-constexpr int NCH = LW / 16;
+constexpr int TH = 4 * RPT;             // 4 lane rows per wave
+constexpr int LW = 320;                 // LDS row pitch (80 words: 16 mod 32 banks)
+constexpr int BW = 288;                 // staged box width: 18 chunks of 16 bytes
+constexpr int NCH = BW / 16;
 constexpr int MAXR = 96;                // staged rows at most
 constexpr int NLD = (NCH * MAXR + 255) / 256;
 constexpr float BIG = 1048576.0f;       // boxes beyond +-2^20 take the direct path
@@ -101,8 +104,8 @@ __global__ __launch_bounds__(256, 5) void warp_kernel(IO io, int W, int H, int s
     if (!vs::xcd_map(blockIdx.x, n_items, tiles_x * tiles_y, by_xcd != 0, item, tile)) return;
     const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
     const int ox = tx * TW, oy = ty * TH;
-    const int x4 = ox + (threadIdx.x & 63) * 4;
-    const int ybase = oy + (threadIdx.x >> 6) * RPT;
+    const int x4 = ox + 64 * (int)(threadIdx.x >> 6) + 4 * (int)(threadIdx.x & 15);
+    const int ybase = oy + (int)((threadIdx.x >> 4) & 3);   // the thread's rows: ybase + 4 r
     const uint8_t* s;
     const double* M;
     uint8_t* dst;
@@ -118,7 +121,7 @@ __global__ __launch_bounds__(256, 5) void warp_kernel(IO io, int W, int H, int s
     const float f00 = (float)i00, f01 = (float)i01;
     const float f10 = (float)i10, f11 = (float)i11;
     const int nx = W - x4 < 4 ? W - x4 : 4;      // <= 0 for threads past the right edge
-    const int ny = H - ybase < RPT ? H - ybase : RPT;
+    const int ny = H - ybase <= 0 ? 0 : ((H - ybase + 3) >> 2 < RPT ? (H - ybase + 3) >> 2 : RPT);
     uint8_t* drow = dst + (int64_t)ybase * dst_pitch + x4;
     const bool word_store = nx == 4 && (reinterpret_cast<uintptr_t>(drow) & 3) == 0 && (dst_pitch & 3) == 0;
     const int xe = (ox + TW < W ? ox + TW : W) - 1, ye = (oy + TH < H ? oy + TH : H) - 1;
@@ -136,7 +139,7 @@ __global__ __launch_bounds__(256, 5) void warp_kernel(IO io, int W, int H, int s
         // the same box in the relative coordinates the pixels use: every tap must be inside the buffer
         const Box rb = corner_box(f00, f01, g02, f10, f11, g12, ox, xe, oy, ye);
         nr = (int)floorf(rb.mxy) + 2;
-        staged = rb.finite && rb.mnx >= 0.0f && rb.mny >= 0.0f && rb.mxx < (float)(LW - 1) && nr <= MAXR;
+        staged = rb.finite && rb.mnx >= 0.0f && rb.mny >= 0.0f && rb.mxx < (float)(BW - 1) && nr <= MAXR;
     }
     if (staged) {
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(s), (short)0,
@@ -184,7 +187,7 @@ __global__ __launch_bounds__(256, 5) void warp_kernel(IO io, int W, int H, int s
 #pragma unroll
         for (int q = 0; q < 4; ++q) fxq[q] = (float)(x4 + (q < nx ? q : nx - 1));   // past-the-edge columns repeat
         for (int r = 0; r < ny; ++r) {
-            const float fy = (float)(ybase + r);
+            const float fy = (float)(ybase + 4 * r);
             const float bx = fmaf(f01, fy, g02), by = fmaf(f11, fy, g12);
             uint32_t packed = 0;
 #pragma unroll
@@ -203,7 +206,7 @@ __global__ __launch_bounds__(256, 5) void warp_kernel(IO io, int W, int H, int s
                 const float v = lerp(lerp(v00, v10, a), lerp(v01, v11, a), b);
                 packed = __builtin_amdgcn_cvt_pk_u8_f32(floorf(v + 0.5f), q, packed);
             }
-            uint8_t* out = drow + (int64_t)r * dst_pitch;
+            uint8_t* out = drow + (int64_t)(4 * r) * dst_pitch;
             if (word_store) *reinterpret_cast<uint32_t*>(out) = packed;
             else
                 for (int q = 0; q < nx; ++q) out[q] = (uint8_t)(packed >> (8 * q));
@@ -216,7 +219,7 @@ __global__ __launch_bounds__(256, 5) void warp_kernel(IO io, int W, int H, int s
     const float bord = (float)border;
     const float fW = (float)W, fH = (float)H;
     for (int r = 0; r < ny; ++r) {
-        const float fy = (float)(ybase + r);
+        const float fy = (float)(ybase + 4 * r);
         const float bx = fmaf(f01, fy, f02), by = fmaf(f11, fy, f12);
         uint32_t packed = 0;
 #pragma unroll
@@ -240,7 +243,7 @@ __global__ __launch_bounds__(256, 5) void warp_kernel(IO io, int W, int H, int s
             }
             packed |= o << (8 * q);
         }
-        uint8_t* out = drow + (int64_t)r * dst_pitch;
+        uint8_t* out = drow + (int64_t)(4 * r) * dst_pitch;
         if (word_store) *reinterpret_cast<uint32_t*>(out) = packed;
         else
             for (int q = 0; q < nx; ++q) out[q] = (uint8_t)(packed >> (8 * q));
